@@ -1,0 +1,8 @@
+"""FP64 CPU oracle of the fused warp + dissimilarity path (test infrastructure).
+
+Only the tests, the smoke check and the benchmark's CPU timing leg import
+this package.  It shares no code with the library's HIP path.
+"""
+from .oracle import (  # noqa: F401
+    adam, lncc, lncc_grad_u_at, lncc_loss_mw, load, mi, parzen, resample, warp,
+)

@@ -1,0 +1,522 @@
+/*
+ * FP64 CPU oracle for the fused warp + dissimilarity path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library or its Python binding may
+ * link, load or call this file; only the tests, the smoke check and the CPU
+ * timing leg of the benchmark do.  It shares no code with the HIP path.
+ *
+ * Every routine is the plain definition written out, in double precision,
+ * with no blocking, fusion or reordering: inputs arrive as fp32 and are
+ * converted exactly to double.  Each function names the passage it follows.
+ *
+ * Conventions:
+ *   volumes  [D][H][W] C-order;  displacement u [3][D][H][W], channel 0 adds
+ *   to x (W axis), 1 to y (H), 2 to z (D)  (App. "Composite Implicit Grid
+ *   Sampler", Alg. gridsampler: X = (x,y,z), displacement u[:, z, y, x]).
+ *   roi = {z0,z1,y0,y1,x0,x1}, half-open, or NULL for the whole array.
+ *   pad: 0 = border (clamp), 1 = zeros.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef int64_t i64;
+
+#define AT(z, y, x) ((((z) * H) + (y)) * W + (x))
+
+static void roi_or_full(const i64* roi, i64 D, i64 H, i64 W, i64 r[6])
+{
+    if (roi) { memcpy(r, roi, 6 * sizeof(i64)); }
+    else { r[0] = 0; r[1] = D; r[2] = 0; r[3] = H; r[4] = 0; r[5] = W; }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O1. Trilinear sample of M at p = x + u(x)                                 */
+/* eq. (interp) of App. "Ring Sampler": the value is the sum over the eight  */
+/* lattice neighbours of M times the product of 1-D hat weights.  Border     */
+/* mode clamps p to [0, n-1] per axis and the derivative along a clamped     */
+/* axis is zero; a point exactly on the border counts as clamped.  Zero mode */
+/* treats lattice points outside the array as 0 (Alg. gridsampler).          */
+/* ------------------------------------------------------------------------ */
+static double sample_point(const float* M, i64 D, i64 H, i64 W, const double p[3] /* x,y,z */,
+                           int pad, double dvdp[3] /* x,y,z; nullable */)
+{
+    const i64 n[3] = {W, H, D};
+    double q[3];
+    int clamped[3];
+    for (int k = 0; k < 3; ++k) {
+        q[k] = p[k];
+        clamped[k] = 0;
+        if (pad == 0) {
+            if (q[k] <= 0.0) { q[k] = 0.0; clamped[k] = 1; }
+            else if (q[k] >= (double)(n[k] - 1)) { q[k] = (double)(n[k] - 1); clamped[k] = 1; }
+        }
+    }
+    i64 i0[3];
+    double a[3];
+    for (int k = 0; k < 3; ++k) { double f = floor(q[k]); i0[k] = (i64)f; a[k] = q[k] - f; }
+    double val = 0.0, g[3] = {0.0, 0.0, 0.0};
+    for (int bz = 0; bz < 2; ++bz)
+        for (int by = 0; by < 2; ++by)
+            for (int bx = 0; bx < 2; ++bx) {
+                i64 cx = i0[0] + bx, cy = i0[1] + by, cz = i0[2] + bz;
+                double m;
+                if (cx < 0 || cx >= W || cy < 0 || cy >= H || cz < 0 || cz >= D) {
+                    if (pad == 0) {  /* only reached with zero weight at the clamped edge */
+                        cx = cx < 0 ? 0 : (cx >= W ? W - 1 : cx);
+                        cy = cy < 0 ? 0 : (cy >= H ? H - 1 : cy);
+                        cz = cz < 0 ? 0 : (cz >= D ? D - 1 : cz);
+                        m = (double)M[AT(cz, cy, cx)];
+                    } else {
+                        m = 0.0;
+                    }
+                } else {
+                    m = (double)M[AT(cz, cy, cx)];
+                }
+                double wx = bx ? a[0] : 1.0 - a[0];
+                double wy = by ? a[1] : 1.0 - a[1];
+                double wz = bz ? a[2] : 1.0 - a[2];
+                val += m * wx * wy * wz;
+                g[0] += m * (bx ? 1.0 : -1.0) * wy * wz;
+                g[1] += m * (by ? 1.0 : -1.0) * wx * wz;
+                g[2] += m * (bz ? 1.0 : -1.0) * wx * wy;
+            }
+    if (dvdp)
+        for (int k = 0; k < 3; ++k) dvdp[k] = clamped[k] ? 0.0 : g[k];
+    return val;
+}
+
+/* Mw(x) = M(x + u(x)) over the whole array; dMw [3][N] = dMw/dp (x,y,z). */
+int orc_warp(const float* M, const float* u, i64 D, i64 H, i64 W, int pad, double* out, double* dout)
+{
+    const i64 N = D * H * W;
+#pragma omp parallel for schedule(static)
+    for (i64 z = 0; z < D; ++z)
+        for (i64 y = 0; y < H; ++y)
+            for (i64 x = 0; x < W; ++x) {
+                i64 k = AT(z, y, x);
+                double p[3] = {(double)x, (double)y, (double)z};
+                if (u) { p[0] += (double)u[k]; p[1] += (double)u[N + k]; p[2] += (double)u[2 * N + k]; }
+                double dv[3];
+                out[k] = sample_point(M, D, H, W, p, pad, dv);
+                if (dout) { dout[k] = dv[0]; dout[N + k] = dv[1]; dout[2 * N + k] = dv[2]; }
+            }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2. LNCC window statistics, eq. (lncc-loss) and (lncc-a/b/c):             */
+/*   mu_F, mu_M = windowed means; A, B, C = windowed (co)variances taken in  */
+/*   their centred form; W is the uniform w^3 box with weights 1/w^3, values */
+/*   outside the array are 0 (zero-padded convolution).                      */
+/* Sub-volume access: vals are given on the box [o, o+e) of the full array.  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const double* F;  /* on the sub-box */
+    const double* Mw;
+    i64 o[3];         /* z, y, x origin of the sub-box in the full array */
+    i64 e[3];         /* extents */
+    i64 D, H, W;      /* full array */
+} vol_view;
+
+static inline int in_array(const vol_view* v, i64 z, i64 y, i64 x)
+{
+    return z >= 0 && z < v->D && y >= 0 && y < v->H && x >= 0 && x < v->W;
+}
+static inline i64 vidx(const vol_view* v, i64 z, i64 y, i64 x)
+{
+    return ((z - v->o[0]) * v->e[1] + (y - v->o[1])) * v->e[2] + (x - v->o[2]);
+}
+
+static void lncc_stats(const vol_view* v, i64 z, i64 y, i64 x, int r,
+                       double* muF, double* muM, double* A, double* B, double* C)
+{
+    const double inv = 1.0 / (double)((2 * r + 1) * (2 * r + 1) * (2 * r + 1));
+    double sF = 0, sM = 0;
+    for (i64 dz = -r; dz <= r; ++dz)
+        for (i64 dy = -r; dy <= r; ++dy)
+            for (i64 dx = -r; dx <= r; ++dx) {
+                i64 zz = z + dz, yy = y + dy, xx = x + dx;
+                if (!in_array(v, zz, yy, xx)) continue;
+                i64 k = vidx(v, zz, yy, xx);
+                sF += v->F[k];
+                sM += v->Mw[k];
+            }
+    double mf = sF * inv, mm = sM * inv;
+    double a = 0, b = 0, c = 0;
+    for (i64 dz = -r; dz <= r; ++dz)
+        for (i64 dy = -r; dy <= r; ++dy)
+            for (i64 dx = -r; dx <= r; ++dx) {
+                i64 zz = z + dz, yy = y + dy, xx = x + dx;
+                double f = 0.0, m = 0.0;  /* padded voxels are 0 */
+                if (in_array(v, zz, yy, xx)) { i64 k = vidx(v, zz, yy, xx); f = v->F[k]; m = v->Mw[k]; }
+                a += (f - mf) * (m - mm);
+                b += (f - mf) * (f - mf);
+                c += (m - mm) * (m - mm);
+            }
+    *muF = mf; *muM = mm; *A = a * inv; *B = b * inv; *C = c * inv;
+}
+
+static inline int in_roi(const i64 r[6], i64 z, i64 y, i64 x)
+{
+    return z >= r[0] && z < r[1] && y >= r[2] && y < r[3] && x >= r[4] && x < r[5];
+}
+
+/* LNCC loss of (F, Mw) over the ROI: 1 - mean n_i, n_i = A^2/(B C + eps)
+ * (eq. lncc-loss; the "1 - mean" form is that of Alg. lncc). */
+double orc_lncc_loss(const float* F, const double* Mw, i64 D, i64 H, i64 W, const i64* roi, int w, double eps)
+{
+    i64 R[6];
+    roi_or_full(roi, D, H, W, R);
+    const i64 N = D * H * W;
+    double* Fd = (double*)malloc(sizeof(double) * N);
+    for (i64 k = 0; k < N; ++k) Fd[k] = (double)F[k];
+    vol_view v = {Fd, Mw, {0, 0, 0}, {D, H, W}, D, H, W};
+    const int r = (w - 1) / 2;
+    double s = 0.0;
+#pragma omp parallel for reduction(+ : s) schedule(dynamic, 1)
+    for (i64 z = R[0]; z < R[1]; ++z)
+        for (i64 y = R[2]; y < R[3]; ++y)
+            for (i64 x = R[4]; x < R[5]; ++x) {
+                double mf, mm, A, B, C;
+                lncc_stats(&v, z, y, x, r, &mf, &mm, &A, &B, &C);
+                s += A * A / (B * C + eps);
+            }
+    free(Fd);
+    const double nroi = (double)((R[1] - R[0]) * (R[3] - R[2]) * (R[5] - R[4]));
+    return 1.0 - s / nroi;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O3. Gradient of the LNCC loss with respect to Mw.                         */
+/* Chain rule of App. "Efficient Backward Pass" (eq. gradientcc-first ...     */
+/* finalccgradM) redone for the moving image with eps kept:                  */
+/*   g_i = dL/dn_i = -1/N_roi on the ROI;  D_i = B_i C_i + eps               */
+/*   dn_i/dMw_k = w_ik [ 2A_i/D_i (F_k - muF_i) - 2 A_i^2 B_i/D_i^2 (Mw_k - muM_i) ] */
+/*   dL/dMw_k   = sum_{i in ROI, k in window(i)} g_i dn_i/dMw_k              */
+/* ANTs approximation (App. "ANTs gradient approximation"): the window sum   */
+/* over i is dropped and the factors of voxel k itself are used.             */
+/* ------------------------------------------------------------------------ */
+static double lncc_dloss_dmw_at(const vol_view* v, const i64 R[6], i64 z, i64 y, i64 x, int r, double eps,
+                                int ants, double nroi)
+{
+    const double inv = 1.0 / (double)((2 * r + 1) * (2 * r + 1) * (2 * r + 1));
+    const double g = -1.0 / nroi;
+    const i64 k = vidx(v, z, y, x);
+    const double Fk = v->F[k], Mk = v->Mw[k];
+    if (ants) {
+        if (!in_roi(R, z, y, x)) return 0.0;
+        double mf, mm, A, B, C;
+        lncc_stats(v, z, y, x, r, &mf, &mm, &A, &B, &C);
+        double Dn = B * C + eps;
+        return g * (2.0 * A / Dn * (Fk - mf) - 2.0 * A * A * B / (Dn * Dn) * (Mk - mm));
+    }
+    double s = 0.0;
+    for (i64 dz = -r; dz <= r; ++dz)
+        for (i64 dy = -r; dy <= r; ++dy)
+            for (i64 dx = -r; dx <= r; ++dx) {
+                i64 zi = z + dz, yi = y + dy, xi = x + dx;
+                if (!in_roi(R, zi, yi, xi)) continue;
+                double mf, mm, A, B, C;
+                lncc_stats(v, zi, yi, xi, r, &mf, &mm, &A, &B, &C);
+                double Dn = B * C + eps;
+                s += g * inv * (2.0 * A / Dn * (Fk - mf) - 2.0 * A * A * B / (Dn * Dn) * (Mk - mm));
+            }
+    return s;
+}
+
+/* Full LNCC oracle on (F, M, u): loss and, if grad_u != NULL, dL/du over the
+ * whole array (dL/du_c = dL/dMw * dMw/dp_c, Alg. gridsampler Backward). */
+int orc_lncc(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, const i64* roi,
+             int w, double eps, int ants, int pad, double* loss, double* grad_u)
+{
+    const i64 N = D * H * W;
+    i64 R[6];
+    roi_or_full(roi, D, H, W, R);
+    double* Mw = (double*)malloc(sizeof(double) * N);
+    double* dM = grad_u ? (double*)malloc(sizeof(double) * 3 * N) : NULL;
+    orc_warp(M, u, D, H, W, pad, Mw, dM);
+    if (loss) *loss = orc_lncc_loss(F, Mw, D, H, W, R, w, eps);
+    if (grad_u) {
+        double* Fd = (double*)malloc(sizeof(double) * N);
+        for (i64 k = 0; k < N; ++k) Fd[k] = (double)F[k];
+        vol_view v = {Fd, Mw, {0, 0, 0}, {D, H, W}, D, H, W};
+        const int r = (w - 1) / 2;
+        const double nroi = (double)((R[1] - R[0]) * (R[3] - R[2]) * (R[5] - R[4]));
+        /* the per-i factors of the chain rule are tabulated once, then the
+         * sum over i in window(k) is taken for every k */
+        double* a = (double*)calloc(N, sizeof(double));
+        double* c = (double*)calloc(N, sizeof(double));
+        double* mfa = (double*)calloc(N, sizeof(double));
+        double* mmc = (double*)calloc(N, sizeof(double));
+        const double g = -1.0 / nroi;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (i64 z = R[0]; z < R[1]; ++z)
+            for (i64 y = R[2]; y < R[3]; ++y)
+                for (i64 x = R[4]; x < R[5]; ++x) {
+                    double mf, mm, A, B, C;
+                    lncc_stats(&v, z, y, x, r, &mf, &mm, &A, &B, &C);
+                    double Dn = B * C + eps;
+                    i64 i = AT(z, y, x);
+                    a[i] = 2.0 * g * A / Dn;               /* factor of (F_k - muF_i) */
+                    c[i] = 2.0 * g * A * A * B / (Dn * Dn); /* factor of (Mw_k - muM_i) */
+                    mfa[i] = mf;
+                    mmc[i] = mm;
+                }
+        const double inv = 1.0 / (double)((2 * r + 1) * (2 * r + 1) * (2 * r + 1));
+#pragma omp parallel for schedule(dynamic, 1)
+        for (i64 z = 0; z < D; ++z)
+            for (i64 y = 0; y < H; ++y)
+                for (i64 x = 0; x < W; ++x) {
+                    i64 k = AT(z, y, x);
+                    double s = 0.0;
+                    if (ants) {
+                        if (in_roi(R, z, y, x)) s = a[k] * (Fd[k] - mfa[k]) - c[k] * (Mw[k] - mmc[k]);
+                    } else {
+                        for (i64 dz = -r; dz <= r; ++dz)
+                            for (i64 dy = -r; dy <= r; ++dy)
+                                for (i64 dx = -r; dx <= r; ++dx) {
+                                    i64 zi = z + dz, yi = y + dy, xi = x + dx;
+                                    if (!in_roi(R, zi, yi, xi)) continue;
+                                    i64 i = AT(zi, yi, xi);
+                                    s += inv * (a[i] * (Fd[k] - mfa[i]) - c[i] * (Mw[k] - mmc[i]));
+                                }
+                    }
+                    grad_u[k] = s * dM[k];
+                    grad_u[N + k] = s * dM[N + k];
+                    grad_u[2 * N + k] = s * dM[2 * N + k];
+                }
+        free(a); free(c); free(mfa); free(mmc); free(Fd);
+    }
+    free(Mw);
+    if (dM) free(dM);
+    return 0;
+}
+
+/* dL/du at selected voxels only (for arrays too large for the full oracle).
+ * idx holds n triples (z, y, x); out receives n triples (d/du_x, d/du_y, d/du_z).
+ * The ROI size, which sets g_i, is that of the whole array's ROI. */
+int orc_lncc_grad_u_at(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, const i64* roi,
+                       int w, double eps, int ants, int pad, const i64* idx, i64 n, double* out)
+{
+    i64 R[6];
+    roi_or_full(roi, D, H, W, R);
+    const int r = (w - 1) / 2;
+    const i64 h = 2 * r;
+    const i64 N = D * H * W;
+    const double nroi = (double)((R[1] - R[0]) * (R[3] - R[2]) * (R[5] - R[4]));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (i64 s = 0; s < n; ++s) {
+        i64 z = idx[3 * s], y = idx[3 * s + 1], x = idx[3 * s + 2];
+        i64 e = 2 * h + 1;
+        double* Fl = (double*)malloc(sizeof(double) * e * e * e);
+        double* Ml = (double*)malloc(sizeof(double) * e * e * e);
+        vol_view v = {Fl, Ml, {z - h, y - h, x - h}, {e, e, e}, D, H, W};
+        double dv_c[3] = {0, 0, 0};
+        for (i64 zz = z - h; zz <= z + h; ++zz)
+            for (i64 yy = y - h; yy <= y + h; ++yy)
+                for (i64 xx = x - h; xx <= x + h; ++xx) {
+                    i64 l = vidx(&v, zz, yy, xx);
+                    if (!in_array(&v, zz, yy, xx)) { Fl[l] = 0.0; Ml[l] = 0.0; continue; }
+                    i64 k = AT(zz, yy, xx);
+                    double p[3] = {(double)xx, (double)yy, (double)zz};
+                    if (u) { p[0] += (double)u[k]; p[1] += (double)u[N + k]; p[2] += (double)u[2 * N + k]; }
+                    double dv[3];
+                    Fl[l] = (double)F[k];
+                    Ml[l] = sample_point(M, D, H, W, p, pad, dv);
+                    if (zz == z && yy == y && xx == x) { dv_c[0] = dv[0]; dv_c[1] = dv[1]; dv_c[2] = dv[2]; }
+                }
+        double gm = lncc_dloss_dmw_at(&v, R, z, y, x, r, eps, ants, nroi);
+        out[3 * s] = gm * dv_c[0];
+        out[3 * s + 1] = gm * dv_c[1];
+        out[3 * s + 2] = gm * dv_c[2];
+        free(Fl); free(Ml);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O4. Parzen-window mutual information, eq. (mi) and App. "Vanilla MI".      */
+/* Bin centres b_m = (m + 1/2)/B on [0,1]; kappa is the cubic B-spline in    */
+/* units of the bin width, kappa_m(v) = beta3(s - m) with s = clamp(v,0,1) B  */
+/* - 1/2.  Support falling outside [0, B-1] is folded onto the edge bin so   */
+/* that sum_m kappa_m(v) = 1 for every v.  omega = d kappa / dv.             */
+/* hard: kappa_m(v) = 1[m = min(floor(v B), B-1)] (box kernel, omega = 0).   */
+/* ------------------------------------------------------------------------ */
+static double beta3(double t)
+{
+    double a = fabs(t);
+    if (a < 1.0) return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;
+    if (a < 2.0) { double q = 2.0 - a; return q * q * q / 6.0; }
+    return 0.0;
+}
+static double dbeta3(double t)
+{
+    double a = fabs(t), sg = t < 0 ? -1.0 : 1.0;
+    if (a < 1.0) return sg * (-12.0 * a + 9.0 * a * a) / 6.0;
+    if (a < 2.0) { double q = 2.0 - a; return -sg * q * q / 2.0; }
+    return 0.0;
+}
+
+/* kappa_m(v) and omega_m(v) for every m in [0, B). */
+static void parzen_all(double v, int B, int hard, double* kap, double* om)
+{
+    for (int m = 0; m < B; ++m) { kap[m] = 0.0; om[m] = 0.0; }
+    double vc = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+    if (hard) {
+        i64 m = (i64)floor(vc * B);
+        if (m > B - 1) m = B - 1;
+        kap[m] = 1.0;
+        return;
+    }
+    const double dsdv = (v >= 0.0 && v <= 1.0) ? (double)B : 0.0;
+    const double s = vc * B - 0.5;
+    /* every integer j with |s - j| < 2 contributes to bin clamp(j, 0, B-1) */
+    for (i64 j = (i64)floor(s) - 2; j <= (i64)floor(s) + 2; ++j) {
+        double t = s - (double)j;
+        if (fabs(t) >= 2.0) continue;
+        i64 m = j < 0 ? 0 : (j > B - 1 ? B - 1 : j);
+        kap[m] += beta3(t);
+        om[m] += dbeta3(t) * dsdv;
+    }
+}
+
+/* MI of (F, Mw) over the ROI; loss = -MI.  p [B][B] (row: F bin m, column:
+ * Mw bin n) receives the joint PMF if non-NULL.  If grad_u != NULL it gets
+ * dloss/du over the whole array (zero outside the ROI):
+ *   dMI/dp[m][n] = ln p[m][n] - ln pF[m] - ln pM[n] - 1   (marginals as sums)
+ *   dp[m][n]/dMw_k = kappa_m(F_k) omega_n(Mw_k) / N_roi                     */
+int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, const i64* roi,
+           int B, int hard, int pad, double* loss, double* p_out, double* grad_u)
+{
+    const i64 N = D * H * W;
+    i64 R[6];
+    roi_or_full(roi, D, H, W, R);
+    const double nroi = (double)((R[1] - R[0]) * (R[3] - R[2]) * (R[5] - R[4]));
+    double* Mw = (double*)malloc(sizeof(double) * N);
+    double* dM = grad_u ? (double*)malloc(sizeof(double) * 3 * N) : NULL;
+    orc_warp(M, u, D, H, W, pad, Mw, dM);
+    double* p = (double*)calloc((size_t)B * B, sizeof(double));
+#pragma omp parallel
+    {
+        double* pl = (double*)calloc((size_t)B * B, sizeof(double));
+        double* kf = (double*)malloc(sizeof(double) * B);
+        double* km = (double*)malloc(sizeof(double) * B);
+        double* of = (double*)malloc(sizeof(double) * B);
+        double* om = (double*)malloc(sizeof(double) * B);
+#pragma omp for schedule(static)
+        for (i64 z = R[0]; z < R[1]; ++z)
+            for (i64 y = R[2]; y < R[3]; ++y)
+                for (i64 x = R[4]; x < R[5]; ++x) {
+                    i64 k = AT(z, y, x);
+                    parzen_all((double)F[k], B, hard, kf, of);
+                    parzen_all(Mw[k], B, hard, km, om);
+                    for (int m = 0; m < B; ++m) {
+                        if (kf[m] == 0.0) continue;
+                        for (int nn = 0; nn < B; ++nn) pl[m * B + nn] += kf[m] * km[nn];
+                    }
+                }
+#pragma omp critical
+        for (int q = 0; q < B * B; ++q) p[q] += pl[q];
+        free(pl); free(kf); free(km); free(of); free(om);
+    }
+    for (int q = 0; q < B * B; ++q) p[q] /= nroi;
+    double* pF = (double*)calloc(B, sizeof(double));
+    double* pM = (double*)calloc(B, sizeof(double));
+    for (int m = 0; m < B; ++m)
+        for (int nn = 0; nn < B; ++nn) { pF[m] += p[m * B + nn]; pM[nn] += p[m * B + nn]; }
+    double mi = 0.0;
+    for (int m = 0; m < B; ++m)
+        for (int nn = 0; nn < B; ++nn) {
+            double q = p[m * B + nn];
+            if (q > 0.0) mi += q * log(q / (pF[m] * pM[nn]));
+        }
+    if (loss) *loss = -mi;
+    if (p_out) memcpy(p_out, p, sizeof(double) * B * B);
+    if (grad_u) {
+#pragma omp parallel
+        {
+            double* kf = (double*)malloc(sizeof(double) * B);
+            double* km = (double*)malloc(sizeof(double) * B);
+            double* of = (double*)malloc(sizeof(double) * B);
+            double* om = (double*)malloc(sizeof(double) * B);
+#pragma omp for schedule(static)
+            for (i64 z = 0; z < D; ++z)
+                for (i64 y = 0; y < H; ++y)
+                    for (i64 x = 0; x < W; ++x) {
+                        i64 k = AT(z, y, x);
+                        double s = 0.0;
+                        if (in_roi(R, z, y, x)) {
+                            parzen_all((double)F[k], B, hard, kf, of);
+                            parzen_all(Mw[k], B, hard, km, om);
+                            for (int m = 0; m < B; ++m)
+                                for (int nn = 0; nn < B; ++nn) {
+                                    double wgt = kf[m] * om[nn];
+                                    if (wgt == 0.0) continue;
+                                    double dmi = log(p[m * B + nn]) - log(pF[m]) - log(pM[nn]) - 1.0;
+                                    s += -wgt / nroi * dmi;
+                                }
+                        }
+                        grad_u[k] = s * dM[k];
+                        grad_u[N + k] = s * dM[N + k];
+                        grad_u[2 * N + k] = s * dM[2 * N + k];
+                    }
+            free(kf); free(km); free(of); free(om);
+        }
+    }
+    free(p); free(pF); free(pM); free(Mw);
+    if (dM) free(dM);
+    return 0;
+}
+
+/* Parzen weights of one value (exported for the tests). */
+int orc_parzen(double v, int B, int hard, double* kap, double* om)
+{
+    parzen_all(v, B, hard, kap, om);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O5. Adam (Kingma & Ba) with bias correction, the per-voxel optimiser with */
+/* first and second moment states of the paper's registration loop.         */
+/* ------------------------------------------------------------------------ */
+int orc_adam(double* x, const double* g, double* m, double* v, i64 n, double lr, double b1, double b2,
+             double eps, i64 step)
+{
+    const double bc1 = 1.0 - pow(b1, (double)step);
+    const double bc2 = 1.0 - pow(b2, (double)step);
+    for (i64 i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        double mh = m[i] / bc1, vh = v[i] / bc2;
+        x[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trilinear resize with corner alignment (multi-scale pyramid): dst voxel j */
+/* samples src at j (n_src - 1)/(n_dst - 1) per axis; values are scaled by   */
+/* value_scale (a displacement in voxels scales with the grid).              */
+/* ------------------------------------------------------------------------ */
+int orc_resample(const float* src, i64 sD, i64 sH, i64 sW, double* dst, i64 dD, i64 dH, i64 dW, int channels,
+                 double value_scale)
+{
+    const i64 D = sD, H = sH, W = sW;
+    const double fz = dD > 1 ? (double)(sD - 1) / (double)(dD - 1) : 0.0;
+    const double fy = dH > 1 ? (double)(sH - 1) / (double)(dH - 1) : 0.0;
+    const double fx = dW > 1 ? (double)(sW - 1) / (double)(dW - 1) : 0.0;
+    for (int c = 0; c < channels; ++c) {
+        const float* s = src + (i64)c * sD * sH * sW;
+        double* d = dst + (i64)c * dD * dH * dW;
+#pragma omp parallel for schedule(static)
+        for (i64 z = 0; z < dD; ++z)
+            for (i64 y = 0; y < dH; ++y)
+                for (i64 x = 0; x < dW; ++x) {
+                    double p[3] = {x * fx, y * fy, z * fz};
+                    d[(z * dH + y) * dW + x] = value_scale * sample_point(s, D, H, W, p, 0, NULL);
+                }
+    }
+    return 0;
+}

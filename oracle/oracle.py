@@ -1,0 +1,158 @@
+"""ctypes front end of the FP64 C oracle (test infrastructure only).
+
+All arguments are numpy arrays (float32 inputs, float64 outputs) or torch CPU
+tensors, converted here; results come back as float64 numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+_f32p = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i64 = C.c_int64
+
+
+def load():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = os.path.join(_HERE, "libffdp_oracle.so")
+    if not os.path.exists(path):
+        from .build import build
+        build()
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.orc_warp.argtypes = [vp, vp, _i64, _i64, _i64, C.c_int, vp, vp]
+    lib.orc_lncc_loss.argtypes = [vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_double]
+    lib.orc_lncc_loss.restype = C.c_double
+    lib.orc_lncc.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_double, C.c_int, C.c_int, vp, vp]
+    lib.orc_lncc_grad_u_at.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_double, C.c_int, C.c_int,
+                                       vp, _i64, vp]
+    lib.orc_mi.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
+    lib.orc_parzen.argtypes = [C.c_double, C.c_int, C.c_int, vp, vp]
+    lib.orc_adam.argtypes = [vp, vp, vp, vp, _i64, C.c_double, C.c_double, C.c_double, C.c_double, _i64]
+    lib.orc_resample.argtypes = [vp, _i64, _i64, _i64, vp, _i64, _i64, _i64, C.c_int, C.c_double]
+    for f in ("orc_warp", "orc_lncc", "orc_lncc_grad_u_at", "orc_mi", "orc_parzen", "orc_adam", "orc_resample"):
+        getattr(lib, f).restype = C.c_int
+    _LIB = lib
+    return lib
+
+
+def _f32(a):
+    if a is None:
+        return None
+    if hasattr(a, "detach"):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _roi(roi):
+    if roi is None:
+        return None
+    r = np.asarray(roi, dtype=np.int64).reshape(-1)
+    assert r.size == 6
+    return np.ascontiguousarray(r)
+
+
+def warp(M, u=None, pad: int = 0, with_grad: bool = False):
+    """Mw = M(x + u) in float64 (and dMw/dp [3][D][H][W] if with_grad)."""
+    lib = load()
+    M = _f32(M)
+    u = _f32(u)
+    D, H, W = M.shape
+    out = np.empty((D, H, W), np.float64)
+    dout = np.empty((3, D, H, W), np.float64) if with_grad else None
+    lib.orc_warp(_ptr(M), _ptr(u), D, H, W, pad, _ptr(out), _ptr(dout))
+    return (out, dout) if with_grad else out
+
+
+def lncc_loss_mw(F, Mw, roi=None, window: int = 5, eps: float = 1e-5) -> float:
+    """LNCC loss of F against an already warped (float64) moving image."""
+    lib = load()
+    F = _f32(F)
+    Mw = np.ascontiguousarray(Mw, dtype=np.float64)
+    D, H, W = F.shape
+    r = _roi(roi)
+    return float(lib.orc_lncc_loss(_ptr(F), _ptr(Mw), D, H, W, _ptr(r), window, eps))
+
+
+def lncc(F, M, u=None, roi=None, window: int = 5, eps: float = 1e-5, ants: bool = False, pad: int = 0,
+         with_grad: bool = True):
+    """(loss, dloss/du [3][D][H][W] or None)."""
+    lib = load()
+    F, M, u = _f32(F), _f32(M), _f32(u)
+    D, H, W = F.shape
+    r = _roi(roi)
+    loss = np.zeros(1, np.float64)
+    g = np.empty((3, D, H, W), np.float64) if with_grad else None
+    lib.orc_lncc(_ptr(F), _ptr(M), _ptr(u), D, H, W, _ptr(r), window, eps, int(ants), pad, _ptr(loss), _ptr(g))
+    return float(loss[0]), g
+
+
+def lncc_grad_u_at(F, M, u, idx, roi=None, window: int = 5, eps: float = 1e-5, ants: bool = False, pad: int = 0):
+    """dloss/du at the voxels idx [n,3] (z,y,x) -> [n,3] (d/du_x, d/du_y, d/du_z)."""
+    lib = load()
+    F, M, u = _f32(F), _f32(M), _f32(u)
+    D, H, W = F.shape
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).reshape(-1, 3))
+    out = np.empty((idx.shape[0], 3), np.float64)
+    r = _roi(roi)
+    lib.orc_lncc_grad_u_at(_ptr(F), _ptr(M), _ptr(u), D, H, W, _ptr(r), window, eps, int(ants), pad,
+                           _ptr(idx), idx.shape[0], _ptr(out))
+    return out
+
+
+def mi(F, M, u=None, roi=None, bins: int = 32, hard: bool = False, pad: int = 0, with_grad: bool = True):
+    """(loss = -MI, joint PMF p[B][B], dloss/du or None)."""
+    lib = load()
+    F, M, u = _f32(F), _f32(M), _f32(u)
+    D, H, W = F.shape
+    r = _roi(roi)
+    loss = np.zeros(1, np.float64)
+    p = np.empty((bins, bins), np.float64)
+    g = np.empty((3, D, H, W), np.float64) if with_grad else None
+    lib.orc_mi(_ptr(F), _ptr(M), _ptr(u), D, H, W, _ptr(r), bins, int(hard), pad, _ptr(loss), _ptr(p), _ptr(g))
+    return float(loss[0]), p, g
+
+
+def parzen(v: float, bins: int, hard: bool = False):
+    lib = load()
+    k = np.empty(bins, np.float64)
+    o = np.empty(bins, np.float64)
+    lib.orc_parzen(float(v), bins, int(hard), _ptr(k), _ptr(o))
+    return k, o
+
+
+def adam(x, g, m, v, lr, b1=0.9, b2=0.999, eps=1e-8, step=1):
+    """In-place float64 Adam step on numpy float64 arrays."""
+    lib = load()
+    for a in (x, g, m, v):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    lib.orc_adam(_ptr(x), _ptr(g), _ptr(m), _ptr(v), x.size, lr, b1, b2, eps, step)
+    return x, m, v
+
+
+def resample(src, dst_shape: Sequence[int], value_scale: float = 1.0):
+    """src [C][D][H][W] or [D][H][W] float32 -> float64 of dst_shape (same channel count)."""
+    lib = load()
+    src = _f32(src)
+    squeeze = src.ndim == 3
+    if squeeze:
+        src = src[None]
+    Cn, sD, sH, sW = src.shape
+    dD, dH, dW = dst_shape
+    out = np.empty((Cn, dD, dH, dW), np.float64)
+    lib.orc_resample(_ptr(src), sD, sH, sW, _ptr(out), dD, dH, dW, Cn, value_scale)
+    return out[0] if squeeze else out
