@@ -1,0 +1,168 @@
+/*
+ * ffdp.h — C ABI of the fused warp + dissimilarity library for MI355X (gfx950).
+ *
+ * The library computes the data-parallel hot path of deformable image
+ * registration in the paper's formulation (Sec. "Composite Implicit Grid
+ * Sampler", App. "Fused LNCC", App. "Implicit MI"): the moving volume M is
+ * sampled trilinearly at the implicit identity grid plus a displacement u,
+ * never materialising a grid, and compared with the fixed volume F by local
+ * normalised cross-correlation (LNCC) or Parzen-window mutual information
+ * (MI); the hand-written adjoint returns dloss/du and a per-voxel Adam step
+ * updates u.
+ *
+ * Common conventions (every entry point):
+ *  - Volumes are float32, C-order [D][H][W] (z, y, x), contiguous.
+ *    Displacements and their gradients are [3][D][H][W]; channel 0 adds to
+ *    x (the W axis), channel 1 to y (H), channel 2 to z (D), in voxel units
+ *    (Alg. gridsampler: X = (x, y, z), displacement u[:, z, y, x]).
+ *  - All data pointers are DEVICE pointers, 4-byte aligned, owned by the
+ *    caller.  The library never allocates device memory: scratch comes from
+ *    a caller workspace whose size the *_workspace_bytes queries return
+ *    (it grows with the number of thread blocks, never with the voxel count).
+ *  - D*H*W must be below 2^31.
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  Arguments are validated on the host before anything is
+ *    launched; on error nothing is launched and outputs are untouched.
+ *  - Return value: FFDP_OK or one of the FFDP_ERR_* codes below.  The text
+ *    of the last error on the calling thread is in ffdp_last_error().
+ *  - Calls on different streams with disjoint outputs and workspaces may run
+ *    concurrently; the library keeps no mutable global state.
+ *  - Reductions are two-stage and in a fixed order (LNCC) or in exact
+ *    integer arithmetic (MI histogram), so results are bitwise reproducible.
+ */
+#ifndef FFDP_H
+#define FFDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FFDP_OK 0
+#define FFDP_ERR_NULL 1      /* a required pointer is NULL */
+#define FFDP_ERR_SHAPE 2     /* bad dimensions or ROI */
+#define FFDP_ERR_PARAM 3     /* bad window, eps, bins, pad mode, lr, step ... */
+#define FFDP_ERR_ALIGN 4     /* a pointer is not 4-byte aligned */
+#define FFDP_ERR_WORKSPACE 5 /* workspace NULL or smaller than the query */
+#define FFDP_ERR_HIP 6       /* the HIP runtime refused a launch */
+
+#define FFDP_PAD_BORDER 0 /* samples clamp to the array (default) */
+#define FFDP_PAD_ZEROS 1  /* lattice points outside the array read as 0 */
+
+/* Array geometry and the loss region (ROI), all in (z, y, x) order.  The ROI
+ * is the half-open box [roi_lo, roi_hi); it must be non-empty and inside the
+ * array.  Window sums read real array values around the ROI (the halo) and
+ * zeros outside the array. */
+typedef struct ffdp_grid {
+    int64_t D, H, W;
+    int64_t roi_lo[3];
+    int64_t roi_hi[3];
+} ffdp_grid;
+
+/* LNCC settings (App. "Definition of LNCC loss", Alg. fusedlncc):
+ *  window      odd box edge w in {3, 5, 7, 9}; the filter is the uniform
+ *              w^3 box with weights 1/w^3, zero padding at the array border.
+ *  eps         the stabiliser in n_i = A_i^2 / (B_i C_i + eps); >= 0.
+ *  ants_approx 1: skip the window sum of the adjoint (App. "ANTs gradient
+ *              approximation"); 0: exact gradient.
+ *  pad_mode    FFDP_PAD_BORDER or FFDP_PAD_ZEROS for the sampler. */
+typedef struct ffdp_lncc_params {
+    int32_t window;
+    float eps;
+    int32_t ants_approx;
+    int32_t pad_mode;
+} ffdp_lncc_params;
+
+/* MI settings (eq. mi, App. "Vanilla MI implementation"):
+ *  bins      B in [8, 64]; bin centres (m + 1/2)/B on [0, 1]; intensities
+ *            are clamped to [0, 1].  The kernel is the cubic B-spline of one
+ *            bin width; support beyond the first/last bin folds onto it.
+ *  hard_bins 1: box kernel (one bin per voxel, zero gradient) — test mode.
+ *  pad_mode  as for LNCC. */
+typedef struct ffdp_mi_params {
+    int32_t bins;
+    int32_t hard_bins;
+    int32_t pad_mode;
+    int32_t reserved; /* must be 0 */
+} ffdp_mi_params;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int ffdp_version(void);
+/* Static text for a status code. */
+const char* ffdp_status_string(int status);
+/* Text of the last error on this thread ("" if none). */
+const char* ffdp_last_error(void);
+
+/* Workspace bytes for the LNCC / MI calls on this geometry (0 never occurs). */
+size_t ffdp_lncc_workspace_bytes(const ffdp_grid* g, const ffdp_lncc_params* p);
+size_t ffdp_mi_workspace_bytes(const ffdp_grid* g, const ffdp_mi_params* p);
+/* Number of floats in the caller-owned MI state: 2*B*B + 2*B + 16. */
+size_t ffdp_mi_state_floats(int32_t bins);
+
+/* Composite implicit grid sampler, identity + displacement case
+ * (Sec. "Composite Implicit Grid Sampler", Alg. gridsampler Forward):
+ *   out(x) = M(x + u(x)) by trilinear interpolation (eq. interp).
+ * M [D][H][W]; u [3][D][H][W] or NULL (zero displacement); out [D][H][W].
+ * The ROI fields of g are ignored. */
+int ffdp_warp(const float* M, const float* u, const ffdp_grid* g, int32_t pad_mode, float* out, void* stream);
+
+/* Trilinear resize with corner alignment, the multi-scale pyramid step of the
+ * paper's registration loop: dst voxel j samples src at j*(n_src-1)/(n_dst-1)
+ * per axis; every value is multiplied by value_scale (2.0 when a displacement
+ * in voxels moves to a grid twice as fine).  src [channels][sD][sH][sW],
+ * dst [channels][dD][dH][dW]; src and dst must not overlap. */
+int ffdp_resample(const float* src, int64_t sD, int64_t sH, int64_t sW, float* dst, int64_t dD, int64_t dH,
+                  int64_t dW, int32_t channels, float value_scale, void* stream);
+
+/* Fused warp + LNCC forward (Alg. fusedlncc Forward with the sampler fused in):
+ *   loss = 1 - (1/N_roi) sum_{i in ROI} A_i^2/(B_i C_i + eps)
+ * with A, B, C the windowed covariance/variances of F and M(x + u).
+ * *loss (one device float) receives the value; ws/ws_bytes as queried. */
+int ffdp_warp_lncc_fwd(const float* F, const float* M, const float* u, const ffdp_grid* g,
+                       const ffdp_lncc_params* p, float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* Fused warp + LNCC forward and adjoint in one pass (Alg. fusedlncc Backward,
+ * eq. finalccgradM, Alg. gridsampler Backward for the displacement):
+ *   grad_u = grad_scale * dloss/du, OVERWRITTEN over the whole array (zero
+ *   where no window of the ROI reaches).
+ * grad_scale: device float or NULL (= 1).  loss: device float or NULL; when
+ * given it receives the same value as ffdp_warp_lncc_fwd. */
+int ffdp_warp_lncc_bwd(const float* F, const float* M, const float* u, const ffdp_grid* g,
+                       const ffdp_lncc_params* p, const float* grad_scale, float* grad_u, float* loss, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* Fused warp + Parzen MI forward (eq. mi; App. "Implicit MI implementation",
+ * Forward Pass): the joint histogram of (F, M(x+u)) over the ROI, then
+ *   loss = -MI = -sum p log(p / (p_F p_M)).
+ * mi_state (ffdp_mi_state_floats(bins) device floats, caller-owned) receives
+ *   [0, B*B)            T[m][n] = log p[m][n] - log p_M[n] (0 where p = 0)
+ *   [B*B, 2*B*B)        p[m][n] (m: F bin, n: warped-M bin)
+ *   [2B*B, 2B*B+B)      p_F;   [2B*B+B, 2B*B+2B) p_M
+ *   [2B*B+2B] loss, [+1] MI, [+2] bins, rest reserved.
+ * loss: device float (may point into mi_state). */
+int ffdp_warp_mi_fwd(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_mi_params* p,
+                     float* loss, float* mi_state, void* ws, size_t ws_bytes, void* stream);
+
+/* MI adjoint (App. "Implicit MI implementation", Backward Pass, with the
+ * sampler adjoint): grad_u = grad_scale * dloss/du, OVERWRITTEN over the whole
+ * array (zero outside the ROI).  mi_state must come from ffdp_warp_mi_fwd on
+ * the same F, M, u and parameters (a stale state gives a wrong gradient). */
+int ffdp_warp_mi_bwd(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_mi_params* p,
+                     const float* mi_state, const float* grad_scale, float* grad_u, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* Per-element Adam with bias correction, the optimiser with first and second
+ * moment states that the paper shards with the displacement (Sec. "Grid
+ * Parallel"), in place on x, m, v over n elements:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   x -= lr (m/(1-b1^step)) / (sqrt(v/(1-b2^step)) + eps)
+ * step >= 1; 0 <= b1, b2 < 1; eps > 0.  Also used for network weights. */
+int ffdp_adam_step(float* x, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                   float eps, int64_t step, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFDP_H */

@@ -1,0 +1,330 @@
+// C-ABI entry points: host-side validation, workspace layout, dispatch.
+// Nothing here allocates device memory.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/ffdp.h"
+#include "internal.hpp"
+
+using namespace ffdp;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return FFDP_OK;
+    return fail(FFDP_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool misaligned(const void* p) { return (((uintptr_t)p) & 3u) != 0; }
+
+constexpr int64_t MAX_VOXELS = 2147483647LL;  // 32-bit element offsets per channel
+
+int check_dims(int64_t D, int64_t H, int64_t W)
+{
+    if (D < 1 || H < 1 || W < 1) return fail(FFDP_ERR_SHAPE, "dimensions must be >= 1 (got %lld x %lld x %lld)",
+                                             (long long)D, (long long)H, (long long)W);
+    if (H > 65535) return fail(FFDP_ERR_SHAPE, "H must be <= 65535");
+    if (D > MAX_VOXELS / H || D * H > MAX_VOXELS / W)
+        return fail(FFDP_ERR_SHAPE, "D*H*W must be below 2^31");
+    return FFDP_OK;
+}
+
+int check_grid(const ffdp_grid* g)
+{
+    if (!g) return fail(FFDP_ERR_NULL, "grid is NULL");
+    int s = check_dims(g->D, g->H, g->W);
+    if (s) return s;
+    const int64_t n[3] = {g->D, g->H, g->W};
+    for (int k = 0; k < 3; ++k)
+        if (g->roi_lo[k] < 0 || g->roi_hi[k] > n[k] || g->roi_lo[k] >= g->roi_hi[k])
+            return fail(FFDP_ERR_SHAPE, "ROI axis %d [%lld, %lld) is empty or outside [0, %lld)", k,
+                        (long long)g->roi_lo[k], (long long)g->roi_hi[k], (long long)n[k]);
+    return FFDP_OK;
+}
+
+int check_lncc(const ffdp_lncc_params* p)
+{
+    if (!p) return fail(FFDP_ERR_NULL, "lncc params are NULL");
+    if (p->window != 3 && p->window != 5 && p->window != 7 && p->window != 9)
+        return fail(FFDP_ERR_PARAM, "window must be 3, 5, 7 or 9 (got %d)", p->window);
+    if (!(p->eps >= 0.0f) || isinf(p->eps)) return fail(FFDP_ERR_PARAM, "eps must be finite and >= 0");
+    if (p->ants_approx != 0 && p->ants_approx != 1) return fail(FFDP_ERR_PARAM, "ants_approx must be 0 or 1");
+    if (p->pad_mode != FFDP_PAD_BORDER && p->pad_mode != FFDP_PAD_ZEROS)
+        return fail(FFDP_ERR_PARAM, "pad_mode must be 0 (border) or 1 (zeros)");
+    return FFDP_OK;
+}
+
+int check_mi(const ffdp_mi_params* p)
+{
+    if (!p) return fail(FFDP_ERR_NULL, "mi params are NULL");
+    if (p->bins < 8 || p->bins > 64) return fail(FFDP_ERR_PARAM, "bins must be in [8, 64] (got %d)", p->bins);
+    if (p->hard_bins != 0 && p->hard_bins != 1) return fail(FFDP_ERR_PARAM, "hard_bins must be 0 or 1");
+    if (p->pad_mode != FFDP_PAD_BORDER && p->pad_mode != FFDP_PAD_ZEROS)
+        return fail(FFDP_ERR_PARAM, "pad_mode must be 0 (border) or 1 (zeros)");
+    if (p->reserved != 0) return fail(FFDP_ERR_PARAM, "reserved must be 0");
+    return FFDP_OK;
+}
+
+int check_ptrs(const char* names, int n, ...)
+{
+    // names: comma-separated names of the n pointers (for the error text)
+    va_list ap;
+    va_start(ap, n);
+    int code = FFDP_OK;
+    char which[64] = "";
+    for (int i = 0; i < n; ++i) {
+        const void* p = va_arg(ap, const void*);
+        if (code != FFDP_OK) continue;
+        if (!p) code = FFDP_ERR_NULL;
+        else if (misaligned(p)) code = FFDP_ERR_ALIGN;
+        if (code != FFDP_OK) {
+            // extract the i-th name
+            const char* s = names;
+            for (int k = 0; k < i && s; ++k) { s = strchr(s, ','); if (s) ++s; }
+            size_t len = 0;
+            while (s && s[len] && s[len] != ',' && len < sizeof(which) - 1) ++len;
+            if (s) memcpy(which, s, len);
+            which[len] = 0;
+        }
+    }
+    va_end(ap);
+    if (code == FFDP_ERR_NULL) return fail(code, "pointer '%s' is NULL", which);
+    if (code == FFDP_ERR_ALIGN) return fail(code, "pointer '%s' is not 4-byte aligned", which);
+    return FFDP_OK;
+}
+
+int check_opt_ptr(const void* p, const char* name)
+{
+    if (p && misaligned(p)) return fail(FFDP_ERR_ALIGN, "pointer '%s' is not 4-byte aligned", name);
+    return FFDP_OK;
+}
+
+double roi_voxels(const ffdp_grid* g)
+{
+    return (double)(g->roi_hi[0] - g->roi_lo[0]) * (double)(g->roi_hi[1] - g->roi_lo[1]) *
+           (double)(g->roi_hi[2] - g->roi_lo[2]);
+}
+
+void fill_roi(const ffdp_grid* g, int roi[6])
+{
+    roi[0] = (int)g->roi_lo[0]; roi[1] = (int)g->roi_hi[0];
+    roi[2] = (int)g->roi_lo[1]; roi[3] = (int)g->roi_hi[1];
+    roi[4] = (int)g->roi_lo[2]; roi[5] = (int)g->roi_hi[2];
+}
+
+size_t lncc_ws(const ffdp_grid* g)
+{
+    LnccLaunch L = lncc_plan((int)g->D, (int)g->H, (int)g->W);
+    return (size_t)L.nblocks * sizeof(double);
+}
+
+size_t mi_ws(const ffdp_mi_params* p) { return ((size_t)p->bins * p->bins + 1) * sizeof(unsigned long long); }
+
+int lncc_common(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_lncc_params* p,
+                void* ws, size_t ws_bytes, LnccArgs& a)
+{
+    int s = check_grid(g);
+    if (s) return s;
+    if ((s = check_lncc(p))) return s;
+    if ((s = check_ptrs("F,M", 2, (const void*)F, (const void*)M))) return s;
+    if ((s = check_opt_ptr(u, "u"))) return s;
+    const size_t need = lncc_ws(g);
+    if (!ws || ws_bytes < need)
+        return fail(FFDP_ERR_WORKSPACE, "workspace of %zu bytes required (got %zu%s)", need, ws_bytes,
+                    ws ? "" : ", NULL");
+    if (((uintptr_t)ws) & 7u) return fail(FFDP_ERR_ALIGN, "workspace must be 8-byte aligned");
+    LnccLaunch L = lncc_plan((int)g->D, (int)g->H, (int)g->W);
+    a.F = F; a.M = M; a.u = u; a.gu = nullptr; a.grad_scale = nullptr;
+    a.partial = (double*)ws;
+    a.D = (int)g->D; a.H = (int)g->H; a.W = (int)g->W;
+    fill_roi(g, a.roi);
+    a.eps = p->eps;
+    a.neg_inv_nroi = (float)(-1.0 / roi_voxels(g));
+    a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk; a.nblocks = L.nblocks;
+    return FFDP_OK;
+}
+
+int mi_common(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_mi_params* p,
+              void* ws, size_t ws_bytes, MiArgs& a)
+{
+    int s = check_grid(g);
+    if (s) return s;
+    if ((s = check_mi(p))) return s;
+    if ((s = check_ptrs("F,M", 2, (const void*)F, (const void*)M))) return s;
+    if ((s = check_opt_ptr(u, "u"))) return s;
+    const size_t need = mi_ws(p);
+    if (!ws || ws_bytes < need)
+        return fail(FFDP_ERR_WORKSPACE, "workspace of %zu bytes required (got %zu%s)", need, ws_bytes,
+                    ws ? "" : ", NULL");
+    if (((uintptr_t)ws) & 7u) return fail(FFDP_ERR_ALIGN, "workspace must be 8-byte aligned");
+    a.F = F; a.M = M; a.u = u;
+    a.D = (int)g->D; a.H = (int)g->H; a.W = (int)g->W;
+    fill_roi(g, a.roi);
+    a.bins = p->bins;
+    return FFDP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ffdp_version(void) { return 100; }
+
+const char* ffdp_status_string(int s)
+{
+    switch (s) {
+        case FFDP_OK: return "ok";
+        case FFDP_ERR_NULL: return "null pointer";
+        case FFDP_ERR_SHAPE: return "bad shape or ROI";
+        case FFDP_ERR_PARAM: return "bad parameter";
+        case FFDP_ERR_ALIGN: return "misaligned pointer";
+        case FFDP_ERR_WORKSPACE: return "workspace missing or too small";
+        case FFDP_ERR_HIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char* ffdp_last_error(void) { return g_err; }
+
+size_t ffdp_lncc_workspace_bytes(const ffdp_grid* g, const ffdp_lncc_params* p)
+{
+    (void)p;
+    if (!g || check_dims(g->D, g->H, g->W)) return sizeof(double);
+    return lncc_ws(g);
+}
+
+size_t ffdp_mi_workspace_bytes(const ffdp_grid* g, const ffdp_mi_params* p)
+{
+    (void)g;
+    if (!p || p->bins < 8 || p->bins > 64) return sizeof(unsigned long long) * (64 * 64 + 1);
+    return mi_ws(p);
+}
+
+size_t ffdp_mi_state_floats(int32_t bins)
+{
+    if (bins < 1) bins = 1;
+    return (size_t)2 * bins * bins + 2 * (size_t)bins + 16;
+}
+
+int ffdp_warp(const float* M, const float* u, const ffdp_grid* g, int32_t pad_mode, float* out, void* stream)
+{
+    if (!g) return fail(FFDP_ERR_NULL, "grid is NULL");
+    int s = check_dims(g->D, g->H, g->W);
+    if (s) return s;
+    if (pad_mode != FFDP_PAD_BORDER && pad_mode != FFDP_PAD_ZEROS)
+        return fail(FFDP_ERR_PARAM, "pad_mode must be 0 (border) or 1 (zeros)");
+    if ((s = check_ptrs("M,out", 2, (const void*)M, (const void*)out))) return s;
+    if ((s = check_opt_ptr(u, "u"))) return s;
+    if (out == M) return fail(FFDP_ERR_PARAM, "out must not alias M");
+    return hip_status(warp_launch(M, u, (int)g->D, (int)g->H, (int)g->W, pad_mode, out, (hipStream_t)stream),
+                      "ffdp_warp");
+}
+
+int ffdp_resample(const float* src, int64_t sD, int64_t sH, int64_t sW, float* dst, int64_t dD, int64_t dH,
+                  int64_t dW, int32_t channels, float value_scale, void* stream)
+{
+    int s;
+    if ((s = check_dims(sD, sH, sW))) return s;
+    if ((s = check_dims(dD, dH, dW))) return s;
+    if (channels < 1 || channels > 65535) return fail(FFDP_ERR_PARAM, "channels must be in [1, 65535]");
+    if (!isfinite(value_scale)) return fail(FFDP_ERR_PARAM, "value_scale must be finite");
+    if ((s = check_ptrs("src,dst", 2, (const void*)src, (const void*)dst))) return s;
+    const char* a0 = (const char*)src;
+    const char* a1 = a0 + (size_t)channels * sD * sH * sW * sizeof(float);
+    const char* b0 = (const char*)dst;
+    const char* b1 = b0 + (size_t)channels * dD * dH * dW * sizeof(float);
+    if (a0 < b1 && b0 < a1) return fail(FFDP_ERR_PARAM, "src and dst overlap");
+    return hip_status(resample_launch(src, (int)sD, (int)sH, (int)sW, dst, (int)dD, (int)dH, (int)dW, channels,
+                                      value_scale, (hipStream_t)stream),
+                      "ffdp_resample");
+}
+
+int ffdp_warp_lncc_fwd(const float* F, const float* M, const float* u, const ffdp_grid* g,
+                       const ffdp_lncc_params* p, float* loss, void* ws, size_t ws_bytes, void* stream)
+{
+    LnccArgs a;
+    int s = lncc_common(F, M, u, g, p, ws, ws_bytes, a);
+    if (s) return s;
+    if ((s = check_ptrs("loss", 1, (const void*)loss))) return s;
+    return hip_status(lncc_launch(0, p->window, p->pad_mode, a, loss, roi_voxels(g), (hipStream_t)stream),
+                      "ffdp_warp_lncc_fwd");
+}
+
+int ffdp_warp_lncc_bwd(const float* F, const float* M, const float* u, const ffdp_grid* g,
+                       const ffdp_lncc_params* p, const float* grad_scale, float* grad_u, float* loss, void* ws,
+                       size_t ws_bytes, void* stream)
+{
+    LnccArgs a;
+    int s = lncc_common(F, M, u, g, p, ws, ws_bytes, a);
+    if (s) return s;
+    if ((s = check_ptrs("grad_u", 1, (const void*)grad_u))) return s;
+    if ((s = check_opt_ptr(grad_scale, "grad_scale"))) return s;
+    if ((s = check_opt_ptr(loss, "loss"))) return s;
+    a.gu = grad_u;
+    a.grad_scale = grad_scale;
+    const int mode = p->ants_approx ? 2 : 1;
+    return hip_status(lncc_launch(mode, p->window, p->pad_mode, a, loss, roi_voxels(g), (hipStream_t)stream),
+                      "ffdp_warp_lncc_bwd");
+}
+
+int ffdp_warp_mi_fwd(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_mi_params* p,
+                     float* loss, float* mi_state, void* ws, size_t ws_bytes, void* stream)
+{
+    MiArgs a;
+    int s = mi_common(F, M, u, g, p, ws, ws_bytes, a);
+    if (s) return s;
+    if ((s = check_ptrs("loss,mi_state", 2, (const void*)loss, (const void*)mi_state))) return s;
+    MiLaunch L = mi_plan(a.roi[1] - a.roi[0], a.roi[3] - a.roi[2], a.roi[5] - a.roi[4]);
+    a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk; a.nblocks = L.nblocks;
+    return hip_status(mi_fwd_launch(a, p->hard_bins, p->pad_mode, (unsigned long long*)ws, mi_state, loss,
+                                    roi_voxels(g), (hipStream_t)stream),
+                      "ffdp_warp_mi_fwd");
+}
+
+int ffdp_warp_mi_bwd(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_mi_params* p,
+                     const float* mi_state, const float* grad_scale, float* grad_u, void* ws, size_t ws_bytes,
+                     void* stream)
+{
+    MiArgs a;
+    int s = mi_common(F, M, u, g, p, ws, ws_bytes, a);
+    if (s) return s;
+    if ((s = check_ptrs("mi_state,grad_u", 2, (const void*)mi_state, (const void*)grad_u))) return s;
+    if ((s = check_opt_ptr(grad_scale, "grad_scale"))) return s;
+    MiLaunch L = mi_plan(a.D, a.H, a.W);
+    a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk; a.nblocks = L.nblocks;
+    return hip_status(mi_bwd_launch(a, p->hard_bins, p->pad_mode, mi_state, grad_scale, grad_u, roi_voxels(g),
+                                    (hipStream_t)stream),
+                      "ffdp_warp_mi_bwd");
+}
+
+int ffdp_adam_step(float* x, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                   float eps, int64_t step, void* stream)
+{
+    int s;
+    if (n < 0) return fail(FFDP_ERR_SHAPE, "n must be >= 0");
+    if (n == 0) return FFDP_OK;
+    if ((s = check_ptrs("x,g,m,v", 4, (const void*)x, (const void*)g, (const void*)m, (const void*)v))) return s;
+    if (step < 1) return fail(FFDP_ERR_PARAM, "step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+        return fail(FFDP_ERR_PARAM, "betas must be in [0, 1)");
+    if (!(eps > 0.0f) || !isfinite(eps) || !isfinite(lr)) return fail(FFDP_ERR_PARAM, "eps > 0, lr finite required");
+    return hip_status(adam_launch(x, g, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream),
+                      "ffdp_adam_step");
+}
+
+}  // extern "C"

@@ -1,0 +1,292 @@
+// Fused warp + Parzen-window mutual information for gfx950.
+//
+// What is computed (eq. mi; App. "Implicit MI implementation"):
+//   p[m][n] = (1/N_roi) sum_{k in ROI} kappa_m(F_k) kappa_n(Mw_k),  Mw = M(x+u)
+//   MI = sum p log(p / (p_F p_M)),  loss = -MI
+//   dloss/dMw_k = -(1/N_roi) sum_{m,n} kappa_m(F_k) omega_n(Mw_k) T[m][n],
+//   T[m][n] = log p[m][n] - log p_M[n]
+// kappa_m(v) = beta3(s - m), s = clamp(v,0,1) B - 1/2, the cubic B-spline
+// over one bin width, support beyond the edge bins folded onto them;
+// omega = d kappa / dv.  The full derivative of MI with respect to p also has
+// the terms -log p_F[m] - 1, which drop out because sum_n omega_n = 0 (the
+// kernel is a partition of unity).
+//
+// Forward: no Parzen block is materialised (the paper's point).  Each voxel
+// touches a 4 x 4 patch of the joint histogram.  A thread walks one (x, y)
+// column along z; consecutive voxels of a smooth volume usually share the
+// same 4 x 4 patch, so the thread accumulates the patch in registers and
+// flushes it to an LDS histogram only when the patch moves.  LDS and global
+// histograms hold unsigned 64-bit fixed point (2^-32 units): integer atomics
+// commute, so the histogram is bitwise reproducible.  A one-block kernel
+// then forms p, the marginals, MI and the log table T.
+// Backward: T in LDS, 4 x 4 weighted lookups per voxel, then the sampler's
+// derivative; grad_u written over the whole array (zero outside the ROI).
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ffdp {
+
+constexpr double FIX_ONE = 4294967296.0;  // 2^32
+
+// Four cubic B-spline weights of v on bins j0..j0+3 (before folding) and, with
+// DERIV, their derivatives with respect to v.  Hard mode: one unit weight.
+template <bool HARD, bool DERIV>
+__device__ __forceinline__ void parzen4(float v, int B, int& j0, float w[4], float dw[4])
+{
+    const float vc = fminf(fmaxf(v, 0.0f), 1.0f);  // NaN -> 0; flagged separately
+    if (HARD) {
+        j0 = min((int)(vc * (float)B), B - 1);
+        w[0] = 1.0f; w[1] = w[2] = w[3] = 0.0f;
+        if (DERIV) dw[0] = dw[1] = dw[2] = dw[3] = 0.0f;
+        return;
+    }
+    const float s = vc * (float)B - 0.5f;
+    const float f = floorf(s);
+    const float t = s - f, q = 1.0f - t;
+    j0 = (int)f - 1;
+    const float t2 = t * t, q2 = q * q;
+    w[0] = q2 * q * (1.0f / 6.0f);
+    w[1] = fmaf(0.5f * t, t2, 2.0f / 3.0f - t2);
+    w[2] = fmaf(0.5f * q, q2, 2.0f / 3.0f - q2);
+    w[3] = t2 * t * (1.0f / 6.0f);
+    if (DERIV) {
+        const float ds = (v >= 0.0f && v <= 1.0f) ? (float)B : 0.0f;
+        dw[0] = -0.5f * q2 * ds;
+        dw[1] = fmaf(1.5f, t2, -2.0f * t) * ds;
+        dw[2] = fmaf(-1.5f, q2, 2.0f * q) * ds;
+        dw[3] = 0.5f * t2 * ds;
+    }
+}
+
+__device__ __forceinline__ int fold(int j, int B) { return min(max(j, 0), B - 1); }
+
+__device__ __forceinline__ unsigned long long to_fix(float x)
+{
+    return (unsigned long long)fma((double)x, FIX_ONE, 0.5);
+}
+
+template <bool HARD, int PAD>
+__global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long long* __restrict__ ghist,
+                                                        unsigned long long* __restrict__ gflag)
+{
+    extern __shared__ unsigned long long hist[];  // [B*B]
+    const int B = a.bins, BB = B * B;
+    for (int q = threadIdx.x; q < BB; q += MI_NT) hist[q] = 0ull;
+    __shared__ int nanflag;
+    if (threadIdx.x == 0) nanflag = 0;
+    __syncthreads();
+
+    const int bid = xcd_remap(blockIdx.x, a.nblocks);
+    const int tx = bid % a.ntx, rest = bid / a.ntx, ty = rest % a.nty, ch = rest / a.nty;
+    const int x = a.roi[4] + tx * MI_TX + (threadIdx.x % MI_TX);
+    const int y = a.roi[2] + ty * MI_TY + (threadIdx.x / MI_TX);
+    const int zb = a.roi[0] + ch * a.zchunk;
+    const int ze = min(a.roi[1], zb + a.zchunk);
+    const int H = a.H, W = a.W, HW = H * W;
+    const size_t N = (size_t)a.D * HW;
+    const bool active = x < a.roi[5] && y < a.roi[3];
+
+    int cm = -1000, cn = -1000;  // current 4x4 patch origin (sentinel: none)
+    float acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+    bool bad = false;
+
+    auto flush = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const unsigned long long v = to_fix(acc[i * 4 + jj]);
+                if (v) atomicAdd(&hist[fold(cm + i, B) * B + fold(cn + jj, B)], v);
+            }
+    };
+
+    if (active) {
+        for (int z = zb; z < ze; ++z) {
+            const int idx = z * HW + y * W + x;
+            float ux = 0.f, uy = 0.f, uz = 0.f;
+            if (a.u) { ux = a.u[idx]; uy = a.u[N + idx]; uz = a.u[2 * N + idx]; }
+            const float fv = a.F[idx];
+            const float mv = trilinear<PAD, false>(a.M, a.D, H, W, x, y, z, ux, uy, uz).v;
+            bad |= (fv != fv) || (mv != mv);
+            int jf, jm;
+            float wf[4], wm[4], dd[4];
+            parzen4<HARD, false>(fv, B, jf, wf, dd);
+            parzen4<HARD, false>(mv, B, jm, wm, dd);
+            if (jf != cm || jm != cn) {
+                if (cm != -1000) flush();
+                cm = jf; cn = jm;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) acc[i * 4 + jj] = fmaf(wf[i], wm[jj], acc[i * 4 + jj]);
+        }
+        if (cm != -1000) flush();
+    }
+    if (bad) nanflag = 1;
+    __syncthreads();
+    for (int q = threadIdx.x; q < BB; q += MI_NT) {
+        const unsigned long long v = hist[q];
+        if (v) atomicAdd(&ghist[q], v);
+    }
+    if (threadIdx.x == 0 && nanflag) atomicOr(gflag, 1ull);
+}
+
+__global__ void __launch_bounds__(256) mi_zero(unsigned long long* p, int n)
+{
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0ull;
+}
+
+// One block: p, marginals, MI, log table.  Fixed-order reductions.
+__global__ void __launch_bounds__(1024) mi_finalize(const unsigned long long* __restrict__ hist,
+                                                    const unsigned long long* __restrict__ flag, int B,
+                                                    double nroi, float* __restrict__ state, float* __restrict__ loss)
+{
+    __shared__ double pF[128], pM[128];
+    __shared__ double red[1024];
+    const int BB = B * B;
+    const double sc = 1.0 / (nroi * FIX_ONE);
+    for (int t = threadIdx.x; t < B; t += 1024) {
+        unsigned long long rs = 0, cs = 0;
+        for (int n = 0; n < B; ++n) rs += hist[t * B + n];
+        for (int m = 0; m < B; ++m) cs += hist[m * B + t];
+        pF[t] = (double)rs * sc;
+        pM[t] = (double)cs * sc;
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int q = threadIdx.x; q < BB; q += 1024) {
+        const int m = q / B, n = q - m * B;
+        const double p = (double)hist[q] * sc;
+        float tv = 0.0f;
+        if (p > 0.0) {
+            part += p * log(p / (pF[m] * pM[n]));
+            tv = (float)(log(p) - log(pM[n]));
+        }
+        state[q] = tv;
+        state[BB + q] = (float)p;
+    }
+    for (int t = threadIdx.x; t < B; t += 1024) {
+        state[2 * BB + t] = (float)pF[t];
+        state[2 * BB + B + t] = (float)pM[t];
+    }
+    const double mi = block_sum<1024>(part, red);
+    if (threadIdx.x == 0) {
+        const float l = (*flag) ? __int_as_float(0x7fc00000) : (float)(-mi);
+        float* hdr = state + 2 * BB + 2 * B;
+        hdr[0] = l;
+        hdr[1] = (float)mi;
+        hdr[2] = (float)B;
+        *loss = l;
+    }
+}
+
+template <bool HARD, int PAD>
+__global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* __restrict__ state,
+                                                        const float* __restrict__ grad_scale, float neg_inv_nroi,
+                                                        float* __restrict__ gu)
+{
+    extern __shared__ float T[];  // [B*B]
+    const int B = a.bins, BB = B * B;
+    for (int q = threadIdx.x; q < BB; q += MI_NT) T[q] = state[q];
+    __syncthreads();
+    const float g = neg_inv_nroi * (grad_scale ? *grad_scale : 1.0f);
+
+    const int bid = xcd_remap(blockIdx.x, a.nblocks);
+    const int tx = bid % a.ntx, rest = bid / a.ntx, ty = rest % a.nty, ch = rest / a.nty;
+    const int x = tx * MI_TX + (threadIdx.x % MI_TX);
+    const int y = ty * MI_TY + (threadIdx.x / MI_TX);
+    const int zb = ch * a.zchunk, ze = min(a.D, zb + a.zchunk);
+    const int H = a.H, W = a.W, HW = H * W;
+    const size_t N = (size_t)a.D * HW;
+    if (x >= W || y >= H) return;
+    const bool colroi = x >= a.roi[4] && x < a.roi[5] && y >= a.roi[2] && y < a.roi[3];
+    for (int z = zb; z < ze; ++z) {
+        const int idx = z * HW + y * W + x;
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+        if (!HARD && colroi && z >= a.roi[0] && z < a.roi[1]) {
+            float ux = 0.f, uy = 0.f, uz = 0.f;
+            if (a.u) { ux = a.u[idx]; uy = a.u[N + idx]; uz = a.u[2 * N + idx]; }
+            const Tri t = trilinear<PAD, true>(a.M, a.D, H, W, x, y, z, ux, uy, uz);
+            int jf, jm;
+            float wf[4], wm[4], dm[4], dd[4];
+            parzen4<false, false>(a.F[idx], B, jf, wf, dd);
+            parzen4<false, true>(t.v, B, jm, wm, dm);
+            float S = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float* row = T + fold(jf + i, B) * B;
+                float si = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) si = fmaf(dm[jj], row[fold(jm + jj, B)], si);
+                S = fmaf(wf[i], si, S);
+            }
+            const float gm = g * S;
+            g0 = gm * t.dx; g1 = gm * t.dy; g2 = gm * t.dz;
+        }
+        gu[idx] = g0;
+        gu[N + idx] = g1;
+        gu[2 * N + idx] = g2;
+    }
+}
+
+MiLaunch mi_plan(int rz, int ry, int rx)
+{
+    MiLaunch L;
+    L.ntx = (rx + MI_TX - 1) / MI_TX;
+    L.nty = (ry + MI_TY - 1) / MI_TY;
+    const int tiles = L.ntx * L.nty;
+    int chunks = 4096 / tiles;
+    const int maxchunks = (rz + 31) / 32;
+    if (chunks > maxchunks) chunks = maxchunks;
+    if (chunks < 1) chunks = 1;
+    L.zchunk = (rz + chunks - 1) / chunks;
+    L.nchunks = (rz + L.zchunk - 1) / L.zchunk;
+    L.nblocks = tiles * L.nchunks;
+    return L;
+}
+
+hipError_t mi_fwd_launch(const MiArgs& a, int hard, int pad, unsigned long long* hist, float* state, float* loss,
+                         double nroi, hipStream_t st)
+{
+    const int BB = a.bins * a.bins;
+    unsigned long long* flag = hist + BB;
+    hipLaunchKernelGGL(mi_zero, dim3((BB + 1 + 255) / 256), dim3(256), 0, st, hist, BB + 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = sizeof(unsigned long long) * BB;
+    dim3 grid(a.nblocks), block(MI_NT);
+    if (hard) {
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER>), grid, block, lds, st, a, hist, flag);
+        else hipLaunchKernelGGL((mi_hist_kernel<true, PAD_ZEROS>), grid, block, lds, st, a, hist, flag);
+    } else {
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<false, PAD_BORDER>), grid, block, lds, st, a, hist, flag);
+        else hipLaunchKernelGGL((mi_hist_kernel<false, PAD_ZEROS>), grid, block, lds, st, a, hist, flag);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mi_finalize, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, nroi, state, loss);
+    return hipGetLastError();
+}
+
+hipError_t mi_bwd_launch(const MiArgs& a, int hard, int pad, const float* state, const float* grad_scale,
+                         float* gu, double nroi, hipStream_t st)
+{
+    const size_t lds = sizeof(float) * a.bins * a.bins;
+    dim3 grid(a.nblocks), block(MI_NT);
+    const float nin = (float)(-1.0 / nroi);
+    if (hard) {
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<true, PAD_BORDER>), grid, block, lds, st, a, state, grad_scale, nin, gu);
+        else hipLaunchKernelGGL((mi_grad_kernel<true, PAD_ZEROS>), grid, block, lds, st, a, state, grad_scale, nin, gu);
+    } else {
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<false, PAD_BORDER>), grid, block, lds, st, a, state, grad_scale, nin, gu);
+        else hipLaunchKernelGGL((mi_grad_kernel<false, PAD_ZEROS>), grid, block, lds, st, a, state, grad_scale, nin, gu);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ffdp

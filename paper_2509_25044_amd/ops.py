@@ -1,0 +1,208 @@
+"""Torch-tensor front end of the C ABI, one function per entry point, same names.
+
+Tensors must be float32, contiguous and on a HIP device; every call runs on
+the current torch stream of that device.  Only argument marshalling happens
+here: the computation is entirely in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import Grid, LnccParams, MiParams, check
+
+PAD = {"border": 0, "zeros": 1, 0: 0, 1: 1}
+
+_ws_cache: dict = {}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(t: torch.Tensor):
+    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _vol(t: torch.Tensor, name: str, ndim: int = 3):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a HIP device (got {t.device}); the library has no CPU path")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32 (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions (got shape {tuple(t.shape)})")
+    return t
+
+
+def make_grid(shape: Sequence[int], roi=None) -> Grid:
+    """shape (D, H, W); roi ((z0,z1),(y0,y1),(x0,x1)) or None for the full array."""
+    D, H, W = (int(s) for s in shape)
+    g = Grid()
+    g.D, g.H, g.W = D, H, W
+    if roi is None:
+        roi = ((0, D), (0, H), (0, W))
+    for k in range(3):
+        g.roi_lo[k] = int(roi[k][0])
+        g.roi_hi[k] = int(roi[k][1])
+    return g
+
+
+def roi_voxels(shape, roi=None) -> int:
+    if roi is None:
+        return int(shape[0]) * int(shape[1]) * int(shape[2])
+    return (roi[0][1] - roi[0][0]) * (roi[1][1] - roi[1][0]) * (roi[2][1] - roi[2][0])
+
+
+def _workspace(nbytes: int, device, ws: Optional[torch.Tensor]) -> torch.Tensor:
+    if ws is not None:
+        return ws
+    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
+    t = _ws_cache.get(key)
+    if t is None or t.numel() < nbytes:
+        t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = t
+    return t
+
+
+def _check_pair(F, M, u):
+    _vol(F, "F")
+    _vol(M, "M")
+    if F.shape != M.shape:
+        raise ValueError(f"F and M shapes differ: {tuple(F.shape)} vs {tuple(M.shape)}")
+    if F.device != M.device:
+        raise ValueError("F and M are on different devices")
+    if u is not None:
+        _vol(u, "u", 4)
+        if tuple(u.shape) != (3,) + tuple(F.shape) or u.device != F.device:
+            raise ValueError(f"u must be [3, D, H, W] on F's device (got {tuple(u.shape)})")
+
+
+def lncc_params(window=5, eps=1e-5, ants=False, pad="border") -> LnccParams:
+    p = LnccParams()
+    p.window, p.eps, p.ants_approx, p.pad_mode = int(window), float(eps), int(bool(ants)), PAD[pad]
+    return p
+
+
+def mi_params(bins=32, hard=False, pad="border") -> MiParams:
+    p = MiParams()
+    p.bins, p.hard_bins, p.pad_mode, p.reserved = int(bins), int(bool(hard)), PAD[pad], 0
+    return p
+
+
+def lncc_workspace_bytes(shape, roi=None, window=5) -> int:
+    g = make_grid(shape, roi)
+    return int(_lib.lib().ffdp_lncc_workspace_bytes(C.byref(g), C.byref(lncc_params(window))))
+
+
+def mi_workspace_bytes(bins=32) -> int:
+    g = make_grid((1, 1, 1))
+    return int(_lib.lib().ffdp_mi_workspace_bytes(C.byref(g), C.byref(mi_params(bins))))
+
+
+def mi_state_floats(bins=32) -> int:
+    return int(_lib.lib().ffdp_mi_state_floats(int(bins)))
+
+
+# ----------------------------------------------------------------------------
+def warp(M: torch.Tensor, u: Optional[torch.Tensor] = None, pad="border", out=None) -> torch.Tensor:
+    """M(x + u(x)) by trilinear sampling (ffdp_warp)."""
+    _vol(M, "M")
+    if u is not None:
+        _vol(u, "u", 4)
+    out = torch.empty_like(M) if out is None else _vol(out, "out")
+    g = make_grid(M.shape)
+    check("ffdp_warp", _lib.lib().ffdp_warp(_ptr(M), _ptr(u), C.byref(g), PAD[pad], _ptr(out), _stream(M)))
+    return out
+
+
+def resample(src: torch.Tensor, size: Sequence[int], value_scale: float = 1.0, out=None) -> torch.Tensor:
+    """Corner-aligned trilinear resize of [C, D, H, W] or [D, H, W] (ffdp_resample)."""
+    squeeze = src.dim() == 3
+    s4 = src[None] if squeeze else src
+    _vol(s4, "src", 4)
+    Cn = s4.shape[0]
+    dD, dH, dW = (int(v) for v in size)
+    o4 = torch.empty((Cn, dD, dH, dW), dtype=torch.float32, device=src.device) if out is None else out.view(Cn, dD, dH, dW)
+    check("ffdp_resample", _lib.lib().ffdp_resample(_ptr(s4), s4.shape[1], s4.shape[2], s4.shape[3], _ptr(o4),
+                                                     dD, dH, dW, Cn, float(value_scale), _stream(src)))
+    return o4[0] if squeeze else o4
+
+
+def warp_lncc_fwd(F, M, u=None, window=5, eps=1e-5, pad="border", roi=None, loss=None, ws=None) -> torch.Tensor:
+    """LNCC loss 1 - mean n_i of (F, M(x+u)) over the ROI -> float32 tensor [1] (ffdp_warp_lncc_fwd)."""
+    _check_pair(F, M, u)
+    g = make_grid(F.shape, roi)
+    p = lncc_params(window, eps, False, pad)
+    L = _lib.lib()
+    ws = _workspace(int(L.ffdp_lncc_workspace_bytes(C.byref(g), C.byref(p))), F.device, ws)
+    loss = torch.empty(1, dtype=torch.float32, device=F.device) if loss is None else loss
+    check("ffdp_warp_lncc_fwd", L.ffdp_warp_lncc_fwd(_ptr(F), _ptr(M), _ptr(u), C.byref(g), C.byref(p), _ptr(loss),
+                                                      _ptr(ws), ws.numel(), _stream(F)))
+    return loss
+
+
+def warp_lncc_bwd(F, M, u=None, window=5, eps=1e-5, ants=False, pad="border", roi=None, grad_scale=None,
+                  grad_u=None, loss=None, want_loss=True, ws=None) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+    """Fused LNCC forward + adjoint: (grad_u [3,D,H,W], loss [1] or None) (ffdp_warp_lncc_bwd)."""
+    _check_pair(F, M, u)
+    g = make_grid(F.shape, roi)
+    p = lncc_params(window, eps, ants, pad)
+    L = _lib.lib()
+    ws = _workspace(int(L.ffdp_lncc_workspace_bytes(C.byref(g), C.byref(p))), F.device, ws)
+    if grad_u is None:
+        grad_u = torch.empty((3,) + tuple(F.shape), dtype=torch.float32, device=F.device)
+    if loss is None and want_loss:
+        loss = torch.empty(1, dtype=torch.float32, device=F.device)
+    check("ffdp_warp_lncc_bwd", L.ffdp_warp_lncc_bwd(_ptr(F), _ptr(M), _ptr(u), C.byref(g), C.byref(p),
+                                                      _ptr(grad_scale), _ptr(grad_u), _ptr(loss), _ptr(ws),
+                                                      ws.numel(), _stream(F)))
+    return grad_u, loss
+
+
+def warp_mi_fwd(F, M, u=None, bins=32, hard=False, pad="border", roi=None, state=None, loss=None, ws=None):
+    """Parzen MI: (loss = -MI [1], mi_state) (ffdp_warp_mi_fwd)."""
+    _check_pair(F, M, u)
+    g = make_grid(F.shape, roi)
+    p = mi_params(bins, hard, pad)
+    L = _lib.lib()
+    ws = _workspace(int(L.ffdp_mi_workspace_bytes(C.byref(g), C.byref(p))), F.device, ws)
+    if state is None:
+        state = torch.empty(int(L.ffdp_mi_state_floats(int(bins))), dtype=torch.float32, device=F.device)
+    loss = torch.empty(1, dtype=torch.float32, device=F.device) if loss is None else loss
+    check("ffdp_warp_mi_fwd", L.ffdp_warp_mi_fwd(_ptr(F), _ptr(M), _ptr(u), C.byref(g), C.byref(p), _ptr(loss),
+                                                  _ptr(state), _ptr(ws), ws.numel(), _stream(F)))
+    return loss, state
+
+
+def warp_mi_bwd(F, M, u, state, bins=32, hard=False, pad="border", roi=None, grad_scale=None, grad_u=None, ws=None):
+    """MI adjoint -> grad_u [3,D,H,W] (ffdp_warp_mi_bwd)."""
+    _check_pair(F, M, u)
+    g = make_grid(F.shape, roi)
+    p = mi_params(bins, hard, pad)
+    L = _lib.lib()
+    ws = _workspace(int(L.ffdp_mi_workspace_bytes(C.byref(g), C.byref(p))), F.device, ws)
+    if grad_u is None:
+        grad_u = torch.empty((3,) + tuple(F.shape), dtype=torch.float32, device=F.device)
+    check("ffdp_warp_mi_bwd", L.ffdp_warp_mi_bwd(_ptr(F), _ptr(M), _ptr(u), C.byref(g), C.byref(p), _ptr(state),
+                                                  _ptr(grad_scale), _ptr(grad_u), _ptr(ws), ws.numel(), _stream(F)))
+    return grad_u
+
+
+def adam_step(x, g, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
+    """In-place Adam on x, m, v (ffdp_adam_step)."""
+    for t, n in ((x, "x"), (g, "g"), (m, "m"), (v, "v")):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"{n} must be a contiguous float32 device tensor")
+        if t.numel() != x.numel():
+            raise ValueError("x, g, m, v must have the same number of elements")
+    check("ffdp_adam_step", _lib.lib().ffdp_adam_step(_ptr(x), _ptr(g), _ptr(m), _ptr(v), x.numel(), float(lr),
+                                                       float(beta1), float(beta2), float(eps), int(step),
+                                                       _stream(x)))
+    return x

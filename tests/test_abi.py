@@ -1,0 +1,155 @@
+"""The C-ABI library: it loads, exports every declared entry point, and its
+host-side validation rejects bad arguments before any launch (no GPU needed:
+every call below fails validation, so nothing reaches the HIP runtime)."""
+import ctypes as C
+import os
+import subprocess
+
+import pytest
+
+from paper_2509_25044_amd import _lib
+from paper_2509_25044_amd._lib import Grid, LnccParams, MiParams
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def test_every_header_function_is_exported(L):
+    names = _lib.header_functions()
+    assert len(names) >= 13
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(L, n)
+
+
+def test_library_is_gfx950_code_object():
+    data = open(_lib.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in data
+
+
+def _grid(D=8, H=8, W=8, roi=None):
+    g = Grid()
+    g.D, g.H, g.W = D, H, W
+    roi = roi or ((0, D), (0, H), (0, W))
+    for k in range(3):
+        g.roi_lo[k], g.roi_hi[k] = roi[k]
+    return g
+
+
+def _lp(window=5, eps=1e-5, ants=0, pad=0):
+    p = LnccParams()
+    p.window, p.eps, p.ants_approx, p.pad_mode = window, eps, ants, pad
+    return p
+
+
+def _mp(bins=32, hard=0, pad=0, reserved=0):
+    p = MiParams()
+    p.bins, p.hard_bins, p.pad_mode, p.reserved = bins, hard, pad, reserved
+    return p
+
+
+FAKE = C.c_void_p(0x10000)       # 4-byte aligned, never dereferenced (validation fails first)
+FAKE_MIS = C.c_void_p(0x10002)   # misaligned
+
+
+def test_status_strings_and_version(L):
+    assert L.ffdp_version() >= 100
+    assert L.ffdp_status_string(0) == b"ok"
+    assert L.ffdp_status_string(5).startswith(b"workspace")
+    assert L.ffdp_status_string(99) == b"unknown status"
+
+
+def test_workspace_queries_grow_with_blocks_not_voxels(L):
+    lp = _lp()
+    small = L.ffdp_lncc_workspace_bytes(C.byref(_grid(64, 64, 64)), C.byref(lp))
+    big = L.ffdp_lncc_workspace_bytes(C.byref(_grid(512, 512, 512)), C.byref(lp))
+    assert 0 < small <= big <= 64 * 1024      # O(#blocks) doubles, far below N
+    assert L.ffdp_mi_workspace_bytes(C.byref(_grid()), C.byref(_mp(32))) == (32 * 32 + 1) * 8
+    assert L.ffdp_mi_state_floats(32) == 2 * 32 * 32 + 2 * 32 + 16
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(F=None), 1),
+    (dict(M=None), 1),
+    (dict(grid=None), 1),
+    (dict(params=None), 1),
+    (dict(F=FAKE_MIS), 4),
+    (dict(u=FAKE_MIS), 4),
+    (dict(grid=_grid(0, 8, 8)), 2),
+    (dict(grid=_grid(8, 8, 8, ((0, 9), (0, 8), (0, 8)))), 2),
+    (dict(grid=_grid(8, 8, 8, ((3, 3), (0, 8), (0, 8)))), 2),
+    (dict(grid=_grid(2048, 2048, 1024)), 2),
+    (dict(grid=_grid(8, 70000, 8)), 2),
+    (dict(params=_lp(window=4)), 3),
+    (dict(params=_lp(window=11)), 3),
+    (dict(params=_lp(window=1)), 3),
+    (dict(params=_lp(eps=-1.0)), 3),
+    (dict(params=_lp(eps=float("nan"))), 3),
+    (dict(params=_lp(pad=2)), 3),
+    (dict(params=_lp(ants=3)), 3),
+    (dict(ws=None), 5),
+    (dict(ws_bytes=1), 5),
+    (dict(loss=None), 1),
+])
+def test_lncc_fwd_validation(L, kw, code):
+    a = dict(F=FAKE, M=FAKE, u=None, grid=_grid(), params=_lp(), loss=FAKE, ws=FAKE, ws_bytes=1 << 20)
+    a.update(kw)
+    g = C.byref(a["grid"]) if a["grid"] is not None else None
+    p = C.byref(a["params"]) if a["params"] is not None else None
+    s = L.ffdp_warp_lncc_fwd(a["F"], a["M"], a["u"], g, p, a["loss"], a["ws"], a["ws_bytes"], None)
+    assert s == code, L.ffdp_last_error()
+    assert len(L.ffdp_last_error()) > 0
+
+
+def test_lncc_bwd_validation(L):
+    g, p = _grid(), _lp()
+    assert L.ffdp_warp_lncc_bwd(FAKE, FAKE, None, C.byref(g), C.byref(p), None, None, None, FAKE, 1 << 20, None) == 1
+    assert L.ffdp_warp_lncc_bwd(FAKE, FAKE, None, C.byref(g), C.byref(p), FAKE_MIS, FAKE, None, FAKE, 1 << 20,
+                                None) == 4
+    assert L.ffdp_warp_lncc_bwd(FAKE, FAKE, None, C.byref(g), C.byref(_lp(window=2)), None, FAKE, None, FAKE,
+                                1 << 20, None) == 3
+
+
+@pytest.mark.parametrize("mp,code", [(_mp(bins=7), 3), (_mp(bins=65), 3), (_mp(hard=2), 3), (_mp(pad=5), 3),
+                                     (_mp(reserved=1), 3)])
+def test_mi_validation(L, mp, code):
+    g = _grid()
+    s = L.ffdp_warp_mi_fwd(FAKE, FAKE, None, C.byref(g), C.byref(mp), FAKE, FAKE, FAKE, 1 << 20, None)
+    assert s == code
+    s = L.ffdp_warp_mi_bwd(FAKE, FAKE, None, C.byref(g), C.byref(mp), FAKE, None, FAKE, FAKE, 1 << 20, None)
+    assert s == code
+
+
+def test_mi_workspace_and_null_checks(L):
+    g, mp = _grid(), _mp()
+    assert L.ffdp_warp_mi_fwd(FAKE, FAKE, None, C.byref(g), C.byref(mp), FAKE, FAKE, FAKE, 8, None) == 5
+    assert L.ffdp_warp_mi_fwd(FAKE, FAKE, None, C.byref(g), C.byref(mp), FAKE, None, FAKE, 1 << 20, None) == 1
+    assert L.ffdp_warp_mi_bwd(FAKE, FAKE, None, C.byref(g), C.byref(mp), None, None, FAKE, FAKE, 1 << 20, None) == 1
+
+
+def test_adam_validation(L):
+    assert L.ffdp_adam_step(FAKE, FAKE, FAKE, FAKE, 0, 0.1, 0.9, 0.999, 1e-8, 1, None) == 0  # n = 0: no-op
+    assert L.ffdp_adam_step(FAKE, FAKE, FAKE, FAKE, -1, 0.1, 0.9, 0.999, 1e-8, 1, None) == 2
+    assert L.ffdp_adam_step(None, FAKE, FAKE, FAKE, 8, 0.1, 0.9, 0.999, 1e-8, 1, None) == 1
+    assert L.ffdp_adam_step(FAKE, FAKE, FAKE, FAKE, 8, 0.1, 0.9, 0.999, 1e-8, 0, None) == 3
+    assert L.ffdp_adam_step(FAKE, FAKE, FAKE, FAKE, 8, 0.1, 1.0, 0.999, 1e-8, 1, None) == 3
+    assert L.ffdp_adam_step(FAKE, FAKE, FAKE, FAKE, 8, 0.1, 0.9, 0.999, 0.0, 1, None) == 3
+    assert L.ffdp_adam_step(FAKE, FAKE_MIS, FAKE, FAKE, 8, 0.1, 0.9, 0.999, 1e-8, 1, None) == 4
+
+
+def test_warp_and_resample_validation(L):
+    g = _grid()
+    assert L.ffdp_warp(None, None, C.byref(g), 0, FAKE, None) == 1
+    assert L.ffdp_warp(FAKE, None, C.byref(g), 3, FAKE, None) == 3
+    assert L.ffdp_warp(FAKE, None, C.byref(g), 0, FAKE, None) == 3  # out aliases M
+    assert L.ffdp_resample(FAKE, 4, 4, 4, FAKE, 8, 8, 8, 1, 2.0, None) == 3  # overlap
+    assert L.ffdp_resample(FAKE, 0, 4, 4, C.c_void_p(0x900000), 8, 8, 8, 1, 2.0, None) == 2
+    assert L.ffdp_resample(FAKE, 4, 4, 4, C.c_void_p(0x900000), 8, 8, 8, 0, 2.0, None) == 3

@@ -1,0 +1,231 @@
+"""GPU parity: every C-ABI call against the FP64 oracle on the same seeded inputs.
+
+Sizes stay where the oracle finishes in seconds but span several 64 x 16
+tiles, z-chunks and ragged tails; edge cases cover single voxels, ROIs, the
+zero-padding sampler, NaN propagation and determinism.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2509_25044_amd import ops, synth
+from paper_2509_25044_amd.configs import C1, C2
+from parity_util import assert_grad, assert_loss
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _dev(t):
+    return t.to(DEV).contiguous()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _roi6(roi):
+    return None if roi is None else np.array([roi[0][0], roi[0][1], roi[1][0], roi[1][1], roi[2][0], roi[2][1]])
+
+
+@pytest.fixture(scope="module")
+def c1():
+    p = synth.make_pair(C1.pair, seed=2025)
+    u = (-0.6 * p["d"]).contiguous()
+    return p["F"], p["M"], u
+
+
+@pytest.fixture(scope="module")
+def c2():
+    p = synth.make_pair(C2.pair, seed=2025)
+    u = (-0.6 * p["d"]).contiguous()
+    return p["F"], p["M"], u
+
+
+def _rand_case(shape, seed, scale=2.0):
+    F = synth.random_volume(shape, seed)
+    M = synth.random_volume(shape, seed + 1)
+    u = synth.random_disp(shape, seed + 2, scale)
+    return F, M, u
+
+
+# ------------------------------------------------------------------ warp ----
+@pytest.mark.parametrize("shift", [(0, 0, 0), (3, -2, 1), (-7, 5, 11)])
+def test_warp_integer_shift_bitwise(shift):
+    print(f"[warp int shift {shift}]", flush=True)
+    F, M, _ = _rand_case((19, 23, 70), 100)
+    u = torch.zeros((3, 19, 23, 70))
+    for c in range(3):
+        u[c] = shift[c]
+    out = _np(ops.warp(_dev(M), _dev(u)))
+    ref = oracle.warp(M.numpy(), u.numpy())
+    assert np.array_equal(out.astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("pad", ["border", "zeros"])
+def test_warp_random_field(pad):
+    print(f"[warp random {pad}]", flush=True)
+    F, M, u = _rand_case((21, 33, 130), 110, scale=4.0)
+    out = _np(ops.warp(_dev(M), _dev(u), pad=pad))
+    ref = oracle.warp(M.numpy(), u.numpy(), pad=1 if pad == "zeros" else 0)
+    np.testing.assert_allclose(out, ref, rtol=0, atol=2e-6)
+
+
+def test_resample_matches_oracle():
+    print("[resample]", flush=True)
+    src = synth.random_disp((10, 12, 14), 120, 3.0)
+    out = _np(ops.resample(_dev(src), (20, 24, 28), value_scale=2.0))
+    ref = oracle.resample(src.numpy(), (20, 24, 28), value_scale=2.0)
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-5)
+    down = _np(ops.resample(_dev(src), (5, 6, 7), value_scale=0.5))
+    np.testing.assert_allclose(down, oracle.resample(src.numpy(), (5, 6, 7), 0.5), rtol=0, atol=1e-5)
+
+
+# ------------------------------------------------------------------ LNCC ----
+def _lncc_case(F, M, u, window=5, eps=1e-5, ants=False, pad="border", roi=None, what=""):
+    print(f"[lncc {what} shape={tuple(F.shape)} w={window} ants={ants} pad={pad} roi={roi}]", flush=True)
+    Fd, Md = _dev(F), _dev(M)
+    ud = None if u is None else _dev(u)
+    lf = float(ops.warp_lncc_fwd(Fd, Md, ud, window=window, eps=eps, pad=pad, roi=roi).item())
+    g, lb = ops.warp_lncc_bwd(Fd, Md, ud, window=window, eps=eps, ants=ants, pad=pad, roi=roi)
+    lb = float(lb.item())
+    lr, gr = oracle.lncc(F.numpy(), M.numpy(), None if u is None else u.numpy(), roi=_roi6(roi), window=window,
+                         eps=eps, ants=ants, pad=1 if pad == "zeros" else 0)
+    assert_loss(lf, lr, f"{what} fwd")
+    assert_loss(lb, lr, f"{what} bwd")
+    assert_grad(_np(g), gr, f"{what} grad")
+
+
+@pytest.mark.parametrize("window", [3, 5, 7, 9])
+def test_lncc_c1_pair(c1, window):
+    F, M, u = c1
+    _lncc_case(F, M, u, window=window, what="c1")
+
+
+def test_lncc_c1_zero_displacement_and_self(c1):
+    F, M, u = c1
+    _lncc_case(F, M, None, window=5, what="c1 u=None")
+    # F against itself at u = 0 and eps = 0: LNCC = 1 everywhere -> loss 0
+    l = float(ops.warp_lncc_fwd(_dev(F), _dev(F), None, window=5, eps=0.0).item())
+    assert abs(l) < 1e-5
+
+
+def test_lncc_c1_ants(c1):
+    F, M, u = c1
+    _lncc_case(F, M, u, window=5, ants=True, what="c1 ants")
+
+
+def test_lncc_c1_zeros_pad_and_roi(c1):
+    F, M, u = c1
+    _lncc_case(F, M, u * 3.0, window=5, pad="zeros", what="c1 zeros")
+    _lncc_case(F, M, u, window=5, roi=((8, 56), (3, 61), (10, 50)), what="c1 roi")
+
+
+def test_lncc_c2_clinical_window7(c2):
+    F, M, u = c2
+    _lncc_case(F, M, u, window=7, what="c2")
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (2, 40, 3), (37, 45, 70), (20, 17, 130)])
+def test_lncc_ragged_shapes(shape):
+    F, M, u = _rand_case(shape, 130)
+    _lncc_case(F, M, u, window=5, eps=1e-3, what="ragged")
+    _lncc_case(F, M, u, window=3, eps=1e-3, ants=True, what="ragged ants")
+
+
+def test_lncc_deterministic(c1):
+    F, M, u = (_dev(t) for t in c1)
+    g1, l1 = ops.warp_lncc_bwd(F, M, u)
+    g2, l2 = ops.warp_lncc_bwd(F, M, u)
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+
+
+def test_lncc_grad_scale_and_nan(c1):
+    F, M, u = (_dev(t) for t in c1)
+    g1, _ = ops.warp_lncc_bwd(F, M, u)
+    s = torch.tensor([2.5], device=DEV)
+    g2, _ = ops.warp_lncc_bwd(F, M, u, grad_scale=s)
+    torch.testing.assert_close(g2, g1 * 2.5, rtol=1e-6, atol=0)
+    Fn = F.clone()
+    Fn[10, 10, 10] = float("nan")
+    l = ops.warp_lncc_fwd(Fn, M, u)
+    assert torch.isnan(l).all()
+
+
+# -------------------------------------------------------------------- MI ----
+def _mi_case(F, M, u, bins=32, hard=False, pad="border", roi=None, what=""):
+    print(f"[mi {what} shape={tuple(F.shape)} bins={bins} hard={hard} pad={pad} roi={roi}]", flush=True)
+    Fd, Md = _dev(F), _dev(M)
+    ud = None if u is None else _dev(u)
+    loss, state = ops.warp_mi_fwd(Fd, Md, ud, bins=bins, hard=hard, pad=pad, roi=roi)
+    g = ops.warp_mi_bwd(Fd, Md, ud, state, bins=bins, hard=hard, pad=pad, roi=roi)
+    lr, pr, gr = oracle.mi(F.numpy(), M.numpy(), None if u is None else u.numpy(), roi=_roi6(roi), bins=bins,
+                           hard=hard, pad=1 if pad == "zeros" else 0)
+    assert_loss(float(loss.item()), lr, f"{what} loss")
+    st = _np(state)
+    B = bins
+    np.testing.assert_allclose(st[B * B:2 * B * B].reshape(B, B), pr, rtol=1e-5, atol=1e-9)
+    if hard:
+        assert float(g.abs().max()) == 0.0
+    else:
+        assert_grad(_np(g), gr, f"{what} grad")
+
+
+def test_mi_c1_pair(c1):
+    F, M, u = c1
+    _mi_case(F, M, u, bins=32, what="c1")
+    _mi_case(F, M, None, bins=8, what="c1 b8 u=None")
+
+
+def test_mi_c2_multimodal(c2):
+    F, M, u = c2
+    _mi_case(F, M, u, bins=32, what="c2")
+
+
+def test_mi_roi_zeros_hard(c1):
+    F, M, u = c1
+    _mi_case(F, M, u, bins=16, roi=((5, 60), (0, 64), (7, 33)), what="c1 roi")
+    _mi_case(F, M, u * 3, bins=32, pad="zeros", what="c1 zeros")
+    _mi_case(F, M, u, bins=32, hard=True, what="c1 hard")
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (37, 45, 70)])
+def test_mi_ragged_shapes(shape):
+    F, M, u = _rand_case(shape, 140)
+    _mi_case(F, M, u, bins=16, what="ragged")
+
+
+def test_mi_self_information_and_determinism(c1):
+    F = _dev(c1[0])
+    loss, state = ops.warp_mi_fwd(F, F, None, bins=32, hard=True)
+    B = 32
+    pF = _np(state)[2 * B * B:2 * B * B + B].astype(np.float64)
+    H = -(pF[pF > 0] * np.log(pF[pF > 0])).sum()
+    assert abs(-float(loss.item()) - H) < 1e-5 * H
+    F, M, u = (_dev(t) for t in c1)
+    l1, s1 = ops.warp_mi_fwd(F, M, u)
+    l2, s2 = ops.warp_mi_fwd(F, M, u)
+    assert torch.equal(l1, l2) and torch.equal(s1, s2)
+    g1 = ops.warp_mi_bwd(F, M, u, s1)
+    g2 = ops.warp_mi_bwd(F, M, u, s1)
+    assert torch.equal(g1, g2)
+
+
+# ------------------------------------------------------------------ Adam ----
+@pytest.mark.parametrize("n,offset", [(1_000_003, 0), (4099, 1), (7, 0)])
+def test_adam_matches_oracle(n, offset):
+    print(f"[adam n={n} offset={offset}]", flush=True)
+    rng = np.random.default_rng(150)
+    x0 = rng.normal(size=n + offset).astype(np.float32)
+    xd = torch.from_numpy(x0).to(DEV)
+    md = torch.zeros_like(xd)
+    vd = torch.zeros_like(xd)
+    xr, mr, vr = x0[offset:].astype(np.float64), np.zeros(n), np.zeros(n)
+    for step in range(1, 6):
+        g = (rng.normal(size=n + offset) * 10.0 ** rng.integers(-3, 2)).astype(np.float32)
+        gd = torch.from_numpy(g).to(DEV)
+        ops.adam_step(xd[offset:], gd[offset:], md[offset:], vd[offset:], lr=0.1, step=step)
+        oracle.adam(xr, g[offset:].astype(np.float64), mr, vr, lr=0.1, step=step)
+    np.testing.assert_allclose(_np(xd)[offset:], xr, rtol=2e-6, atol=2e-6)
+    np.testing.assert_allclose(_np(md)[offset:], mr, rtol=2e-6, atol=1e-9)
