@@ -106,7 +106,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=C3.name)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slab", type=int, default=160)
+    ap.add_argument("--cpu-slab", type=int, default=0, help="oracle z-slab depth (0 = whole volume)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -220,7 +220,7 @@ def main():
         "kernel_source_hash": kernel_source_hash(),
     }
     if not args.no_cpu_baseline:
-        slab = min(args.cpu_slab, F.shape[0])
+        slab = F.shape[0] if args.cpu_slab <= 0 else min(args.cpu_slab, F.shape[0])
         out["cpu_baseline"] = cpu_baseline(F, M, u_l, wl.lncc_window, slab)
     else:
         out["cpu_baseline"] = None

@@ -141,20 +141,32 @@ __global__ void __launch_bounds__(256) mi_zero(unsigned long long* p, int n)
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0ull;
 }
 
-// One block: p, marginals, MI, log table.  Fixed-order reductions.
+// One block: p, marginals, MI, log table.  Fixed-order reductions.  The
+// histogram is normalised by its own total (exact integer sum): the B-spline
+// weights partition unity only up to fp32 rounding, and dividing by the total
+// keeps p a probability mass function, so that for instance p = p_F p_M
+// holds to the fixed-point resolution when it holds exactly.
 __global__ void __launch_bounds__(1024) mi_finalize(const unsigned long long* __restrict__ hist,
                                                     const unsigned long long* __restrict__ flag, int B,
-                                                    double nroi, float* __restrict__ state, float* __restrict__ loss)
+                                                    float* __restrict__ state, float* __restrict__ loss)
 {
-    __shared__ double pF[128], pM[128];
+    __shared__ double pF[64], pM[64];
+    __shared__ unsigned long long rowsum[64];
     __shared__ double red[1024];
     const int BB = B * B;
-    const double sc = 1.0 / (nroi * FIX_ONE);
     for (int t = threadIdx.x; t < B; t += 1024) {
-        unsigned long long rs = 0, cs = 0;
+        unsigned long long rs = 0;
         for (int n = 0; n < B; ++n) rs += hist[t * B + n];
+        rowsum[t] = rs;
+    }
+    __syncthreads();
+    unsigned long long total = 0;
+    for (int t = 0; t < B; ++t) total += rowsum[t];
+    const double sc = total ? 1.0 / (double)total : 0.0;
+    for (int t = threadIdx.x; t < B; t += 1024) {
+        unsigned long long cs = 0;
         for (int m = 0; m < B; ++m) cs += hist[m * B + t];
-        pF[t] = (double)rs * sc;
+        pF[t] = (double)rowsum[t] * sc;
         pM[t] = (double)cs * sc;
     }
     __syncthreads();
@@ -181,6 +193,7 @@ __global__ void __launch_bounds__(1024) mi_finalize(const unsigned long long* __
         hdr[0] = l;
         hdr[1] = (float)mi;
         hdr[2] = (float)B;
+        for (int k = 3; k < 16; ++k) hdr[k] = 0.0f;  // reserved
         *loss = l;
     }
 }
@@ -269,7 +282,7 @@ hipError_t mi_fwd_launch(const MiArgs& a, int hard, int pad, unsigned long long*
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mi_finalize, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, nroi, state, loss);
+    hipLaunchKernelGGL(mi_finalize, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, state, loss);
     return hipGetLastError();
 }
 
