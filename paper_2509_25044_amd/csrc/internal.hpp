@@ -6,8 +6,8 @@
 
 namespace ffdp {
 
-// LNCC tile: 64 x 16 columns per block, 512 threads (8 waves of 64)
-constexpr int LNCC_TX = 64;
+// LNCC tile: 32 x 16 columns per block, 512 threads (8 waves of 64)
+constexpr int LNCC_TX = 32;
 constexpr int LNCC_TY = 16;
 constexpr int LNCC_NT = 512;
 

@@ -14,18 +14,21 @@
 // differentiated here, so three fields (a, c, e) suffice.
 //
 // Design (one kernel, nothing N-sized in HBM besides inputs and grad_u):
-//  * a block owns a TX x TY column tile and a z-chunk, and streams z slices;
+//  * a block of 512 threads owns a 32 x 16 column tile and a z-chunk and
+//    streams z slices through a pipeline of LDS stages;
 //  * stage A samples F and Mw on the tile plus a halo of 2r (r for the
-//    forward), keeping the last w slices per column in registers, and writes
-//    the five z-window sums to LDS;
-//  * stages B/C finish the separable box in x then y, form A, B, C and the
-//    loss term, then a, c, e; stages D/E box a, c, e in x, y and (via a
-//    register ring) z; stage F re-samples Mw with its derivative at the output
-//    voxel and writes grad_u.  Interpolation weights are recomputed, never stored.
-//  * all statistics use values shifted by a per-block constant (F and M at
-//    the tile centre).  With the padded voxels shifted too, A, B, C and the
-//    adjoint are unchanged in exact arithmetic, and the fp32 cancellation in
-//    B = mu_FF - mu_F^2 shrinks.
+//    forward) and keeps the last w slices of every column in registers; for
+//    the tile's own voxel (one per thread) it also keeps dMw/dp, so the output stage never
+//    samples again.  It writes the five z-window sums to LDS;
+//  * stage B sums x-windows, stage C y-windows, forms A, B, C, the loss term
+//    and a, c, e; stages D/E box a, c, e in x, y and (register ring) z; stage
+//    F combines them with the stored F, Mw and dMw/dp of the slice 2r behind
+//    the sampling front and writes grad_u.
+//  * the x- and y-window passes read and write 2 floats per LDS access;
+//  * statistics use values shifted by a per-block constant (F and M at the
+//    tile centre).  With padded voxels shifted too, A, B, C and the adjoint
+//    are unchanged in exact arithmetic and the fp32 cancellation in
+//    B = mu_FF - mu_F^2 shrinks;
 //  * window sums are direct w-term sums (no running add/subtract drift).
 #include "device.hpp"
 #include "internal.hpp"
@@ -33,6 +36,8 @@
 namespace ffdp {
 
 enum { MODE_FWD = 0, MODE_BWD = 1, MODE_ANTS = 2 };
+
+__host__ __device__ constexpr int round4(int v) { return (v + 3) & ~3; }
 
 template <int WIN, int MODE>
 struct LnccTile {
@@ -42,31 +47,64 @@ struct LnccTile {
     static constexpr int R1 = (MODE == MODE_BWD) ? r : 0;      // stage-C halo
     static constexpr int X2 = TX + 2 * R2, Y2 = TY + 2 * R2;
     static constexpr int X1 = TX + 2 * R1, Y1 = TY + 2 * R1;
-    static constexpr int NA = X2 * Y2;  // stage A points
-    static constexpr int NB = Y2 * X1;  // x-box outputs
-    static constexpr int NC = X1 * Y1;  // statistic points
-    static constexpr int ND = Y1 * TX;  // x-box of the adjoint fields
-    static constexpr int NE = TX * TY;  // output points
-    static constexpr int PA = (NA + NT - 1) / NT;
-    static constexpr int PE = (NE + NT - 1) / NT;
+    static constexpr int X1p = round4(X1);           // LDS row pitch of x-windowed data
+    static constexpr int X2p = round4(X1p + 2 * r);  // LDS row pitch of stage-A data
+    static constexpr int NV = (WIN + 2) / 2;         // float2 reads per 2-wide x-window run
+    static constexpr int NA = Y2 * X2p;              // floats per channel, stage A
+    static constexpr int NB = Y2 * X1p;              // x-window
+    static constexpr int NC = Y1 * X1p;              // a, c, e
+    static constexpr int ND = Y1 * TX;               // x-window of a, c, e
+    static constexpr int NH = X2 * Y2 - TX * TY;     // halo-only stage-A points
+    static constexpr int PH = (NH + NT - 1) / NT;
+    static constexpr int RB = Y2 * X1p / 2;          // 2-wide runs, stage B
+    static constexpr int RC = Y1 * X1p / 2;          // 2-wide runs, stage C (adjoint mode)
+    static constexpr int RD = Y1 * TX / 2;           // 2-wide runs, stage D
     static constexpr int LDS_FLOATS = 5 * NA + 5 * NB;
+    static_assert(TX * TY == NT, "one tile voxel per thread");
+    static_assert(3 * NC <= 5 * NA && 3 * ND <= 5 * NB, "aliased LDS buffers must fit");
 };
 
+// 2-wide run of w-tap window sums along a row: out[e] = sum_{d<w} row[e + d]
+template <int WIN, int NV>
+__device__ __forceinline__ float2 xwin2(const float* row)
+{
+    float v[2 * NV];
+    const float2* src = reinterpret_cast<const float2*>(row);
+#pragma unroll
+    for (int n = 0; n < NV; ++n) {
+        const float2 t = src[n];
+        v[2 * n] = t.x;
+        v[2 * n + 1] = t.y;
+    }
+    float o0 = v[0], o1 = v[1];
+#pragma unroll
+    for (int d = 1; d < WIN; ++d) {
+        o0 += v[d];
+        o1 += v[d + 1];
+    }
+    return make_float2(o0, o1);
+}
+
+// Windows up to 5 are held to 128 VGPRs so two 512-thread blocks share a CU.
 template <int WIN, int MODE, int PAD>
-__global__ void __launch_bounds__(LNCC_NT) lncc_kernel(LnccArgs a)
+__global__ void __launch_bounds__(LNCC_NT) __attribute__((amdgpu_waves_per_eu(WIN <= 5 ? 4 : 2, 8)))
+lncc_kernel(LnccArgs a)
 {
     using T = LnccTile<WIN, MODE>;
     constexpr int r = T::r, TX = T::TX, TY = T::TY, NT = T::NT;
     constexpr int R2 = T::R2, R1 = T::R1, X2 = T::X2, X1 = T::X1;
+    constexpr int X1p = T::X1p, X2p = T::X2p;
+    constexpr bool DER = (MODE != MODE_FWD);  // keep dMw/dp of the tile voxel
     constexpr float inv = 1.0f / float(WIN * WIN * WIN);
-    __shared__ float lds[T::LDS_FLOATS];
-    float* sA = lds;               // [5][NA]  z-window sums on the stage-A points
-    float* sB = lds + 5 * T::NA;   // [5][NB]  x-box
-    float* sC = lds;               // [3][NC]  a, c, e (aliases sA)
-    float* sD = lds + 5 * T::NA;   // [3][ND]  x-box of a, c, e (aliases sB)
+    __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
+    float* sA = lds;               // [5][Y2][X2p]  z-window sums
+    float* sB = lds + 5 * T::NA;   // [5][Y2][X1p]  + x-window
+    float* sC = lds;               // [3][Y1][X1p]  a, c, e (aliases sA)
+    float* sD = lds + 5 * T::NA;   // [3][Y1][TX]   x-window of a, c, e (aliases sB)
 
     const int D = a.D, H = a.H, W = a.W;
     const int HW = H * W;
+    const size_t N = (size_t)D * HW;
     const int bid = xcd_remap(blockIdx.x, a.nblocks);
     const int tx = bid % a.ntx;
     const int rest = bid / a.ntx;
@@ -78,9 +116,22 @@ __global__ void __launch_bounds__(LNCC_NT) lncc_kernel(LnccArgs a)
 
     const float* __restrict__ F = a.F;
     const float* __restrict__ M = a.M;
-    const float* __restrict__ u0 = a.u;
-    const float* __restrict__ u1 = a.u ? a.u + (size_t)D * HW : nullptr;
-    const float* __restrict__ u2 = a.u ? a.u + 2 * (size_t)D * HW : nullptr;
+    const float* __restrict__ U = a.u;
+
+    // the thread's tile voxel (row iy, column ix) and halo-only stage-A points
+    const int iy = tid / TX, ix = tid % TX;
+    int hx[T::PH], hy[T::PH];
+#pragma unroll
+    for (int k = 0; k < T::PH; ++k) {
+        int q = tid + k * NT;
+        hx[k] = -1; hy[k] = -1;
+        if (q < T::NH) {
+            if (q < R2 * X2) { hy[k] = q / X2; hx[k] = q - hy[k] * X2; }
+            else if ((q -= R2 * X2) < R2 * X2) { hy[k] = R2 + TY + q / X2; hx[k] = q % X2; }
+            else if ((q -= R2 * X2) < TY * R2) { hy[k] = R2 + q / R2; hx[k] = q % R2; }
+            else { q -= TY * R2; hy[k] = R2 + q / R2; hx[k] = R2 + TX + q % R2; }
+        }
+    }
 
     // per-block shift: F and M at the tile centre
     const int sidx = (min((z0 + z1) / 2, D - 1) * H + min(gy0 + TY / 2, H - 1)) * W + min(gx0 + TX / 2, W - 1);
@@ -89,9 +140,40 @@ __global__ void __launch_bounds__(LNCC_NT) lncc_kernel(LnccArgs a)
     const float gi = a.neg_inv_nroi * gsc;  // dL/dn_i on the ROI
     const float eps = a.eps;
 
-    float rF[T::PA][WIN], rM[T::PA][WIN];  // raw shifted samples, last w slices
-    float rE[3][T::PE][WIN];               // xy-boxed a, c, e, last w slices
+    float rF[1 + T::PH][WIN], rM[1 + T::PH][WIN];  // shifted F, Mw: last w slices
+    float rG[DER ? 3 : 1][WIN];                    // dMw/dp of the tile voxel
+    float rE[MODE == MODE_BWD ? 3 : 1][WIN];       // xy-windowed a, c, e of the tile voxel
     double lsum = 0.0;
+
+    // stage-A points of this thread: k = 0 the tile voxel, k >= 1 halo points
+    constexpr int P = 1 + T::PH;
+    int pgx[P], pgy[P], pxy[P];
+    bool pin[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int lx = k == 0 ? R2 + ix : hx[k - 1];
+        const int ly = k == 0 ? R2 + iy : hy[k - 1];
+        pgx[k] = gx0 - R2 + lx;
+        pgy[k] = gy0 - R2 + ly;
+        pin[k] = lx >= 0 && pgx[k] >= 0 && pgx[k] < W && pgy[k] >= 0 && pgy[k] < H;
+        pxy[k] = pin[k] ? pgy[k] * W + pgx[k] : 0;
+    }
+    // u and F of the next slice are loaded one step ahead, so their HBM
+    // latency overlaps the LDS stages of the current slice
+    float pu[P][3], pf[P];
+    auto prefetch = [&](int zs) {
+        const bool zok = zs >= 0 && zs < D;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            pf[k] = 0.f; pu[k][0] = 0.f; pu[k][1] = 0.f; pu[k][2] = 0.f;
+            if (zok && pin[k]) {
+                const int idx = zs * HW + pxy[k];
+                pf[k] = F[idx];
+                if (U) { pu[k][0] = U[idx]; pu[k][1] = U[N + idx]; pu[k][2] = U[2 * N + idx]; }
+            }
+        }
+    };
+    prefetch(z0 - R2);
 
     const int nsteps = (z1 - z0) + 2 * R2;
     for (int base = 0; base < nsteps; base += WIN) {
@@ -99,25 +181,26 @@ __global__ void __launch_bounds__(LNCC_NT) lncc_kernel(LnccArgs a)
         for (int j = 0; j < WIN; ++j) {
             const int s = base + j;
             if (s >= nsteps) break;
-            const int zi = z0 - R2 + s;  // slice entering the ring
+            const int zi = z0 - R2 + s;  // slice entering the rings
             const bool zin = (zi >= 0) && (zi < D);
-            // ---- stage A: sample, push into the ring, z-window sums ----
+            // ---- stage A: sample, push into the rings, z-window sums ----
 #pragma unroll
-            for (int k = 0; k < T::PA; ++k) {
-                const int p = tid + k * NT;
-                if (p < T::NA) {
-                    const int ly = p / X2, lx = p - ly * X2;
-                    const int gx = gx0 - R2 + lx, gy = gy0 - R2 + ly;
+            for (int k = 0; k < P; ++k) {
+                if (k == 0 || hx[k - 1] >= 0) {
                     float f = -sF, m = -sM;  // padded voxels are 0 before the shift
-                    if (zin && gx >= 0 && gx < W && gy >= 0 && gy < H) {
-                        const int idx = zi * HW + gy * W + gx;
-                        float ux = 0.f, uy = 0.f, uz = 0.f;
-                        if (u0) { ux = u0[idx]; uy = u1[idx]; uz = u2[idx]; }
-                        f = F[idx] - sF;
-                        m = trilinear<PAD, false>(M, D, H, W, gx, gy, zi, ux, uy, uz).v - sM;
+                    float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+                    if (zin && pin[k]) {
+                        f = pf[k] - sF;
+                        if (DER && k == 0) {
+                            const Tri t = trilinear<PAD, true>(M, D, H, W, pgx[k], pgy[k], zi, pu[k][0], pu[k][1], pu[k][2]);
+                            m = t.v - sM; d0 = t.dx; d1 = t.dy; d2 = t.dz;
+                        } else {
+                            m = trilinear<PAD, false>(M, D, H, W, pgx[k], pgy[k], zi, pu[k][0], pu[k][1], pu[k][2]).v - sM;
+                        }
                     }
                     rF[k][j] = f;
                     rM[k][j] = m;
+                    if (DER && k == 0) { rG[0][j] = d0; rG[1][j] = d1; rG[2][j] = d2; }
                     if (s >= 2 * r) {
                         float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
 #pragma unroll
@@ -129,127 +212,147 @@ __global__ void __launch_bounds__(LNCC_NT) lncc_kernel(LnccArgs a)
                             s3 = fmaf(mm, mm, s3);
                             s4 = fmaf(ff, mm, s4);
                         }
-                        sA[0 * T::NA + p] = s0;
-                        sA[1 * T::NA + p] = s1;
-                        sA[2 * T::NA + p] = s2;
-                        sA[3 * T::NA + p] = s3;
-                        sA[4 * T::NA + p] = s4;
+                        const int lx = k == 0 ? R2 + ix : hx[k - 1];
+                        const int ly = k == 0 ? R2 + iy : hy[k - 1];
+                        const int o = ly * X2p + lx;
+                        sA[0 * T::NA + o] = s0;
+                        sA[1 * T::NA + o] = s1;
+                        sA[2 * T::NA + o] = s2;
+                        sA[3 * T::NA + o] = s3;
+                        sA[4 * T::NA + o] = s4;
                     }
                 }
             }
-            if (s < 2 * r) continue;  // ring not yet full (uniform over the block)
+            prefetch(zi + 1);
+            if (s < 2 * r) continue;  // rings not yet full (uniform over the block)
             __syncthreads();
-            // ---- stage B: x-box ----
-            for (int p = tid; p < T::NB; p += NT) {
-                const int ly = p / X1, lx = p - ly * X1;
-                const int b0 = ly * X2 + lx;
+            // ---- stage B: x-window, 2 outputs per thread ----
+            for (int q = tid; q < T::RB; q += NT) {
+                const int ly = q / (X1p / 2), lx0 = 2 * (q - ly * (X1p / 2));
 #pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    float acc = 0.f;
-#pragma unroll
-                    for (int d = 0; d < WIN; ++d) acc += sA[c * T::NA + b0 + d];
-                    sB[c * T::NB + p] = acc;
-                }
+                for (int c = 0; c < 5; ++c)
+                    *reinterpret_cast<float2*>(sB + c * T::NB + ly * X1p + lx0) =
+                        xwin2<WIN, T::NV>(sA + c * T::NA + ly * X2p + lx0);
             }
             __syncthreads();
-            // ---- stage C: y-box, statistics, loss term, adjoint fields ----
+            // ---- stage C: y-window, statistics, loss term, adjoint fields ----
             const int zc = zi - r;
-            for (int p = tid; p < T::NC; p += NT) {
-                const int ly = p / X1, lx = p - ly * X1;
+            const bool zroi = zc >= a.roi[0] && zc < a.roi[1];
+            const bool zown = zc >= z0 && zc < z1;
+            if (MODE == MODE_BWD) {
+                for (int q = tid; q < T::RC; q += NT) {
+                    const int ly = q / (X1p / 2), lx0 = 2 * (q - ly * (X1p / 2));
+                    float S[5][2];
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) {
+                        float2 acc = *reinterpret_cast<const float2*>(sB + c * T::NB + ly * X1p + lx0);
+#pragma unroll
+                        for (int d = 1; d < WIN; ++d) {
+                            const float2 t2 = *reinterpret_cast<const float2*>(sB + c * T::NB + (ly + d) * X1p + lx0);
+                            acc.x += t2.x;
+                            acc.y += t2.y;
+                        }
+                        S[c][0] = acc.x;
+                        S[c][1] = acc.y;
+                    }
+                    const int gy = gy0 - R1 + ly;
+                    const bool yroi = zroi && gy >= a.roi[2] && gy < a.roi[3];
+                    const bool yown = zown && ly >= R1 && ly < R1 + TY;
+                    float oa[2], oc[2], oe[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int lx = lx0 + e;
+                        const int gx = gx0 - R1 + lx;
+                        const bool inroi = yroi && lx < X1 && gx >= a.roi[4] && gx < a.roi[5];
+                        const float mf = S[0][e] * inv, mm = S[1][e] * inv;
+                        const float A = fmaf(-mf, mm, S[4][e] * inv);
+                        const float B = fmaf(-mf, mf, S[2][e] * inv);
+                        const float C = fmaf(-mm, mm, S[3][e] * inv);
+                        const float rD = 1.0f / fmaf(B, C, eps);
+                        float ac = 0.f, cc = 0.f, ec = 0.f;
+                        if (inroi) {
+                            if (yown && lx >= R1 && lx < R1 + TX) lsum += (double)(A * A * rD);
+                            ac = 2.0f * gi * A * rD;
+                            cc = ac * A * B * rD;
+                            ec = fmaf(cc, mm, -ac * mf);
+                        }
+                        oa[e] = ac; oc[e] = cc; oe[e] = ec;
+                    }
+                    const int o = ly * X1p + lx0;
+                    *reinterpret_cast<float2*>(sC + 0 * T::NC + o) = make_float2(oa[0], oa[1]);
+                    *reinterpret_cast<float2*>(sC + 1 * T::NC + o) = make_float2(oc[0], oc[1]);
+                    *reinterpret_cast<float2*>(sC + 2 * T::NC + o) = make_float2(oe[0], oe[1]);
+                }
+            } else {
+                // forward / ANTs: statistics at the thread's own tile voxel
                 float S[5];
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     float acc = 0.f;
 #pragma unroll
-                    for (int d = 0; d < WIN; ++d) acc += sB[c * T::NB + (ly + d) * X1 + lx];
+                    for (int d = 0; d < WIN; ++d) acc += sB[c * T::NB + (iy + d) * X1p + ix];
                     S[c] = acc;
                 }
-                const int gx = gx0 - R1 + lx, gy = gy0 - R1 + ly;
-                const bool inroi = zc >= a.roi[0] && zc < a.roi[1] && gy >= a.roi[2] && gy < a.roi[3] &&
-                                   gx >= a.roi[4] && gx < a.roi[5];
-                const bool owned = lx >= R1 && lx < R1 + TX && ly >= R1 && ly < R1 + TY && zc >= z0 && zc < z1;
+                const int gx = gx0 + ix, gy = gy0 + iy;
+                const bool inroi = zroi && gy >= a.roi[2] && gy < a.roi[3] && gx >= a.roi[4] && gx < a.roi[5];
                 const float mf = S[0] * inv, mm = S[1] * inv;
                 const float A = fmaf(-mf, mm, S[4] * inv);
                 const float B = fmaf(-mf, mf, S[2] * inv);
                 const float C = fmaf(-mm, mm, S[3] * inv);
-                const float Dn = fmaf(B, C, eps);
-                if (inroi && owned) lsum += (double)(A * A / Dn);
-                if (MODE == MODE_BWD) {
-                    float ac = 0.f, cc = 0.f, ec = 0.f;
-                    if (inroi) {
-                        ac = 2.0f * gi * A / Dn;
-                        cc = ac * A * B / Dn;
-                        ec = fmaf(cc, mm, -ac * mf);
-                    }
-                    sC[0 * T::NC + p] = ac;
-                    sC[1 * T::NC + p] = cc;
-                    sC[2 * T::NC + p] = ec;
-                }
-                if (MODE == MODE_ANTS && owned && gx < W && gy < H) {
+                const float rD = 1.0f / fmaf(B, C, eps);
+                if (inroi && zown) lsum += (double)(A * A * rD);
+                if (MODE == MODE_ANTS && zown && gx < W && gy < H) {
                     // gradient without the second window sum, at the voxel itself
-                    const int idx = zc * HW + gy * W + gx;
+                    const int sl = (j + WIN - r) % WIN;  // ring slot of slice zc
                     float g0 = 0.f, g1 = 0.f, g2 = 0.f;
                     if (inroi) {
-                        float ux = 0.f, uy = 0.f, uz = 0.f;
-                        if (u0) { ux = u0[idx]; uy = u1[idx]; uz = u2[idx]; }
-                        const Tri t = trilinear<PAD, true>(M, D, H, W, gx, gy, zc, ux, uy, uz);
-                        const float ac = 2.0f * gi * A / Dn;
-                        const float cc = ac * A * B / Dn;
-                        const float gm = ac * ((F[idx] - sF) - mf) - cc * ((t.v - sM) - mm);
-                        g0 = gm * t.dx; g1 = gm * t.dy; g2 = gm * t.dz;
+                        const float ac = 2.0f * gi * A * rD;
+                        const float cc = ac * A * B * rD;
+                        const float gm = ac * (rF[0][sl] - mf) - cc * (rM[0][sl] - mm);
+                        g0 = gm * rG[0][sl]; g1 = gm * rG[1][sl]; g2 = gm * rG[2][sl];
                     }
+                    const size_t idx = (size_t)zc * HW + (size_t)gy * W + gx;
                     a.gu[idx] = g0;
-                    a.gu[(size_t)D * HW + idx] = g1;
-                    a.gu[2 * (size_t)D * HW + idx] = g2;
+                    a.gu[N + idx] = g1;
+                    a.gu[2 * N + idx] = g2;
                 }
             }
             if (MODE != MODE_BWD) continue;
             __syncthreads();
-            // ---- stage D: x-box of a, c, e ----
-            for (int p = tid; p < T::ND; p += NT) {
-                const int ly = p / TX, lx = p - ly * TX;
-                const int b0 = ly * X1 + lx;
+            // ---- stage D: x-window of a, c, e ----
+            for (int q = tid; q < T::RD; q += NT) {
+                const int ly = q / (TX / 2), lx0 = 2 * (q - ly * (TX / 2));
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    *reinterpret_cast<float2*>(sD + c * T::ND + ly * TX + lx0) =
+                        xwin2<WIN, T::NV>(sC + c * T::NC + ly * X1p + lx0);
+            }
+            __syncthreads();
+            // ---- stages E/F: y-window into the ring, z-window, gradient ----
+            {
+                const int zo = zc - r;
+                const int so = (j + 1) % WIN;  // ring slot of slice zo (the oldest)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     float acc = 0.f;
 #pragma unroll
-                    for (int d = 0; d < WIN; ++d) acc += sC[c * T::NC + b0 + d];
-                    sD[c * T::ND + p] = acc;
+                    for (int d = 0; d < WIN; ++d) acc += sD[c * T::ND + (iy + d) * TX + ix];
+                    rE[c][j] = acc;
                 }
-            }
-            __syncthreads();
-            // ---- stages E/F: y-box into the register ring, z-box, gradient ----
-            const int zo = zc - r;
+                const int gx = gx0 + ix, gy = gy0 + iy;
+                if (s >= 4 * r && zo >= z0 && zo < z1 && gx < W && gy < H) {
+                    float ba = 0.f, bc = 0.f, be = 0.f;
 #pragma unroll
-            for (int k = 0; k < T::PE; ++k) {
-                const int p = tid + k * NT;
-                if (p < T::NE) {
-                    const int ly = p / TX, lx = p - ly * TX;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        float acc = 0.f;
-#pragma unroll
-                        for (int d = 0; d < WIN; ++d) acc += sD[c * T::ND + (ly + d) * TX + lx];
-                        rE[c][k][j] = acc;
+                    for (int q = 0; q < WIN; ++q) {
+                        ba += rE[0][q];
+                        bc += rE[1][q];
+                        be += rE[2][q];
                     }
-                    const int gx = gx0 + lx, gy = gy0 + ly;
-                    if (s >= 4 * r && zo >= z0 && zo < z1 && gx < W && gy < H) {
-                        float ba = 0.f, bc = 0.f, be = 0.f;
-#pragma unroll
-                        for (int q = 0; q < WIN; ++q) {
-                            ba += rE[0][k][q];
-                            bc += rE[1][k][q];
-                            be += rE[2][k][q];
-                        }
-                        const int idx = zo * HW + gy * W + gx;
-                        float ux = 0.f, uy = 0.f, uz = 0.f;
-                        if (u0) { ux = u0[idx]; uy = u1[idx]; uz = u2[idx]; }
-                        const Tri t = trilinear<PAD, true>(M, D, H, W, gx, gy, zo, ux, uy, uz);
-                        const float gm = ((F[idx] - sF) * ba - (t.v - sM) * bc + be) * inv;
-                        a.gu[idx] = gm * t.dx;
-                        a.gu[(size_t)D * HW + idx] = gm * t.dy;
-                        a.gu[2 * (size_t)D * HW + idx] = gm * t.dz;
-                    }
+                    const float gm = (rF[0][so] * ba - rM[0][so] * bc + be) * inv;
+                    const size_t idx = (size_t)zo * HW + (size_t)gy * W + gx;
+                    a.gu[idx] = gm * rG[0][so];
+                    a.gu[N + idx] = gm * rG[1][so];
+                    a.gu[2 * N + idx] = gm * rG[2][so];
                 }
             }
         }
