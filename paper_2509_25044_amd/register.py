@@ -1,0 +1,187 @@
+"""Deformable registration driver: multi-scale pyramid, fused loss + adjoint,
+per-voxel Adam on the displacement, checkpoint/resume.
+
+The loop is the paper's registration iteration without the optional
+smoothing steps (Sec. "Grid Parallel" keeps optimiser states m1, m2 per
+voxel of the displacement; the experiments run per-scale iteration lists on
+image pyramids).  Every iteration is two library calls on the current HIP
+stream -- the fused loss+adjoint kernel and the Adam kernel -- and the loss
+of each iteration is written into a device buffer, so the loop never waits
+on the host.
+
+Pyramid: level factors f (e.g. 0.25, 0.5, 1.0) give shapes round(f * shape);
+images are resampled with the library's corner-aligned trilinear resize;
+the displacement moves to the next level by the same resize with each
+channel scaled by that axis's (n_fine - 1)/(n_coarse - 1); Adam state starts
+fresh on each level.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import ops
+
+
+@dataclasses.dataclass
+class RegConfig:
+    loss: str = "lncc"                  # "lncc" or "mi"
+    window: int = 5
+    eps: float = 1e-5
+    ants: bool = False
+    bins: int = 32
+    levels: Tuple[float, ...] = (1.0,)
+    iters: Tuple[int, ...] = (50,)       # per level (one value is used for every level)
+    lr: float = 0.1
+    betas: Tuple[float, float] = (0.9, 0.999)
+    adam_eps: float = 1e-8
+    pad: str = "border"
+    roi: Optional[tuple] = None          # full-resolution ROI; coarser levels use the full array
+
+
+def level_shapes(shape: Sequence[int], levels: Sequence[float]) -> List[Tuple[int, int, int]]:
+    out = []
+    for f in levels:
+        out.append(tuple(max(1, int(round(s * f))) for s in shape))
+    return out
+
+
+def axis_scales(src: Sequence[int], dst: Sequence[int]) -> Tuple[float, float, float]:
+    """Displacement scale per channel (x, y, z) when resampling src -> dst with corner alignment."""
+    def f(a, b):
+        return (b - 1) / (a - 1) if a > 1 else 1.0
+    D0, H0, W0 = src
+    D1, H1, W1 = dst
+    return f(W0, W1), f(H0, H1), f(D0, D1)
+
+
+def resample_disp(u: torch.Tensor, shape: Sequence[int]) -> torch.Tensor:
+    """Move a displacement [3, D, H, W] (voxel units) to another grid."""
+    out = torch.empty((3,) + tuple(shape), dtype=torch.float32, device=u.device)
+    sx, sy, sz = axis_scales(u.shape[1:], shape)
+    for c, s in enumerate((sx, sy, sz)):
+        ops.resample(u[c], shape, value_scale=s, out=out[c])
+    return out
+
+
+@dataclasses.dataclass
+class RegState:
+    """Everything needed to resume a registration exactly."""
+    level: int
+    step: int                 # Adam steps done on this level
+    u: torch.Tensor
+    m: torch.Tensor
+    v: torch.Tensor
+    losses: List[torch.Tensor]
+
+    def save(self, path: str):
+        torch.save({"level": self.level, "step": self.step, "u": self.u.cpu(), "m": self.m.cpu(),
+                    "v": self.v.cpu(), "losses": [l.cpu() for l in self.losses]}, path)
+
+    @staticmethod
+    def load(path: str, device) -> "RegState":
+        d = torch.load(path, map_location="cpu", weights_only=True)
+        return RegState(d["level"], d["step"], d["u"].to(device), d["m"].to(device), d["v"].to(device),
+                        [l.to(device) for l in d["losses"]])
+
+
+class Registration:
+    """Plain deformable registration of F to M (u such that M(x + u) ~ F)."""
+
+    def __init__(self, F: torch.Tensor, M: torch.Tensor, cfg: RegConfig):
+        if cfg.loss not in ("lncc", "mi"):
+            raise ValueError("loss must be 'lncc' or 'mi'")
+        self.cfg = cfg
+        self.shapes = level_shapes(F.shape, cfg.levels)
+        self.F = []
+        self.M = []
+        for shp in self.shapes:
+            if tuple(shp) == tuple(F.shape):
+                self.F.append(F)
+                self.M.append(M)
+            else:
+                self.F.append(ops.resample(F, shp))
+                self.M.append(ops.resample(M, shp))
+
+    def iters(self, level: int) -> int:
+        it = self.cfg.iters
+        return it[level] if len(it) > 1 else it[0]
+
+    def init_state(self, u0: Optional[torch.Tensor] = None, level: int = 0) -> RegState:
+        shp = self.shapes[level]
+        dev = self.F[level].device
+        if u0 is None:
+            u = torch.zeros((3,) + tuple(shp), dtype=torch.float32, device=dev)
+        elif tuple(u0.shape[1:]) != tuple(shp):
+            u = resample_disp(u0.contiguous(), shp)
+        else:
+            u = u0.clone().contiguous()
+        return RegState(level, 0, u, torch.zeros_like(u), torch.zeros_like(u), [])
+
+    def _roi(self, level):
+        return self.cfg.roi if tuple(self.shapes[level]) == tuple(self.F[-1].shape) else None
+
+    def step(self, st: RegState, loss_out: torch.Tensor, grad: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """One iteration: fused loss + adjoint, then Adam.  loss_out: device float [1]."""
+        c = self.cfg
+        lv = st.level
+        F, M = self.F[lv], self.M[lv]
+        if c.loss == "lncc":
+            grad, _ = ops.warp_lncc_bwd(F, M, st.u, window=c.window, eps=c.eps, ants=c.ants, pad=c.pad,
+                                        roi=self._roi(lv), grad_u=grad, loss=loss_out)
+        else:
+            _, state = ops.warp_mi_fwd(F, M, st.u, bins=c.bins, pad=c.pad, roi=self._roi(lv), loss=loss_out)
+            grad = ops.warp_mi_bwd(F, M, st.u, state, bins=c.bins, pad=c.pad, roi=self._roi(lv), grad_u=grad)
+        st.step += 1
+        ops.adam_step(st.u, grad, st.m, st.v, lr=c.lr, beta1=c.betas[0], beta2=c.betas[1], eps=c.adam_eps,
+                      step=st.step)
+        return grad
+
+    def evaluate(self, u: torch.Tensor, level: int = -1) -> float:
+        """Loss of the current displacement at a level (host sync)."""
+        c = self.cfg
+        lv = level % len(self.shapes)
+        if c.loss == "lncc":
+            l = ops.warp_lncc_fwd(self.F[lv], self.M[lv], u, window=c.window, eps=c.eps, pad=c.pad,
+                                  roi=self._roi(lv))
+        else:
+            l, _ = ops.warp_mi_fwd(self.F[lv], self.M[lv], u, bins=c.bins, pad=c.pad, roi=self._roi(lv))
+        return float(l.item())
+
+    def run(self, u0: Optional[torch.Tensor] = None, state: Optional[RegState] = None,
+            stop_after: Optional[int] = None,
+            until: Optional[Callable[[int, int, torch.Tensor], bool]] = None) -> RegState:
+        """Run (or resume) the pyramid.  stop_after: total iterations to run in
+        this call (for checkpointing); until(level, step, loss_dev) -> True
+        stops early (it may synchronise)."""
+        st = state if state is not None else self.init_state(u0, 0)
+        done = 0
+        while True:
+            lv = st.level
+            n = self.iters(lv)
+            hist = torch.empty(n, dtype=torch.float32, device=st.u.device)
+            if len(st.losses) > lv:  # resuming inside this level
+                hist[: st.step] = st.losses[lv][: st.step]
+                st.losses[lv] = hist
+            else:
+                st.losses.append(hist)
+            grad = None
+            while st.step < n:
+                if stop_after is not None and done >= stop_after:
+                    return st
+                grad = self.step(st, hist[st.step: st.step + 1], grad)
+                done += 1
+                if until is not None and until(lv, st.step, hist[st.step - 1: st.step]):
+                    return st
+            if lv + 1 >= len(self.shapes):
+                return st
+            nxt = self.init_state(st.u, lv + 1)
+            nxt.losses = st.losses
+            st = nxt
+
+
+def register(F: torch.Tensor, M: torch.Tensor, cfg: RegConfig, u0: Optional[torch.Tensor] = None) -> RegState:
+    """Register F and M; returns the final state (u at full resolution, losses per level)."""
+    return Registration(F, M, cfg).run(u0=u0)
