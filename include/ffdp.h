@@ -162,6 +162,79 @@ int ffdp_warp_mi_bwd(const float* F, const float* M, const float* u, const ffdp_
 int ffdp_adam_step(float* x, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
                    float eps, int64_t step, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Warm-start network (3D U-Net) kernels.  BF16 operands on MFMA with FP32
+ * accumulation.  Activations are channels-last bf16 [N][D][H][W][C]
+ * (uint16_t holding bfloat16 bits).  All convolutions are 3x3x3 with zero
+ * padding 1 and stride 1 or 2; output size Do = (Di - 1)/stride + 1 per axis.
+ * The convolution input may be the channel concatenation of part a
+ * (channels [0, Ca)) and part b (channels [Ca, Ca + Cb)); with ups = 1 part a
+ * is stored at half resolution (Di/2, Hi/2, Wi/2) and upsampled by nearest
+ * x2 on the fly.  Channel counts Ca, Cb, Cout are multiples of 4;
+ * Ca + Cb <= 192, Cout <= 128.  Pointers to bf16 data are 8-byte aligned,
+ * fp32 gradient tensors 16-byte aligned.
+ * ------------------------------------------------------------------------ */
+typedef struct ffdp_conv_geom {
+    int32_t N;
+    int32_t Di, Hi, Wi; /* convolution input size (after upsampling) */
+    int32_t Ca, Cb;     /* channels of part a and part b (0: no part b) */
+    int32_t Cout;
+    int32_t stride;     /* 1 or 2 */
+    int32_t ups;        /* 1: part a is upsampled x2 (Di, Hi, Wi even) */
+} ffdp_conv_geom;
+
+/* Forward: y[o][co] = act(bias[co] + sum_{t, ci} X[o*stride + t - 1][ci] * w[co][t][ci]).
+ * w bf16 [Cout][27][Cin] (t = (dz*3 + dy)*3 + dx); bias fp32 [Cout] or NULL;
+ * act 1 = LeakyReLU with `slope`, 0 = identity.  y_bf16 and/or y_f32
+ * [N][Do][Ho][Wo][Cout] (at least one non-NULL). */
+int ffdp_conv3d_fwd(const uint16_t* xa, const uint16_t* xb, const uint16_t* w, const float* bias,
+                    const ffdp_conv_geom* g, int32_t act, float slope, uint16_t* y_bf16, float* y_f32, void* stream);
+
+/* Backward to the input: dx[i][ci] (+)= sum_{t, co} P[(i + 1 - t)/stride][co] * w[co][t][ci]
+ * (terms with a non-integer or out-of-range output index are absent), where
+ * P = bf16(dy * act'(y)) with act'(y) = 1 where y > 0 else slope (y = the
+ * layer's bf16 output, or NULL for no activation).  wt is the weight in
+ * [Cin][27][Cout] order (ffdp_conv3d_weight_prep).  dy fp32
+ * [N][Do][Ho][Wo][Cout]; dx fp32 [N][Di][Hi][Wi][Ca + Cb] over the
+ * concatenated fine-resolution input (ffdp_concat_grad_split separates it);
+ * accumulate 1 adds to dx. */
+int ffdp_conv3d_bwd_data(const float* dy, const uint16_t* y, float slope, const uint16_t* wt,
+                         const ffdp_conv_geom* g, float* dx, int32_t accumulate, void* stream);
+
+/* Backward to the weights: dw[co][t][ci] = sum_o P[o][co] X[o*stride + t - 1][ci]
+ * and db[co] = sum_o P[o][co] (db may be NULL), fp32, overwritten; the sums
+ * over output voxels run in chunks whose partials (caller workspace) are
+ * added in a fixed order. */
+size_t ffdp_conv3d_bwd_weight_workspace_bytes(const ffdp_conv_geom* g);
+int ffdp_conv3d_bwd_weight(const uint16_t* xa, const uint16_t* xb, const float* dy, const uint16_t* y, float slope,
+                           const ffdp_conv_geom* g, float* dw, float* db, void* ws, size_t ws_bytes, void* stream);
+
+/* fp32 master weights [Cout][27][Cin] -> bf16 copy (w_bf16, nullable) and
+ * bf16 transpose [Cin][27][Cout] (wt_bf16, nullable), round to nearest even. */
+int ffdp_conv3d_weight_prep(const float* w, int32_t Cout, int32_t Cin, uint16_t* w_bf16, uint16_t* wt_bf16,
+                            void* stream);
+
+/* Network input: (F, M) fp32 volumes of nvox voxels each (batch included)
+ * -> bf16 [nvox][4] = (F, M, 0, 0). */
+int ffdp_unet_pack_pair(const float* F, const float* M, int64_t nvox, uint16_t* x, void* stream);
+
+/* Split dx of a concatenated input (layout of ffdp_conv3d_bwd_data) into the
+ * skip part dxb [N][Di][Hi][Wi][Cb] and part a, summed over each 2x2x2 block
+ * when ups = 1 (the adjoint of nearest upsampling) into dxa
+ * [N][Di/2][Hi/2][Wi/2][Ca]; acc_a / acc_b = 1 add instead of overwrite. */
+int ffdp_concat_grad_split(const float* dxcat, const ffdp_conv_geom* g, float* dxa, float* dxb, int32_t acc_a,
+                           int32_t acc_b, void* stream);
+
+/* Mean squared error between the first 3 channels of pred [N][nvox][Cp] and
+ * target [N][3][nvox]: *loss = mean over N*3*nvox; dpred (nullable) receives
+ * the gradient (channels >= 3 zero).  ws: ffdp_mse_workspace_bytes(). */
+size_t ffdp_mse_workspace_bytes(void);
+int ffdp_mse_disp(const float* pred, int32_t Cp, const float* target, int64_t nvox, int32_t N, float* dpred,
+                  float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* pred [N][nvox][Cp] -> displacement [N][3][nvox] (channels 0..2). */
+int ffdp_unpack_disp(const float* pred, int32_t Cp, int64_t nvox, int32_t N, float* u, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

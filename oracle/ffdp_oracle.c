@@ -520,3 +520,109 @@ int orc_resample(const float* src, i64 sD, i64 sH, i64 sW, double* dst, i64 dD, 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* O6. 3x3x3 convolution of the warm-start network (zero padding 1, stride   */
+/* s), in double on operands the caller has already rounded to bf16.  The    */
+/* input X is the channel concatenation of part a (nearest x2 upsampled when */
+/* ups = 1) and part b; layouts are channels-last [N][D][H][W][C]; the       */
+/* weight is [Cout][27][Cin] with tap t = (dz*3 + dy)*3 + dx.                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    i64 N, Di, Hi, Wi, Do, Ho, Wo, Ca, Cb, Cout, s, ups;
+} cgeo;
+
+static cgeo mkgeo(i64 N, i64 Di, i64 Hi, i64 Wi, i64 Ca, i64 Cb, i64 Cout, i64 s, i64 ups)
+{
+    cgeo g = {N, Di, Hi, Wi, (Di - 1) / s + 1, (Hi - 1) / s + 1, (Wi - 1) / s + 1, Ca, Cb, Cout, s, ups};
+    return g;
+}
+
+/* X[n][z][y][x][c] by its definition */
+static double xin(const cgeo* g, const double* xa, const double* xb, i64 n, i64 z, i64 y, i64 x, i64 c)
+{
+    if (c < g->Ca) {
+        if (g->ups) {
+            i64 Da = g->Di / 2, Ha = g->Hi / 2, Wa = g->Wi / 2;
+            return xa[((((n * Da) + z / 2) * Ha + y / 2) * Wa + x / 2) * g->Ca + c];
+        }
+        return xa[((((n * g->Di) + z) * g->Hi + y) * g->Wi + x) * g->Ca + c];
+    }
+    return xb[((((n * g->Di) + z) * g->Hi + y) * g->Wi + x) * g->Cb + (c - g->Ca)];
+}
+
+int orc_conv3d_fwd(const double* xa, const double* xb, const double* w, const double* bias, i64 N, i64 Di, i64 Hi,
+                   i64 Wi, i64 Ca, i64 Cb, i64 Cout, i64 s, i64 ups, int act, double slope, double* y)
+{
+    cgeo g = mkgeo(N, Di, Hi, Wi, Ca, Cb, Cout, s, ups);
+    const i64 Cin = Ca + Cb;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (i64 n = 0; n < N; ++n)
+        for (i64 zo = 0; zo < g.Do; ++zo)
+            for (i64 yo = 0; yo < g.Ho; ++yo)
+                for (i64 xo = 0; xo < g.Wo; ++xo)
+                    for (i64 co = 0; co < Cout; ++co) {
+                        double acc = bias ? bias[co] : 0.0;
+                        for (i64 t = 0; t < 27; ++t) {
+                            i64 zi = zo * s + t / 9 - 1, yi = yo * s + (t / 3) % 3 - 1, xi = xo * s + t % 3 - 1;
+                            if (zi < 0 || zi >= Di || yi < 0 || yi >= Hi || xi < 0 || xi >= Wi) continue;
+                            for (i64 ci = 0; ci < Cin; ++ci)
+                                acc += xin(&g, xa, xb, n, zi, yi, xi, ci) * w[(co * 27 + t) * Cin + ci];
+                        }
+                        if (act && acc <= 0.0) acc *= slope;
+                        y[((((n * g.Do) + zo) * g.Ho + yo) * g.Wo + xo) * Cout + co] = acc;
+                    }
+    return 0;
+}
+
+/* Adjoint of the convolution with respect to X (scatter form): every output
+ * voxel o and tap t send P[o][co] w[co][t][ci] to input voxel o*s + t - 1.
+ * dx is over the concatenated fine-resolution input, [N][Di][Hi][Wi][Ca+Cb]. */
+int orc_conv3d_bwd_data(const double* P, const double* w, i64 N, i64 Di, i64 Hi, i64 Wi, i64 Ca, i64 Cb, i64 Cout,
+                        i64 s, double* dx)
+{
+    cgeo g = mkgeo(N, Di, Hi, Wi, Ca, Cb, Cout, s, 0);
+    const i64 Cin = Ca + Cb;
+    memset(dx, 0, sizeof(double) * (size_t)(N * Di * Hi * Wi * Cin));
+    for (i64 n = 0; n < N; ++n)
+        for (i64 zo = 0; zo < g.Do; ++zo)
+            for (i64 yo = 0; yo < g.Ho; ++yo)
+                for (i64 xo = 0; xo < g.Wo; ++xo)
+                    for (i64 t = 0; t < 27; ++t) {
+                        i64 zi = zo * s + t / 9 - 1, yi = yo * s + (t / 3) % 3 - 1, xi = xo * s + t % 3 - 1;
+                        if (zi < 0 || zi >= Di || yi < 0 || yi >= Hi || xi < 0 || xi >= Wi) continue;
+                        double* d = dx + ((((n * Di) + zi) * Hi + yi) * Wi + xi) * Cin;
+                        const double* p = P + ((((n * g.Do) + zo) * g.Ho + yo) * g.Wo + xo) * Cout;
+                        for (i64 co = 0; co < Cout; ++co)
+                            for (i64 ci = 0; ci < Cin; ++ci) d[ci] += p[co] * w[(co * 27 + t) * Cin + ci];
+                    }
+    return 0;
+}
+
+/* dW[co][t][ci] = sum_o P[o][co] X[o*s + t - 1][ci];  db[co] = sum_o P[o][co] */
+int orc_conv3d_bwd_weight(const double* xa, const double* xb, const double* P, i64 N, i64 Di, i64 Hi, i64 Wi, i64 Ca,
+                          i64 Cb, i64 Cout, i64 s, i64 ups, double* dw, double* db)
+{
+    cgeo g = mkgeo(N, Di, Hi, Wi, Ca, Cb, Cout, s, ups);
+    const i64 Cin = Ca + Cb;
+#pragma omp parallel for schedule(static)
+    for (i64 co = 0; co < Cout; ++co) {
+        for (i64 q = 0; q < 27 * Cin; ++q) dw[co * 27 * Cin + q] = 0.0;
+        double b = 0.0;
+        for (i64 n = 0; n < N; ++n)
+            for (i64 zo = 0; zo < g.Do; ++zo)
+                for (i64 yo = 0; yo < g.Ho; ++yo)
+                    for (i64 xo = 0; xo < g.Wo; ++xo) {
+                        double p = P[((((n * g.Do) + zo) * g.Ho + yo) * g.Wo + xo) * Cout + co];
+                        b += p;
+                        for (i64 t = 0; t < 27; ++t) {
+                            i64 zi = zo * s + t / 9 - 1, yi = yo * s + (t / 3) % 3 - 1, xi = xo * s + t % 3 - 1;
+                            if (zi < 0 || zi >= Di || yi < 0 || yi >= Hi || xi < 0 || xi >= Wi) continue;
+                            for (i64 ci = 0; ci < Cin; ++ci)
+                                dw[(co * 27 + t) * Cin + ci] += p * xin(&g, xa, xb, n, zi, yi, xi, ci);
+                        }
+                    }
+        if (db) db[co] = b;
+    }
+    return 0;
+}

@@ -40,7 +40,11 @@ def load():
     lib.orc_parzen.argtypes = [C.c_double, C.c_int, C.c_int, vp, vp]
     lib.orc_adam.argtypes = [vp, vp, vp, vp, _i64, C.c_double, C.c_double, C.c_double, C.c_double, _i64]
     lib.orc_resample.argtypes = [vp, _i64, _i64, _i64, vp, _i64, _i64, _i64, C.c_int, C.c_double]
-    for f in ("orc_warp", "orc_lncc", "orc_lncc_grad_u_at", "orc_mi", "orc_parzen", "orc_adam", "orc_resample"):
+    lib.orc_conv3d_fwd.argtypes = [vp, vp, vp, vp] + [_i64] * 9 + [C.c_int, C.c_double, vp]
+    lib.orc_conv3d_bwd_data.argtypes = [vp, vp] + [_i64] * 8 + [vp]
+    lib.orc_conv3d_bwd_weight.argtypes = [vp, vp, vp] + [_i64] * 9 + [vp, vp]
+    for f in ("orc_warp", "orc_lncc", "orc_lncc_grad_u_at", "orc_mi", "orc_parzen", "orc_adam", "orc_resample",
+              "orc_conv3d_fwd", "orc_conv3d_bwd_data", "orc_conv3d_bwd_weight"):
         getattr(lib, f).restype = C.c_int
     _LIB = lib
     return lib
@@ -156,3 +160,42 @@ def resample(src, dst_shape: Sequence[int], value_scale: float = 1.0):
     out = np.empty((Cn, dD, dH, dW), np.float64)
     lib.orc_resample(_ptr(src), sD, sH, sW, _ptr(out), dD, dH, dW, Cn, value_scale)
     return out[0] if squeeze else out
+
+
+def _f64(a):
+    if a is None:
+        return None
+    if hasattr(a, "detach"):
+        a = a.detach().cpu().double().numpy()
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def conv3d_fwd(xa, xb, w, bias, N, Di, Hi, Wi, Ca, Cb, Cout, stride=1, ups=False, act=False, slope=0.2):
+    """Direct 3x3x3 convolution (channels-last) -> float64 [N][Do][Ho][Wo][Cout]."""
+    lib = load()
+    xa, xb, w, bias = _f64(xa), _f64(xb), _f64(w), _f64(bias)
+    Do, Ho, Wo = (Di - 1) // stride + 1, (Hi - 1) // stride + 1, (Wi - 1) // stride + 1
+    y = np.empty((N, Do, Ho, Wo, Cout), np.float64)
+    lib.orc_conv3d_fwd(_ptr(xa), _ptr(xb), _ptr(w), _ptr(bias), N, Di, Hi, Wi, Ca, Cb, Cout, stride, int(ups),
+                       int(act), slope, _ptr(y))
+    return y
+
+
+def conv3d_bwd_data(P, w, N, Di, Hi, Wi, Ca, Cb, Cout, stride=1):
+    """Adjoint w.r.t. the (concatenated, fine-resolution) input -> [N][Di][Hi][Wi][Ca+Cb]."""
+    lib = load()
+    P, w = _f64(P), _f64(w)
+    dx = np.empty((N, Di, Hi, Wi, Ca + Cb), np.float64)
+    lib.orc_conv3d_bwd_data(_ptr(P), _ptr(w), N, Di, Hi, Wi, Ca, Cb, Cout, stride, _ptr(dx))
+    return dx
+
+
+def conv3d_bwd_weight(xa, xb, P, N, Di, Hi, Wi, Ca, Cb, Cout, stride=1, ups=False):
+    """(dW [Cout][27][Cin], db [Cout]) in float64."""
+    lib = load()
+    xa, xb, P = _f64(xa), _f64(xb), _f64(P)
+    dw = np.empty((Cout, 27, Ca + Cb), np.float64)
+    db = np.empty(Cout, np.float64)
+    lib.orc_conv3d_bwd_weight(_ptr(xa), _ptr(xb), _ptr(P), N, Di, Hi, Wi, Ca, Cb, Cout, stride, int(ups),
+                              _ptr(dw), _ptr(db))
+    return dw, db

@@ -30,6 +30,11 @@ class MiParams(C.Structure):
     _fields_ = [("bins", C.c_int32), ("hard_bins", C.c_int32), ("pad_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
+class ConvGeom(C.Structure):
+    _fields_ = [("N", C.c_int32), ("Di", C.c_int32), ("Hi", C.c_int32), ("Wi", C.c_int32), ("Ca", C.c_int32),
+                ("Cb", C.c_int32), ("Cout", C.c_int32), ("stride", C.c_int32), ("ups", C.c_int32)]
+
+
 class FfdpError(RuntimeError):
     def __init__(self, fn: str, code: int, text: str):
         super().__init__(f"{fn} failed with status {code} ({STATUS.get(code, '?')}): {text}")
@@ -50,6 +55,7 @@ def lib():
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, f32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
     gp, lp, mp = C.POINTER(Grid), C.POINTER(LnccParams), C.POINTER(MiParams)
+    cg = C.POINTER(ConvGeom)
     sig = {
         "ffdp_version": ([], C.c_int),
         "ffdp_status_string": ([C.c_int], C.c_char_p),
@@ -64,6 +70,16 @@ def lib():
         "ffdp_warp_mi_fwd": ([vp, vp, vp, gp, mp, vp, vp, vp, sz, vp], C.c_int),
         "ffdp_warp_mi_bwd": ([vp, vp, vp, gp, mp, vp, vp, vp, vp, sz, vp], C.c_int),
         "ffdp_adam_step": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i64, vp], C.c_int),
+        "ffdp_conv3d_fwd": ([vp, vp, vp, vp, cg, i32, f32, vp, vp, vp], C.c_int),
+        "ffdp_conv3d_bwd_data": ([vp, vp, f32, vp, cg, vp, i32, vp], C.c_int),
+        "ffdp_conv3d_bwd_weight_workspace_bytes": ([cg], sz),
+        "ffdp_conv3d_bwd_weight": ([vp, vp, vp, vp, f32, cg, vp, vp, vp, sz, vp], C.c_int),
+        "ffdp_conv3d_weight_prep": ([vp, i32, i32, vp, vp, vp], C.c_int),
+        "ffdp_unet_pack_pair": ([vp, vp, i64, vp, vp], C.c_int),
+        "ffdp_concat_grad_split": ([vp, cg, vp, vp, i32, i32, vp], C.c_int),
+        "ffdp_mse_workspace_bytes": ([], sz),
+        "ffdp_mse_disp": ([vp, i32, vp, i64, i32, vp, vp, vp, sz, vp], C.c_int),
+        "ffdp_unpack_disp": ([vp, i32, i64, i32, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -328,3 +328,161 @@ int ffdp_adam_step(float* x, const float* g, float* m, float* v, int64_t n, floa
 }
 
 }  // extern "C"
+
+namespace {
+
+bool misaligned_n(const void* p, unsigned n) { return (((uintptr_t)p) & (n - 1)) != 0; }
+
+int conv_geom(const ffdp_conv_geom* cg, ConvGeom& g, bool need_b_ptr_ok)
+{
+    if (!cg) return fail(FFDP_ERR_NULL, "conv geometry is NULL");
+    if (cg->N < 1 || cg->Di < 1 || cg->Hi < 1 || cg->Wi < 1) return fail(FFDP_ERR_SHAPE, "N, Di, Hi, Wi must be >= 1");
+    if (cg->stride != 1 && cg->stride != 2) return fail(FFDP_ERR_PARAM, "stride must be 1 or 2");
+    if (cg->ups != 0 && cg->ups != 1) return fail(FFDP_ERR_PARAM, "ups must be 0 or 1");
+    if (cg->Ca < 4 || cg->Ca % 4 || cg->Cb < 0 || cg->Cb % 4 || cg->Cout < 4 || cg->Cout % 4)
+        return fail(FFDP_ERR_PARAM, "Ca >= 4, Cb >= 0, Cout >= 4, all multiples of 4 required");
+    if (cg->Ca + cg->Cb > 192 || cg->Cout > 128) return fail(FFDP_ERR_PARAM, "Ca + Cb <= 192 and Cout <= 128 required");
+    if (cg->ups && ((cg->Di | cg->Hi | cg->Wi) & 1)) return fail(FFDP_ERR_SHAPE, "ups = 1 needs even Di, Hi, Wi");
+    (void)need_b_ptr_ok;
+    g.N = cg->N; g.Di = cg->Di; g.Hi = cg->Hi; g.Wi = cg->Wi;
+    g.stride = cg->stride; g.ups = cg->ups;
+    g.Do = (g.Di - 1) / g.stride + 1; g.Ho = (g.Hi - 1) / g.stride + 1; g.Wo = (g.Wi - 1) / g.stride + 1;
+    g.Ca = cg->Ca; g.Cb = cg->Cb; g.Cout = cg->Cout;
+    return FFDP_OK;
+}
+
+int bf16_ptr(const void* p, const char* name, bool required)
+{
+    if (!p) return required ? fail(FFDP_ERR_NULL, "pointer '%s' is NULL", name) : FFDP_OK;
+    if (misaligned_n(p, 8)) return fail(FFDP_ERR_ALIGN, "pointer '%s' must be 8-byte aligned", name);
+    return FFDP_OK;
+}
+
+int f32_ptr(const void* p, const char* name, bool required, unsigned align)
+{
+    if (!p) return required ? fail(FFDP_ERR_NULL, "pointer '%s' is NULL", name) : FFDP_OK;
+    if (misaligned_n(p, align)) return fail(FFDP_ERR_ALIGN, "pointer '%s' must be %u-byte aligned", name, align);
+    return FFDP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ffdp_conv3d_fwd(const uint16_t* xa, const uint16_t* xb, const uint16_t* w, const float* bias,
+                    const ffdp_conv_geom* cg, int32_t act, float slope, uint16_t* y_bf16, float* y_f32, void* stream)
+{
+    ConvGeom g;
+    int s = conv_geom(cg, g, true);
+    if (s) return s;
+    if ((s = bf16_ptr(xa, "xa", true)) || (s = bf16_ptr(xb, "xb", g.Cb > 0)) || (s = bf16_ptr(w, "w", true)) ||
+        (s = f32_ptr(bias, "bias", false, 4)) || (s = bf16_ptr(y_bf16, "y_bf16", false)) ||
+        (s = f32_ptr(y_f32, "y_f32", false, 4)))
+        return s;
+    if (!y_bf16 && !y_f32) return fail(FFDP_ERR_NULL, "y_bf16 and y_f32 are both NULL");
+    if (act != 0 && act != 1) return fail(FFDP_ERR_PARAM, "act must be 0 or 1");
+    return hip_status(conv_fwd_launch(g, (const unsigned short*)xa, (const unsigned short*)xb,
+                                      (const unsigned short*)w, bias, act, slope, (unsigned short*)y_bf16, y_f32,
+                                      (hipStream_t)stream),
+                      "ffdp_conv3d_fwd");
+}
+
+int ffdp_conv3d_bwd_data(const float* dy, const uint16_t* y, float slope, const uint16_t* wt,
+                         const ffdp_conv_geom* cg, float* dx, int32_t accumulate, void* stream)
+{
+    ConvGeom g;
+    int s = conv_geom(cg, g, true);
+    if (s) return s;
+    if ((s = f32_ptr(dy, "dy", true, 16)) || (s = bf16_ptr(y, "y", false)) || (s = bf16_ptr(wt, "wt", true)) ||
+        (s = f32_ptr(dx, "dx", true, 4)))
+        return s;
+    if (accumulate != 0 && accumulate != 1) return fail(FFDP_ERR_PARAM, "accumulate must be 0 or 1");
+    return hip_status(conv_bwd_data_launch(g, dy, (const unsigned short*)y, slope, (const unsigned short*)wt, dx,
+                                           accumulate, (hipStream_t)stream),
+                      "ffdp_conv3d_bwd_data");
+}
+
+size_t ffdp_conv3d_bwd_weight_workspace_bytes(const ffdp_conv_geom* cg)
+{
+    ConvGeom g;
+    if (conv_geom(cg, g, true)) return 0;
+    return (size_t)conv_wgrad_plan(g).part_floats * sizeof(float);
+}
+
+int ffdp_conv3d_bwd_weight(const uint16_t* xa, const uint16_t* xb, const float* dy, const uint16_t* y, float slope,
+                           const ffdp_conv_geom* cg, float* dw, float* db, void* ws, size_t ws_bytes, void* stream)
+{
+    ConvGeom g;
+    int s = conv_geom(cg, g, true);
+    if (s) return s;
+    if ((s = bf16_ptr(xa, "xa", true)) || (s = bf16_ptr(xb, "xb", g.Cb > 0)) || (s = f32_ptr(dy, "dy", true, 4)) ||
+        (s = bf16_ptr(y, "y", false)) || (s = f32_ptr(dw, "dw", true, 4)) || (s = f32_ptr(db, "db", false, 4)))
+        return s;
+    const size_t need = (size_t)conv_wgrad_plan(g).part_floats * sizeof(float);
+    if (!ws || ws_bytes < need) return fail(FFDP_ERR_WORKSPACE, "workspace of %zu bytes required (got %zu)", need, ws_bytes);
+    if (misaligned_n(ws, 4)) return fail(FFDP_ERR_ALIGN, "workspace must be 4-byte aligned");
+    return hip_status(conv_bwd_weight_launch(g, (const unsigned short*)xa, (const unsigned short*)xb, dy,
+                                             (const unsigned short*)y, slope, dw, db, (float*)ws, (hipStream_t)stream),
+                      "ffdp_conv3d_bwd_weight");
+}
+
+int ffdp_conv3d_weight_prep(const float* w, int32_t Cout, int32_t Cin, uint16_t* w_bf16, uint16_t* wt_bf16,
+                            void* stream)
+{
+    int s;
+    if (Cout < 1 || Cin < 1 || Cout > 4096 || Cin > 4096) return fail(FFDP_ERR_SHAPE, "Cout, Cin must be in [1, 4096]");
+    if ((s = f32_ptr(w, "w", true, 4)) || (s = bf16_ptr(w_bf16, "w_bf16", false)) ||
+        (s = bf16_ptr(wt_bf16, "wt_bf16", false)))
+        return s;
+    return hip_status(weight_prep_launch(w, Cout, Cin, (unsigned short*)w_bf16, (unsigned short*)wt_bf16,
+                                         (hipStream_t)stream),
+                      "ffdp_conv3d_weight_prep");
+}
+
+int ffdp_unet_pack_pair(const float* F, const float* M, int64_t nvox, uint16_t* x, void* stream)
+{
+    int s;
+    if (nvox < 1) return fail(FFDP_ERR_SHAPE, "nvox must be >= 1");
+    if ((s = f32_ptr(F, "F", true, 4)) || (s = f32_ptr(M, "M", true, 4)) || (s = bf16_ptr(x, "x", true))) return s;
+    return hip_status(pack_pair_launch(F, M, nvox, (unsigned short*)x, (hipStream_t)stream), "ffdp_unet_pack_pair");
+}
+
+int ffdp_concat_grad_split(const float* dxcat, const ffdp_conv_geom* cg, float* dxa, float* dxb, int32_t acc_a,
+                           int32_t acc_b, void* stream)
+{
+    ConvGeom g;
+    int s = conv_geom(cg, g, true);
+    if (s) return s;
+    if (!g.ups) return fail(FFDP_ERR_PARAM, "ffdp_concat_grad_split needs ups = 1");
+    if ((s = f32_ptr(dxcat, "dxcat", true, 4)) || (s = f32_ptr(dxa, "dxa", true, 4)) ||
+        (s = f32_ptr(dxb, "dxb", g.Cb > 0, 4)))
+        return s;
+    return hip_status(split_grad_launch(g, dxcat, dxa, dxb, acc_a ? 1 : 0, acc_b ? 1 : 0, (hipStream_t)stream),
+                      "ffdp_concat_grad_split");
+}
+
+size_t ffdp_mse_workspace_bytes(void) { return (size_t)MSE_BLOCKS * sizeof(double); }
+
+int ffdp_mse_disp(const float* pred, int32_t Cp, const float* target, int64_t nvox, int32_t N, float* dpred,
+                  float* loss, void* ws, size_t ws_bytes, void* stream)
+{
+    int s;
+    if (Cp < 3 || N < 1 || nvox < 1) return fail(FFDP_ERR_SHAPE, "Cp >= 3, N >= 1, nvox >= 1 required");
+    if ((s = f32_ptr(pred, "pred", true, 4)) || (s = f32_ptr(target, "target", true, 4)) ||
+        (s = f32_ptr(dpred, "dpred", false, 4)) || (s = f32_ptr(loss, "loss", false, 4)))
+        return s;
+    if (!ws || ws_bytes < (size_t)MSE_BLOCKS * sizeof(double) || misaligned_n(ws, 8))
+        return fail(FFDP_ERR_WORKSPACE, "workspace of %zu 8-byte aligned bytes required", (size_t)MSE_BLOCKS * 8);
+    return hip_status(mse_launch(pred, Cp, target, nvox, N, dpred, (double*)ws, MSE_BLOCKS, loss, (hipStream_t)stream),
+                      "ffdp_mse_disp");
+}
+
+int ffdp_unpack_disp(const float* pred, int32_t Cp, int64_t nvox, int32_t N, float* u, void* stream)
+{
+    int s;
+    if (Cp < 3 || N < 1 || nvox < 1) return fail(FFDP_ERR_SHAPE, "Cp >= 3, N >= 1, nvox >= 1 required");
+    if ((s = f32_ptr(pred, "pred", true, 4)) || (s = f32_ptr(u, "u", true, 4))) return s;
+    return hip_status(unpack_disp_launch(pred, Cp, nvox, N, u, (hipStream_t)stream), "ffdp_unpack_disp");
+}
+
+}  // extern "C"

@@ -1,0 +1,622 @@
+// BF16 MFMA implicit-GEMM 3x3x3 convolutions (pad 1, stride 1 or 2) for the
+// warm-start U-Net, gfx950.  FP32 accumulation.
+//
+// Activations are channels-last bf16 [N][D][H][W][C].  A convolution input
+// may be the channel concatenation of an upsampled coarse tensor xa (nearest
+// x2, channels [0, Ca)) and a skip tensor xb (channels [Ca, Ca+Cb)); the
+// upsampling and the concatenation happen in the operand gather and are never
+// materialised.
+//
+//   forward      y[o][co] = act(b[co] + sum_{t,ci} X[o*s + t - 1][ci] W[co][t][ci])
+//   backward-data dX[i][ci] = sum_{t,co} P[(i + 1 - t)/s][co] W[co][t][ci]
+//   backward-weight dW[co][t][ci] = sum_o P[o][co] X[o*s + t - 1][ci]
+// with P = dL/dy * act'(y) (LeakyReLU: slope where y <= 0), formed in the
+// gather and rounded to bf16 as the MFMA operand.
+//
+// Each 64-lane wave owns one 16-row slab of the GEMM and issues
+// v_mfma_f32_16x16x16_bf16 over 16-wide K chunks.  Operand layout of that
+// instruction (lane l, element e = 0..3):
+//   A[i][k]: i = l % 16, k = 4 (l / 16) + e      B[k][j]: k = 4 (l / 16) + e, j = l % 16
+//   D[i][j]: i = 4 (l / 16) + e, j = l % 16
+// K is ordered (tap, channel) with 4 consecutive channels per lane, so every
+// operand fetch is one 8-byte load of 4 bf16 (channel counts are multiples of 4).
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ffdp {
+
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float f)
+{
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);  // quiet NaN
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);                  // round to nearest even
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ __forceinline__ s4v ld4bf(const unsigned short* p)
+{
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    s4v r;
+    r[0] = (short)(v.x & 0xffffu); r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xffffu); r[3] = (short)(v.y >> 16);
+    return r;
+}
+
+__device__ __forceinline__ s4v pack4(float a, float b, float c, float d)
+{
+    s4v r;
+    r[0] = (short)f2bf(a); r[1] = (short)f2bf(b); r[2] = (short)f2bf(c); r[3] = (short)f2bf(d);
+    return r;
+}
+
+__device__ __forceinline__ float lrelu_d(unsigned short y, float slope) { return bf2f(y) > 0.0f ? 1.0f : slope; }
+
+// element of the virtual input X (concat of upsampled xa and xb) at input
+// voxel (n, z, y, x), channels c..c+3 (c multiple of 4, within one part)
+__device__ __forceinline__ s4v load_x4(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
+                                       int n, int z, int y, int x, int c)
+{
+    if (c < g.Ca) {
+        if (g.ups) {
+            const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
+            const size_t v = (((size_t)n * Da + (z >> 1)) * Ha + (y >> 1)) * Wa + (x >> 1);
+            return ld4bf(xa + v * g.Ca + c);
+        }
+        const size_t v = (((size_t)n * g.Di + z) * g.Hi + y) * g.Wi + x;
+        return ld4bf(xa + v * g.Ca + c);
+    }
+    const size_t v = (((size_t)n * g.Di + z) * g.Hi + y) * g.Wi + x;
+    return ld4bf(xb + v * g.Cb + (c - g.Ca));
+}
+
+// ---------------------------------------------------------------- forward --
+template <int NT>
+__global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
+                                                       const unsigned short* __restrict__ xb,
+                                                       const unsigned short* __restrict__ w,
+                                                       const float* __restrict__ bias, int act, float slope,
+                                                       unsigned short* __restrict__ ybf, float* __restrict__ yf)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Cin = g.Ca + g.Cb;
+    const int K = 27 * Cin;
+    const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
+    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 16;
+    const long long m = m0 + (lane & 15);
+    const bool mvalid = m < M;
+    int n = 0, zo = 0, yo = 0, xo = 0;
+    if (mvalid) {
+        long long q = m;
+        xo = (int)(q % g.Wo); q /= g.Wo;
+        yo = (int)(q % g.Ho); q /= g.Ho;
+        zo = (int)(q % g.Do); n = (int)(q / g.Do);
+    }
+    const int kg = (lane >> 4) * 4;
+    f4v acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const int k = k0 + kg;
+        s4v a = s4v{0, 0, 0, 0};
+        if (mvalid && k < K) {
+            const int t = k / Cin, c = k - t * Cin;
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            const int zi = zo * g.stride + dz - 1, yi = yo * g.stride + dy - 1, xi = xo * g.stride + dx - 1;
+            if ((unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi && (unsigned)xi < (unsigned)g.Wi)
+                a = load_x4(g, xa, xb, n, zi, yi, xi, c);
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int co = j * 16 + (lane & 15);
+            s4v b = s4v{0, 0, 0, 0};
+            if (co < g.Cout && k < K) b = ld4bf(w + (size_t)co * K + k);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = j * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const long long mo = m0 + (lane >> 4) * 4 + e;
+            if (mo < M && co < g.Cout) {
+                float v = acc[j][e] + (bias ? bias[co] : 0.0f);
+                if (act) v = v > 0.0f ? v : v * slope;
+                if (ybf) ybf[mo * g.Cout + co] = f2bf(v);
+                if (yf) yf[mo * g.Cout + co] = v;
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------- backward data --
+// dX over the virtual (concatenated, fine-resolution) input, fp32 [N][Di][Hi][Wi][Cin];
+// accumulate = 1 adds to dX.  wt is the weight in [Cin][27][Cout] order.
+template <int NT>
+__global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const float* __restrict__ dy,
+                                                            const unsigned short* __restrict__ y, float slope,
+                                                            const unsigned short* __restrict__ wt,
+                                                            float* __restrict__ dx, int accumulate)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Cin = g.Ca + g.Cb;
+    const int K = 27 * g.Cout;
+    const long long M = (long long)g.N * g.Di * g.Hi * g.Wi;
+    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 16;
+    const long long m = m0 + (lane & 15);
+    const bool mvalid = m < M;
+    int n = 0, zi = 0, yi = 0, xi = 0;
+    if (mvalid) {
+        long long q = m;
+        xi = (int)(q % g.Wi); q /= g.Wi;
+        yi = (int)(q % g.Hi); q /= g.Hi;
+        zi = (int)(q % g.Di); n = (int)(q / g.Di);
+    }
+    const int kg = (lane >> 4) * 4;
+    f4v acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        const int k = k0 + kg;
+        s4v a = s4v{0, 0, 0, 0};
+        if (mvalid && k < K) {
+            const int t = k / g.Cout, co = k - t * g.Cout;
+            const int dz = t / 9, dyy = (t / 3) % 3, dx_ = t % 3;
+            int oz = zi + 1 - dz, oy = yi + 1 - dyy, ox = xi + 1 - dx_;
+            bool ok = oz >= 0 && oy >= 0 && ox >= 0;
+            if (g.stride == 2) {
+                ok = ok && !(oz & 1) && !(oy & 1) && !(ox & 1);
+                oz >>= 1; oy >>= 1; ox >>= 1;
+            }
+            ok = ok && oz < g.Do && oy < g.Ho && ox < g.Wo;
+            if (ok) {
+                const size_t o = ((((size_t)n * g.Do + oz) * g.Ho + oy) * g.Wo + ox) * g.Cout + co;
+                const float4 d4 = *reinterpret_cast<const float4*>(dy + o);
+                float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
+                if (y) {
+                    s0 = lrelu_d(y[o], slope); s1 = lrelu_d(y[o + 1], slope);
+                    s2 = lrelu_d(y[o + 2], slope); s3 = lrelu_d(y[o + 3], slope);
+                }
+                a = pack4(d4.x * s0, d4.y * s1, d4.z * s2, d4.w * s3);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int ci = j * 16 + (lane & 15);
+            s4v b = s4v{0, 0, 0, 0};
+            if (ci < Cin && k < K) b = ld4bf(wt + (size_t)ci * K + k);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int ci = j * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const long long mo = m0 + (lane >> 4) * 4 + e;
+            if (mo < M && ci < Cin) {
+                float* p = dx + mo * Cin + ci;
+                *p = accumulate ? *p + acc[j][e] : acc[j][e];
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------- backward weight --
+// Block (chunk, tap t): partial dW[co][t][ci] over output voxels
+// [chunk*VC, chunk*VC + VC), written to part[chunk][co][t][ci].  Wave w owns
+// the ci-tiles w, w+4, ... and all co-tiles.
+template <int TM, int TNW>
+__global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
+                                                              const unsigned short* __restrict__ xb,
+                                                              const float* __restrict__ dy,
+                                                              const unsigned short* __restrict__ y, float slope,
+                                                              long long VC, float* __restrict__ part)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Cin = g.Ca + g.Cb;
+    const int t = blockIdx.y;
+    const int dz = t / 9, dyy = (t / 3) % 3, dx_ = t % 3;
+    const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
+    const long long ob = (long long)blockIdx.x * VC;
+    const long long oe = min(M, ob + VC);
+    const int TN = (Cin + 15) / 16;
+    f4v acc[TM][TNW];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TNW; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int kg = (lane >> 4) * 4;
+    for (long long o0 = ob; o0 < oe; o0 += 16) {
+        // this lane's 4 output voxels o0 + kg + e and their shifted input voxels
+        long long iv[4];
+        bool ov[4], iok[4];
+        size_t ooff[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const long long o = o0 + kg + e;
+            ov[e] = o < oe;
+            iok[e] = false;
+            iv[e] = 0;
+            ooff[e] = 0;
+            if (ov[e]) {
+                long long q = o;
+                const int xo = (int)(q % g.Wo); q /= g.Wo;
+                const int yo = (int)(q % g.Ho); q /= g.Ho;
+                const int zo = (int)(q % g.Do);
+                const int n = (int)(q / g.Do);
+                const int zi = zo * g.stride + dz - 1, yi = yo * g.stride + dyy - 1, xi = xo * g.stride + dx_ - 1;
+                iok[e] = (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi && (unsigned)xi < (unsigned)g.Wi;
+                iv[e] = (((long long)n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                ooff[e] = (size_t)o * g.Cout;
+            }
+        }
+        // A operands: P[o][co] for the co-tiles
+        s4v a[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int co = i * 16 + (lane & 15);
+            float pv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                pv[e] = 0.f;
+                if (ov[e] && co < g.Cout) {
+                    pv[e] = dy[ooff[e] + co];
+                    if (y) pv[e] *= lrelu_d(y[ooff[e] + co], slope);
+                }
+            }
+            a[i] = pack4(pv[0], pv[1], pv[2], pv[3]);
+        }
+#pragma unroll
+        for (int jj = 0; jj < TNW; ++jj) {
+            const int jt = wave + 4 * jj;
+            if (jt >= TN) break;
+            const int ci = jt * 16 + (lane & 15);
+            s4v b;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                unsigned short h = 0;
+                if (iok[e] && ci < Cin) {
+                    const long long v = iv[e];
+                    if (ci < g.Ca) {
+                        if (g.ups) {
+                            long long q = v;
+                            const int xi = (int)(q % g.Wi); q /= g.Wi;
+                            const int yi = (int)(q % g.Hi); q /= g.Hi;
+                            const int zi = (int)(q % g.Di);
+                            const int n = (int)(q / g.Di);
+                            const size_t va = (((size_t)n * (g.Di >> 1) + (zi >> 1)) * (g.Hi >> 1) + (yi >> 1)) *
+                                                  (g.Wi >> 1) + (xi >> 1);
+                            h = xa[va * g.Ca + ci];
+                        } else {
+                            h = xa[(size_t)v * g.Ca + ci];
+                        }
+                    } else {
+                        h = xb[(size_t)v * g.Cb + (ci - g.Ca)];
+                    }
+                }
+                b[e] = (short)h;
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i) acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b, acc[i][jj], 0, 0, 0);
+        }
+    }
+    // D[i = co][j = ci]: lane holds co = 16 i_t + 4 (l/16) + e, ci = 16 jt + l % 16
+    float* P = part + (size_t)blockIdx.x * g.Cout * 27 * Cin;
+#pragma unroll
+    for (int jj = 0; jj < TNW; ++jj) {
+        const int jt = wave + 4 * jj;
+        if (jt >= TN) break;
+        const int ci = jt * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = i * 16 + (lane >> 4) * 4 + e;
+                if (co < g.Cout && ci < Cin) P[((size_t)co * 27 + t) * Cin + ci] = acc[i][jj][e];
+            }
+    }
+}
+
+// dW[q] = sum_c part[c][q] (fixed order), dW fp32
+__global__ void __launch_bounds__(256) reduce_parts_kernel(const float* __restrict__ part, int nparts, long long q_n,
+                                                           float* __restrict__ out)
+{
+    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < q_n; q += (long long)gridDim.x * 256) {
+        float s = 0.f;
+        for (int c = 0; c < nparts; ++c) s += part[(size_t)c * q_n + q];
+        out[q] = s;
+    }
+}
+
+// bias gradient partials: part[chunk][co] = sum_{o in chunk} P[o][co]
+__global__ void __launch_bounds__(256) bias_grad_kernel(const float* __restrict__ dy, const unsigned short* __restrict__ y,
+                                                        float slope, long long M, int Cout, long long VC,
+                                                        float* __restrict__ part)
+{
+    __shared__ float red[256];
+    const long long ob = (long long)blockIdx.x * VC, oe = min(M, ob + VC);
+    for (int co = 0; co < Cout; ++co) {
+        float s = 0.f;
+        for (long long o = ob + threadIdx.x; o < oe; o += 256) {
+            const size_t i = (size_t)o * Cout + co;
+            float v = dy[i];
+            if (y) v *= lrelu_d(y[i], slope);
+            s += __uint_as_float((unsigned)f2bf(v) << 16);  // the same bf16 operand the weight gradient uses
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * Cout + co] = red[0];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ small kernels --
+__global__ void __launch_bounds__(256) cast_bf16_kernel(const float* __restrict__ x, long long n,
+                                                        unsigned short* __restrict__ y)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        y[i] = f2bf(x[i]);
+}
+
+// W [Cout][27][Cin] fp32 -> bf16 copy and bf16 transpose [Cin][27][Cout]
+__global__ void __launch_bounds__(256) weight_prep_kernel(const float* __restrict__ w, int Cout, int Cin,
+                                                          unsigned short* __restrict__ wbf,
+                                                          unsigned short* __restrict__ wt)
+{
+    const int n = Cout * 27 * Cin;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const int co = i / (27 * Cin), r = i - co * 27 * Cin, t = r / Cin, ci = r - t * Cin;
+        const unsigned short h = f2bf(w[i]);
+        if (wbf) wbf[i] = h;
+        if (wt) wt[((size_t)ci * 27 + t) * Cout + co] = h;
+    }
+}
+
+// (F, M) fp32 [N][D][H][W] each -> bf16 [N][D][H][W][4] = (F, M, 0, 0)
+__global__ void __launch_bounds__(256) pack_pair_kernel(const float* __restrict__ F, const float* __restrict__ M,
+                                                        long long nvox, unsigned short* __restrict__ x)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < nvox; i += (long long)gridDim.x * 256) {
+        uint2 v;
+        v.x = (unsigned)f2bf(F[i]) | ((unsigned)f2bf(M[i]) << 16);
+        v.y = 0u;
+        *reinterpret_cast<uint2*>(x + 4 * i) = v;
+    }
+}
+
+// split the gradient of a concatenated, upsampled input: dXcat fp32 [N][Di][Hi][Wi][Ca+Cb]
+//   dxb[n,z,y,x,c]  (+)= dXcat[..., Ca + c]
+//   dxa[n,Z,Y,X,c]  (+)= sum over the 8 fine voxels (2Z+a, 2Y+b, 2X+c) of dXcat[..., c]
+__global__ void __launch_bounds__(256) split_grad_kernel(ConvGeom g, const float* __restrict__ dxc,
+                                                         float* __restrict__ dxa, float* __restrict__ dxb, int acc_a,
+                                                         int acc_b)
+{
+    const int Cin = g.Ca + g.Cb;
+    const long long nfine = (long long)g.N * g.Di * g.Hi * g.Wi;
+    const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
+    const long long ncoarse = (long long)g.N * Da * Ha * Wa;
+    const long long tb = nfine * g.Cb, ta = ncoarse * g.Ca;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < tb + ta; i += (long long)gridDim.x * 256) {
+        if (i < tb) {
+            const long long v = i / g.Cb;
+            const int c = (int)(i - v * g.Cb);
+            const float s = dxc[v * Cin + g.Ca + c];
+            dxb[i] = acc_b ? dxb[i] + s : s;
+        } else {
+            const long long j = i - tb;
+            long long v = j / g.Ca;
+            const int c = (int)(j - v * g.Ca);
+            const int X = (int)(v % Wa); v /= Wa;
+            const int Y = (int)(v % Ha); v /= Ha;
+            const int Z = (int)(v % Da);
+            const int n = (int)(v / Da);
+            float s = 0.f;
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int cc = 0; cc < 2; ++cc) {
+                        const size_t f = (((size_t)n * g.Di + 2 * Z + a) * g.Hi + 2 * Y + b) * g.Wi + 2 * X + cc;
+                        s += dxc[f * Cin + c];
+                    }
+            dxa[j] = acc_a ? dxa[j] + s : s;
+        }
+    }
+}
+
+// MSE between pred [N][D][H][W][Cp] channels 0..2 and target [N][3][D][H][W]:
+// grad (written to dpred, channels >= 3 zeroed) and per-block partial sums.
+__global__ void __launch_bounds__(256) mse_kernel(const float* __restrict__ pred, int Cp,
+                                                  const float* __restrict__ tgt, long long nvox_per, int N,
+                                                  float* __restrict__ dpred, double* __restrict__ part, double scale)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    const long long nv = nvox_per * N;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < nv; i += (long long)gridDim.x * 256) {
+        const long long n = i / nvox_per, v = i - n * nvox_per;
+        for (int c = 0; c < Cp; ++c) {
+            float g = 0.f;
+            if (c < 3) {
+                const float d = pred[i * Cp + c] - tgt[(n * 3 + c) * nvox_per + v];
+                s += (double)d * d;
+                g = (float)(2.0 * scale) * d;
+            }
+            if (dpred) dpred[i * Cp + c] = g;
+        }
+    }
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s * scale;
+}
+
+// *out = sum of the partials (fixed order)
+__global__ void __launch_bounds__(256) sum_partials_kernel(const double* __restrict__ part, int n, float* out)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) *out = (float)s;
+}
+
+// pred [N][D][H][W][Cp] -> displacement [N][3][D][H][W]
+__global__ void __launch_bounds__(256) unpack_disp_kernel(const float* __restrict__ pred, int Cp, long long nvox_per,
+                                                          int N, float* __restrict__ u)
+{
+    const long long nv = nvox_per * N;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < nv; i += (long long)gridDim.x * 256) {
+        const long long n = i / nvox_per, v = i - n * nvox_per;
+        for (int c = 0; c < 3; ++c) u[(n * 3 + c) * nvox_per + v] = pred[i * Cp + c];
+    }
+}
+
+// ------------------------------------------------------------------ host ----
+static unsigned grid_for(long long n, int per = 256, long long cap = 16384)
+{
+    long long b = (n + per - 1) / per;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+hipError_t conv_fwd_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
+                           const unsigned short* w, const float* bias, int act, float slope, unsigned short* ybf,
+                           float* yf, hipStream_t st)
+{
+    const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
+    const unsigned blocks = (unsigned)((M + 63) / 64);
+    const int nt = (g.Cout + 15) / 16;
+    if (nt <= 1) hipLaunchKernelGGL(conv_fwd_kernel<1>, dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else if (nt <= 2) hipLaunchKernelGGL(conv_fwd_kernel<2>, dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else if (nt <= 4) hipLaunchKernelGGL(conv_fwd_kernel<4>, dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else if (nt <= 8) hipLaunchKernelGGL(conv_fwd_kernel<8>, dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t conv_bwd_data_launch(const ConvGeom& g, const float* dy, const unsigned short* y, float slope,
+                                const unsigned short* wt, float* dx, int accumulate, hipStream_t st)
+{
+    const long long M = (long long)g.N * g.Di * g.Hi * g.Wi;
+    const unsigned blocks = (unsigned)((M + 63) / 64);
+    const int nt = (g.Ca + g.Cb + 15) / 16;
+    if (nt <= 1) hipLaunchKernelGGL(conv_bwd_data_kernel<1>, dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else if (nt <= 2) hipLaunchKernelGGL(conv_bwd_data_kernel<2>, dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else if (nt <= 4) hipLaunchKernelGGL(conv_bwd_data_kernel<4>, dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else if (nt <= 8) hipLaunchKernelGGL(conv_bwd_data_kernel<8>, dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else if (nt <= 12) hipLaunchKernelGGL(conv_bwd_data_kernel<12>, dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+ConvWgradPlan conv_wgrad_plan(const ConvGeom& g)
+{
+    ConvWgradPlan p;
+    const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
+    long long vc = (M + 255) / 256;
+    vc = ((vc + 15) / 16) * 16;
+    if (vc < 256) vc = 256;
+    p.VC = vc;
+    p.nchunks = (int)((M + vc - 1) / vc);
+    const long long q = (long long)g.Cout * 27 * (g.Ca + g.Cb);
+    p.part_floats = (long long)p.nchunks * q + (long long)p.nchunks * g.Cout;
+    return p;
+}
+
+template <int TM>
+static void launch_wg_tm(int tnw, dim3 grid, hipStream_t st, const ConvGeom& g, const unsigned short* xa,
+                         const unsigned short* xb, const float* dy, const unsigned short* y, float slope, long long VC,
+                         float* part)
+{
+    if (tnw <= 1) hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 1>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VC, part);
+    else if (tnw <= 2) hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 2>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VC, part);
+    else hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 3>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VC, part);
+}
+
+hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
+                                  const float* dy, const unsigned short* y, float slope, float* dw, float* db,
+                                  float* part, hipStream_t st)
+{
+    const ConvWgradPlan p = conv_wgrad_plan(g);
+    const int Cin = g.Ca + g.Cb;
+    const int tm = (g.Cout + 15) / 16, tn = (Cin + 15) / 16, tnw = (tn + 3) / 4;
+    if (tnw > 3 || tm > 8) return hipErrorInvalidValue;
+    dim3 grid(p.nchunks, 27);
+    switch (tm) {
+        case 1: launch_wg_tm<1>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
+        case 2: launch_wg_tm<2>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
+        case 3: case 4: launch_wg_tm<4>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
+        default: launch_wg_tm<8>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long q = (long long)g.Cout * 27 * Cin;
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for(q)), dim3(256), 0, st, part, p.nchunks, q, dw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (db) {
+        const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
+        float* pb = part + (size_t)p.nchunks * q;
+        hipLaunchKernelGGL(bias_grad_kernel, dim3(p.nchunks), dim3(256), 0, st, dy, y, slope, M, g.Cout, p.VC, pb);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, pb, p.nchunks, (long long)g.Cout, db);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t cast_bf16_launch(const float* x, long long n, unsigned short* y, hipStream_t st)
+{
+    hipLaunchKernelGGL(cast_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, st, x, n, y);
+    return hipGetLastError();
+}
+
+hipError_t weight_prep_launch(const float* w, int Cout, int Cin, unsigned short* wbf, unsigned short* wt,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(weight_prep_kernel, dim3(grid_for((long long)Cout * 27 * Cin)), dim3(256), 0, st, w, Cout, Cin,
+                       wbf, wt);
+    return hipGetLastError();
+}
+
+hipError_t pack_pair_launch(const float* F, const float* M, long long nvox, unsigned short* x, hipStream_t st)
+{
+    hipLaunchKernelGGL(pack_pair_kernel, dim3(grid_for(nvox)), dim3(256), 0, st, F, M, nvox, x);
+    return hipGetLastError();
+}
+
+hipError_t split_grad_launch(const ConvGeom& g, const float* dxc, float* dxa, float* dxb, int acc_a, int acc_b,
+                             hipStream_t st)
+{
+    const long long nfine = (long long)g.N * g.Di * g.Hi * g.Wi;
+    const long long tot = nfine * g.Cb + nfine / 8 * g.Ca;
+    hipLaunchKernelGGL(split_grad_kernel, dim3(grid_for(tot)), dim3(256), 0, st, g, dxc, dxa, dxb, acc_a, acc_b);
+    return hipGetLastError();
+}
+
+hipError_t mse_launch(const float* pred, int Cp, const float* tgt, long long nvox_per, int N, float* dpred,
+                      double* part, int nblocks, float* loss, hipStream_t st)
+{
+    const double scale = 1.0 / ((double)nvox_per * N * 3.0);
+    hipLaunchKernelGGL(mse_kernel, dim3(nblocks), dim3(256), 0, st, pred, Cp, tgt, nvox_per, N, dpred, part, scale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (loss) {
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, part, nblocks, loss);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t unpack_disp_launch(const float* pred, int Cp, long long nvox_per, int N, float* u, hipStream_t st)
+{
+    hipLaunchKernelGGL(unpack_disp_kernel, dim3(grid_for(nvox_per * N)), dim3(256), 0, st, pred, Cp, nvox_per, N, u);
+    return hipGetLastError();
+}
+
+}  // namespace ffdp

@@ -64,4 +64,39 @@ hipError_t resample_launch(const float* src, int sD, int sH, int sW, float* dst,
 hipError_t adam_launch(float* x, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, int64_t step, hipStream_t st);
 
+// 3x3x3 convolutions of the warm-start network
+struct ConvGeom {
+    int N;
+    int Di, Hi, Wi;  // convolution input (after upsampling)
+    int Do, Ho, Wo;  // output
+    int Ca, Cb;      // channels of the (optionally upsampled) part a and the skip part b
+    int Cout;
+    int stride;      // 1 or 2
+    int ups;         // part a stored at half resolution, nearest x2
+};
+struct ConvWgradPlan {
+    long long VC;          // output voxels per chunk
+    int nchunks;
+    long long part_floats;  // workspace floats
+};
+ConvWgradPlan conv_wgrad_plan(const ConvGeom& g);
+hipError_t conv_fwd_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
+                           const unsigned short* w, const float* bias, int act, float slope, unsigned short* ybf,
+                           float* yf, hipStream_t st);
+hipError_t conv_bwd_data_launch(const ConvGeom& g, const float* dy, const unsigned short* y, float slope,
+                                const unsigned short* wt, float* dx, int accumulate, hipStream_t st);
+hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
+                                  const float* dy, const unsigned short* y, float slope, float* dw, float* db,
+                                  float* part, hipStream_t st);
+hipError_t cast_bf16_launch(const float* x, long long n, unsigned short* y, hipStream_t st);
+hipError_t weight_prep_launch(const float* w, int Cout, int Cin, unsigned short* wbf, unsigned short* wt,
+                              hipStream_t st);
+hipError_t pack_pair_launch(const float* F, const float* M, long long nvox, unsigned short* x, hipStream_t st);
+hipError_t split_grad_launch(const ConvGeom& g, const float* dxc, float* dxa, float* dxb, int acc_a, int acc_b,
+                             hipStream_t st);
+constexpr int MSE_BLOCKS = 1024;
+hipError_t mse_launch(const float* pred, int Cp, const float* tgt, long long nvox_per, int N, float* dpred,
+                      double* part, int nblocks, float* loss, hipStream_t st);
+hipError_t unpack_disp_launch(const float* pred, int Cp, long long nvox_per, int N, float* u, hipStream_t st);
+
 }  // namespace ffdp

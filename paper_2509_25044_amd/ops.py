@@ -12,7 +12,7 @@ from typing import Optional, Sequence, Tuple
 import torch
 
 from . import _lib
-from ._lib import Grid, LnccParams, MiParams, check
+from ._lib import ConvGeom, Grid, LnccParams, MiParams, check
 
 PAD = {"border": 0, "zeros": 1, 0: 0, 1: 1}
 
@@ -206,3 +206,128 @@ def adam_step(x, g, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
                                                        float(beta1), float(beta2), float(eps), int(step),
                                                        _stream(x)))
     return x
+
+
+# ------------------------------------------------------------ U-Net kernels --
+def _dev_t(t, name, dtype):
+    if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor")
+    return t
+
+
+def conv_geom(N, Di, Hi, Wi, Ca, Cb, Cout, stride=1, ups=False) -> ConvGeom:
+    g = ConvGeom()
+    g.N, g.Di, g.Hi, g.Wi, g.Ca, g.Cb, g.Cout, g.stride, g.ups = (int(N), int(Di), int(Hi), int(Wi), int(Ca),
+                                                                  int(Cb), int(Cout), int(stride), int(bool(ups)))
+    return g
+
+
+def conv_out_shape(g: ConvGeom):
+    s = g.stride
+    return ((g.Di - 1) // s + 1, (g.Hi - 1) // s + 1, (g.Wi - 1) // s + 1)
+
+
+def conv3d_fwd(xa, xb, w_bf16, bias, g: ConvGeom, act=True, slope=0.2, y_bf16=None, y_f32=None, want_bf16=True,
+               want_f32=False):
+    """3x3x3 BF16-MFMA convolution (ffdp_conv3d_fwd); bf16 tensors are torch.bfloat16."""
+    Do, Ho, Wo = conv_out_shape(g)
+    shape = (g.N, Do, Ho, Wo, g.Cout)
+    if want_bf16 and y_bf16 is None:
+        y_bf16 = torch.empty(shape, dtype=torch.bfloat16, device=xa.device)
+    if want_f32 and y_f32 is None:
+        y_f32 = torch.empty(shape, dtype=torch.float32, device=xa.device)
+    check("ffdp_conv3d_fwd", _lib.lib().ffdp_conv3d_fwd(_ptr(xa), _ptr(xb), _ptr(w_bf16), _ptr(bias), C.byref(g),
+                                                        int(bool(act)), float(slope), _ptr(y_bf16), _ptr(y_f32),
+                                                        _stream(xa)))
+    return y_bf16 if y_f32 is None else (y_f32 if y_bf16 is None else (y_bf16, y_f32))
+
+
+def conv3d_bwd_data(dy, y, wt_bf16, g: ConvGeom, slope=0.2, dx=None, accumulate=False):
+    """Input gradient over the concatenated fine-resolution input (ffdp_conv3d_bwd_data)."""
+    if dx is None:
+        dx = torch.empty((g.N, g.Di, g.Hi, g.Wi, g.Ca + g.Cb), dtype=torch.float32, device=dy.device)
+    check("ffdp_conv3d_bwd_data", _lib.lib().ffdp_conv3d_bwd_data(_ptr(dy), _ptr(y), float(slope), _ptr(wt_bf16),
+                                                                  C.byref(g), _ptr(dx), int(bool(accumulate)),
+                                                                  _stream(dy)))
+    return dx
+
+
+def conv3d_bwd_weight(xa, xb, dy, y, g: ConvGeom, slope=0.2, dw=None, db=None, ws=None):
+    """(dW [Cout][27][Cin], db [Cout]) fp32 (ffdp_conv3d_bwd_weight)."""
+    L = _lib.lib()
+    nb = int(L.ffdp_conv3d_bwd_weight_workspace_bytes(C.byref(g)))
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(max(nb, 16), dtype=torch.uint8, device=dy.device)
+    if dw is None:
+        dw = torch.empty((g.Cout, 27, g.Ca + g.Cb), dtype=torch.float32, device=dy.device)
+    if db is None:
+        db = torch.empty(g.Cout, dtype=torch.float32, device=dy.device)
+    check("ffdp_conv3d_bwd_weight", L.ffdp_conv3d_bwd_weight(_ptr(xa), _ptr(xb), _ptr(dy), _ptr(y), float(slope),
+                                                             C.byref(g), _ptr(dw), _ptr(db), _ptr(ws), ws.numel(),
+                                                             _stream(dy)))
+    return dw, db
+
+
+def conv3d_bwd_weight_workspace_bytes(g: ConvGeom) -> int:
+    return int(_lib.lib().ffdp_conv3d_bwd_weight_workspace_bytes(C.byref(g)))
+
+
+def conv3d_weight_prep(w, w_bf16=None, wt_bf16=None):
+    """fp32 [Cout][27][Cin] -> (bf16 copy, bf16 [Cin][27][Cout]) (ffdp_conv3d_weight_prep)."""
+    Cout, _, Cin = w.shape
+    if w_bf16 is None:
+        w_bf16 = torch.empty(w.shape, dtype=torch.bfloat16, device=w.device)
+    if wt_bf16 is None:
+        wt_bf16 = torch.empty((Cin, 27, Cout), dtype=torch.bfloat16, device=w.device)
+    check("ffdp_conv3d_weight_prep", _lib.lib().ffdp_conv3d_weight_prep(_ptr(w), Cout, Cin, _ptr(w_bf16),
+                                                                        _ptr(wt_bf16), _stream(w)))
+    return w_bf16, wt_bf16
+
+
+def unet_pack_pair(F, M, out=None):
+    """(F, M) fp32 [..] -> bf16 [.., 4] (ffdp_unet_pack_pair)."""
+    n = F.numel()
+    if out is None:
+        out = torch.empty(tuple(F.shape) + (4,), dtype=torch.bfloat16, device=F.device)
+    check("ffdp_unet_pack_pair", _lib.lib().ffdp_unet_pack_pair(_ptr(F), _ptr(M), n, _ptr(out), _stream(F)))
+    return out
+
+
+def concat_grad_split(dxcat, g: ConvGeom, dxa=None, dxb=None, acc_a=False, acc_b=False):
+    """Split the gradient of an upsampled+concatenated input (ffdp_concat_grad_split)."""
+    if dxa is None:
+        dxa = torch.empty((g.N, g.Di // 2, g.Hi // 2, g.Wi // 2, g.Ca), dtype=torch.float32, device=dxcat.device)
+    if dxb is None and g.Cb > 0:
+        dxb = torch.empty((g.N, g.Di, g.Hi, g.Wi, g.Cb), dtype=torch.float32, device=dxcat.device)
+    check("ffdp_concat_grad_split", _lib.lib().ffdp_concat_grad_split(_ptr(dxcat), C.byref(g), _ptr(dxa), _ptr(dxb),
+                                                                      int(bool(acc_a)), int(bool(acc_b)),
+                                                                      _stream(dxcat)))
+    return dxa, dxb
+
+
+def mse_disp(pred, target, dpred=None, want_grad=True, loss=None, ws=None):
+    """MSE of pred [N, ..., Cp] channels 0..2 against target [N, 3, ...] (ffdp_mse_disp)."""
+    L = _lib.lib()
+    N = pred.shape[0]
+    Cp = pred.shape[-1]
+    nvox = pred.numel() // (N * Cp)
+    if ws is None:
+        ws = _workspace(int(L.ffdp_mse_workspace_bytes()), pred.device, None)
+    if want_grad and dpred is None:
+        dpred = torch.empty_like(pred)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=pred.device)
+    check("ffdp_mse_disp", L.ffdp_mse_disp(_ptr(pred), Cp, _ptr(target), nvox, N, _ptr(dpred), _ptr(loss), _ptr(ws),
+                                           ws.numel(), _stream(pred)))
+    return loss, dpred
+
+
+def unpack_disp(pred, out=None):
+    """pred [N, D, H, W, Cp] -> displacement [N, 3, D, H, W] (ffdp_unpack_disp)."""
+    N = pred.shape[0]
+    Cp = pred.shape[-1]
+    nvox = pred.numel() // (N * Cp)
+    if out is None:
+        out = torch.empty((N, 3) + tuple(pred.shape[1:-1]), dtype=torch.float32, device=pred.device)
+    check("ffdp_unpack_disp", _lib.lib().ffdp_unpack_disp(_ptr(pred), Cp, nvox, N, _ptr(out), _stream(pred)))
+    return out

@@ -123,8 +123,13 @@ def _texture_modes(rng, spec: PairSpec):
     return [(float(k[i, 0]), float(k[i, 1]), float(k[i, 2]), float(ph[i]), float(a[i])) for i in range(n)]
 
 
-def _noise(rng, shape, std, device):
+def _noise(rng, shape, std, device, on_device=False):
     seed = int(rng.integers(0, 2**62))
+    if on_device and torch.device(device).type != "cpu":
+        # fast path for bulk training data: the device's own generator (not
+        # bitwise identical to the host stream, but seeded and repeatable)
+        g = torch.Generator(device=device).manual_seed(seed)
+        return torch.randn(shape, generator=g, dtype=torch.float32, device=device) * std
     g = torch.Generator(device="cpu").manual_seed(seed)
     return (torch.randn(shape, generator=g, dtype=torch.float32) * std).to(device)
 
@@ -146,7 +151,7 @@ def _remap_coeffs(rng):
 
 
 def make_pair(spec: PairSpec, seed: int = BASE_SEED, device="cpu",
-              with_disp: bool = True, z_range: Optional[Tuple[int, int]] = None):
+              with_disp: bool = True, z_range: Optional[Tuple[int, int]] = None, noise_on_device: bool = False):
     """Return dict(F, M, d) as float32 tensors on ``device``.
 
     ``z_range`` restricts evaluation to slices [z0, z1) of the full volume (the
@@ -187,8 +192,8 @@ def make_pair(spec: PairSpec, seed: int = BASE_SEED, device="cpu",
         Fv.add_(_eval_modes(tmodes, z, y, x, shape, device, dt), alpha=spec.texture_std)
         Mv.add_(_eval_modes(tmodes, pz, py, px, shape, device, dt), alpha=spec.texture_std)
     del pz, py, px
-    Fv.add_(_noise(st["noise"], shape, spec.noise_std, device))
-    Mv.add_(_noise(st["noise"], shape, spec.noise_std, device))
+    Fv.add_(_noise(st["noise"], shape, spec.noise_std, device, noise_on_device))
+    Mv.add_(_noise(st["noise"], shape, spec.noise_std, device, noise_on_device))
     _minmax_(Fv)
     _minmax_(Mv)
     if spec.multimodal:
