@@ -99,6 +99,63 @@ __device__ __forceinline__ Tri trilinear(const float* __restrict__ M, int D, int
     return t;
 }
 
+// Border-mode trilinear sample with clamped corner indices, the form the
+// streaming kernels use.  Along an axis whose sample point is clamped both
+// corner indices coincide, so the value needs no special case and the corner
+// difference (the derivative) is exactly zero; a point exactly on index 0 is
+// also treated as clamped for the derivative.  Same results as
+// trilinear<PAD_BORDER>.  Loads use 32-bit byte offsets from the volume base
+// unless BIG (volumes of 2^30 voxels or more).
+template <bool DERIV, bool BIG>
+__device__ __forceinline__ Tri trilinear_clamped(const float* __restrict__ M, int D, int H, int W, int HW, int x,
+                                                 int y, int z, float ux, float uy, float uz)
+{
+    const float fx = fminf(fmaxf(floorf(ux), -268435456.0f), 268435456.0f);
+    const float fy = fminf(fmaxf(floorf(uy), -268435456.0f), 268435456.0f);
+    const float fz = fminf(fmaxf(floorf(uz), -268435456.0f), 268435456.0f);
+    const float ax = ux - fx, ay = uy - fy, az = uz - fz;
+    const int ix = x + (int)fx, iy = y + (int)fy, iz = z + (int)fz;
+    const int x0 = min(max(ix, 0), W - 1), x1 = min(max(ix + 1, 0), W - 1);
+    const int y0 = min(max(iy, 0), H - 1), y1 = min(max(iy + 1, 0), H - 1);
+    const int z0 = min(max(iz, 0), D - 1), z1 = min(max(iz + 1, 0), D - 1);
+    float m000, m001, m010, m011, m100, m101, m110, m111;
+    if (BIG) {
+        const size_t r00 = (size_t)z0 * HW + (size_t)y0 * W, r01 = (size_t)z0 * HW + (size_t)y1 * W;
+        const size_t r10 = (size_t)z1 * HW + (size_t)y0 * W, r11 = (size_t)z1 * HW + (size_t)y1 * W;
+        m000 = M[r00 + x0]; m001 = M[r00 + x1]; m010 = M[r01 + x0]; m011 = M[r01 + x1];
+        m100 = M[r10 + x0]; m101 = M[r10 + x1]; m110 = M[r11 + x0]; m111 = M[r11 + x1];
+    } else {
+        const char* base = reinterpret_cast<const char*>(M);
+        const unsigned r00 = (unsigned)(z0 * HW + y0 * W) * 4u, r01 = (unsigned)(z0 * HW + y1 * W) * 4u;
+        const unsigned r10 = (unsigned)(z1 * HW + y0 * W) * 4u, r11 = (unsigned)(z1 * HW + y1 * W) * 4u;
+        const unsigned c0 = (unsigned)x0 * 4u, c1 = (unsigned)x1 * 4u;
+        m000 = *reinterpret_cast<const float*>(base + (r00 + c0));
+        m001 = *reinterpret_cast<const float*>(base + (r00 + c1));
+        m010 = *reinterpret_cast<const float*>(base + (r01 + c0));
+        m011 = *reinterpret_cast<const float*>(base + (r01 + c1));
+        m100 = *reinterpret_cast<const float*>(base + (r10 + c0));
+        m101 = *reinterpret_cast<const float*>(base + (r10 + c1));
+        m110 = *reinterpret_cast<const float*>(base + (r11 + c0));
+        m111 = *reinterpret_cast<const float*>(base + (r11 + c1));
+    }
+    const float e00 = m001 - m000, e01 = m011 - m010, e10 = m101 - m100, e11 = m111 - m110;
+    const float c00 = fmaf(ax, e00, m000), c01 = fmaf(ax, e01, m010);
+    const float c10 = fmaf(ax, e10, m100), c11 = fmaf(ax, e11, m110);
+    const float f0 = c01 - c00, f1 = c11 - c10;
+    const float c0 = fmaf(ay, f0, c00), c1 = fmaf(ay, f1, c10);
+    Tri t;
+    t.v = fmaf(az, c1 - c0, c0);
+    if (DERIV) {
+        const float gx0 = fmaf(ay, e01 - e00, e00), gx1 = fmaf(ay, e11 - e10, e10);
+        t.dx = (ix == 0 && ax == 0.0f) ? 0.0f : fmaf(az, gx1 - gx0, gx0);
+        t.dy = (iy == 0 && ay == 0.0f) ? 0.0f : fmaf(az, f1 - f0, f0);
+        t.dz = (iz == 0 && az == 0.0f) ? 0.0f : (c1 - c0);
+    } else {
+        t.dx = t.dy = t.dz = 0.0f;
+    }
+    return t;
+}
+
 // Deterministic block sum of a double (fixed tree order).  All threads of the
 // block must call it; `red` holds blockDim.x doubles of LDS.
 template <int NT>

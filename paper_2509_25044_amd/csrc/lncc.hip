@@ -85,8 +85,17 @@ __device__ __forceinline__ float2 xwin2(const float* row)
     return make_float2(o0, o1);
 }
 
+template <int PAD, bool DERIV, bool BIG>
+__device__ __forceinline__ Tri sample(const float* __restrict__ M, int D, int H, int W, int HW, int x, int y, int z,
+                                      float ux, float uy, float uz)
+{
+    if (PAD == PAD_BORDER) return trilinear_clamped<DERIV, BIG>(M, D, H, W, HW, x, y, z, ux, uy, uz);
+    return trilinear<PAD_ZEROS, DERIV>(M, D, H, W, x, y, z, ux, uy, uz);
+}
+
 // Windows up to 5 are held to 128 VGPRs so two 512-thread blocks share a CU.
-template <int WIN, int MODE, int PAD>
+// BIG selects 64-bit gather offsets (volumes of 2^30 voxels or more).
+template <int WIN, int MODE, int PAD, bool BIG>
 __global__ void __launch_bounds__(LNCC_NT) __attribute__((amdgpu_waves_per_eu(WIN <= 5 ? 4 : 2, 8)))
 lncc_kernel(LnccArgs a)
 {
@@ -159,18 +168,18 @@ lncc_kernel(LnccArgs a)
         pxy[k] = pin[k] ? pgy[k] * W + pgx[k] : 0;
     }
     // u and F of the next slice are loaded one step ahead, so their HBM
-    // latency overlaps the LDS stages of the current slice
+    // latency overlaps the LDS stages of the current slice.  Loads are
+    // unconditional (slice index clamped, off-array points read voxel 0) and
+    // the results are selected later, so the loop has no per-point branches.
     float pu[P][3], pf[P];
     auto prefetch = [&](int zs) {
-        const bool zok = zs >= 0 && zs < D;
+        const size_t zoff = (size_t)min(max(zs, 0), D - 1) * HW;
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            pf[k] = 0.f; pu[k][0] = 0.f; pu[k][1] = 0.f; pu[k][2] = 0.f;
-            if (zok && pin[k]) {
-                const int idx = zs * HW + pxy[k];
-                pf[k] = F[idx];
-                if (U) { pu[k][0] = U[idx]; pu[k][1] = U[N + idx]; pu[k][2] = U[2 * N + idx]; }
-            }
+            const size_t idx = zoff + pxy[k];
+            pf[k] = F[idx];
+            if (U) { pu[k][0] = U[idx]; pu[k][1] = U[N + idx]; pu[k][2] = U[2 * N + idx]; }
+            else { pu[k][0] = 0.f; pu[k][1] = 0.f; pu[k][2] = 0.f; }
         }
     };
     prefetch(z0 - R2);
@@ -187,15 +196,16 @@ lncc_kernel(LnccArgs a)
 #pragma unroll
             for (int k = 0; k < P; ++k) {
                 if (k == 0 || hx[k - 1] >= 0) {
+                    const bool ok = zin && pin[k];
                     float f = -sF, m = -sM;  // padded voxels are 0 before the shift
                     float d0 = 0.f, d1 = 0.f, d2 = 0.f;
-                    if (zin && pin[k]) {
+                    if (ok) {
                         f = pf[k] - sF;
                         if (DER && k == 0) {
-                            const Tri t = trilinear<PAD, true>(M, D, H, W, pgx[k], pgy[k], zi, pu[k][0], pu[k][1], pu[k][2]);
+                            const Tri t = sample<PAD, DER, BIG>(M, D, H, W, HW, pgx[k], pgy[k], zi, pu[k][0], pu[k][1], pu[k][2]);
                             m = t.v - sM; d0 = t.dx; d1 = t.dy; d2 = t.dz;
                         } else {
-                            m = trilinear<PAD, false>(M, D, H, W, pgx[k], pgy[k], zi, pu[k][0], pu[k][1], pu[k][2]).v - sM;
+                            m = sample<PAD, false, BIG>(M, D, H, W, HW, pgx[k], pgy[k], zi, pu[k][0], pu[k][1], pu[k][2]).v - sM;
                         }
                     }
                     rF[k][j] = f;
@@ -268,7 +278,7 @@ lncc_kernel(LnccArgs a)
                         const float A = fmaf(-mf, mm, S[4][e] * inv);
                         const float B = fmaf(-mf, mf, S[2][e] * inv);
                         const float C = fmaf(-mm, mm, S[3][e] * inv);
-                        const float rD = 1.0f / fmaf(B, C, eps);
+                        const float rD = __builtin_amdgcn_rcpf(fmaf(B, C, eps));  // 1 ulp reciprocal
                         float ac = 0.f, cc = 0.f, ec = 0.f;
                         if (inroi) {
                             if (yown && lx >= R1 && lx < R1 + TX) lsum += (double)(A * A * rD);
@@ -299,7 +309,7 @@ lncc_kernel(LnccArgs a)
                 const float A = fmaf(-mf, mm, S[4] * inv);
                 const float B = fmaf(-mf, mf, S[2] * inv);
                 const float C = fmaf(-mm, mm, S[3] * inv);
-                const float rD = 1.0f / fmaf(B, C, eps);
+                const float rD = __builtin_amdgcn_rcpf(fmaf(B, C, eps));  // 1 ulp reciprocal
                 if (inroi && zown) lsum += (double)(A * A * rD);
                 if (MODE == MODE_ANTS && zown && gx < W && gy < H) {
                     // gradient without the second window sum, at the voxel itself
@@ -397,10 +407,13 @@ template <int WIN, int MODE>
 static hipError_t launch_w(int pad, const LnccArgs& a, hipStream_t st)
 {
     dim3 grid(a.nblocks), block(LNCC_NT);
-    if (pad == PAD_BORDER)
-        hipLaunchKernelGGL((lncc_kernel<WIN, MODE, PAD_BORDER>), grid, block, 0, st, a);
-    else
-        hipLaunchKernelGGL((lncc_kernel<WIN, MODE, PAD_ZEROS>), grid, block, 0, st, a);
+    const bool big = (long long)a.D * a.H * a.W >= (1LL << 30);
+    if (pad == PAD_BORDER) {
+        if (big) hipLaunchKernelGGL((lncc_kernel<WIN, MODE, PAD_BORDER, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((lncc_kernel<WIN, MODE, PAD_BORDER, false>), grid, block, 0, st, a);
+    } else {
+        hipLaunchKernelGGL((lncc_kernel<WIN, MODE, PAD_ZEROS, true>), grid, block, 0, st, a);
+    }
     return hipGetLastError();
 }
 
