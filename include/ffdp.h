@@ -162,6 +162,17 @@ int ffdp_warp_mi_bwd(const float* F, const float* M, const float* u, const ffdp_
 int ffdp_adam_step(float* x, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
                    float eps, int64_t step, void* stream);
 
+/* Gaussian smoothing of a multi-channel field, the regulariser applied to the
+ * displacement gradient (sigma_grad = 1) before the optimiser step and to the
+ * displacement (sigma_warp = 0.5) after it in the paper's registration runs
+ * (Sec. "Grid Parallel", App. experiment settings):
+ *   out[c] = g * g * g (separable) applied to in[c], per channel, with
+ *   g(t) = exp(-t^2 / (2 sigma^2)) / sum_{|s| <= R} exp(-s^2 / (2 sigma^2)),
+ *   |t| <= R = ceil(3 sigma), and the array edge value replicated outside.
+ * in, out [channels][D][H][W]; they must not overlap.  0 < sigma <= 2. */
+int ffdp_gaussian_smooth(const float* in, float* out, int64_t D, int64_t H, int64_t W, int32_t channels, float sigma,
+                         void* stream);
+
 /* ------------------------------------------------------------------------
  * Warm-start network (3D U-Net) kernels.  BF16 operands on MFMA with FP32
  * accumulation.  Activations are channels-last bf16 [N][D][H][W][C]

@@ -522,6 +522,45 @@ int orc_resample(const float* src, i64 sD, i64 sH, i64 sW, double* dst, i64 dD, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Gaussian smoothing of a field (the sigma_grad / sigma_warp regulariser of */
+/* the paper's registration runs): each output is the sum over the full      */
+/* (2R+1)^3 neighbourhood of g(a) g(b) g(c) times the input at the offset,   */
+/* indices clamped to the array (edge replication), with                     */
+/* g(t) = exp(-t^2/(2 sigma^2)) / sum_{|s|<=R} exp(-s^2/(2 sigma^2)) and     */
+/* R = ceil(3 sigma).  Direct triple sum, no separation.                     */
+/* ------------------------------------------------------------------------ */
+static i64 clampi(i64 v, i64 lo, i64 hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+int orc_gaussian_smooth(const float* in, i64 D, i64 H, i64 W, int channels, double sigma, double* out)
+{
+    if (!(sigma > 0.0)) return 1;
+    const int R = (int)ceil(3.0 * sigma);
+    double* g = (double*)malloc(sizeof(double) * (2 * R + 1));
+    double tot = 0.0;
+    for (int t = -R; t <= R; ++t) tot += (g[t + R] = exp(-(double)(t * t) / (2.0 * sigma * sigma)));
+    for (int t = 0; t <= 2 * R; ++t) g[t] /= tot;
+    for (int c = 0; c < channels; ++c) {
+        const float* s = in + (i64)c * D * H * W;
+        double* o = out + (i64)c * D * H * W;
+#pragma omp parallel for schedule(static)
+        for (i64 z = 0; z < D; ++z)
+            for (i64 y = 0; y < H; ++y)
+                for (i64 x = 0; x < W; ++x) {
+                    double acc = 0.0;
+                    for (int a = -R; a <= R; ++a)
+                        for (int b = -R; b <= R; ++b)
+                            for (int e = -R; e <= R; ++e)
+                                acc += g[a + R] * g[b + R] * g[e + R] *
+                                       (double)s[AT(clampi(z + a, 0, D - 1), clampi(y + b, 0, H - 1),
+                                                    clampi(x + e, 0, W - 1))];
+                    o[AT(z, y, x)] = acc;
+                }
+    }
+    free(g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* O6. 3x3x3 convolution of the warm-start network (zero padding 1, stride   */
 /* s), in double on operands the caller has already rounded to bf16.  The    */
 /* input X is the channel concatenation of part a (nearest x2 upsampled when */

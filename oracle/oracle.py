@@ -40,11 +40,12 @@ def load():
     lib.orc_parzen.argtypes = [C.c_double, C.c_int, C.c_int, vp, vp]
     lib.orc_adam.argtypes = [vp, vp, vp, vp, _i64, C.c_double, C.c_double, C.c_double, C.c_double, _i64]
     lib.orc_resample.argtypes = [vp, _i64, _i64, _i64, vp, _i64, _i64, _i64, C.c_int, C.c_double]
+    lib.orc_gaussian_smooth.argtypes = [vp, _i64, _i64, _i64, C.c_int, C.c_double, vp]
     lib.orc_conv3d_fwd.argtypes = [vp, vp, vp, vp] + [_i64] * 9 + [C.c_int, C.c_double, vp]
     lib.orc_conv3d_bwd_data.argtypes = [vp, vp] + [_i64] * 8 + [vp]
     lib.orc_conv3d_bwd_weight.argtypes = [vp, vp, vp] + [_i64] * 9 + [vp, vp]
     for f in ("orc_warp", "orc_lncc", "orc_lncc_grad_u_at", "orc_mi", "orc_parzen", "orc_adam", "orc_resample",
-              "orc_conv3d_fwd", "orc_conv3d_bwd_data", "orc_conv3d_bwd_weight"):
+              "orc_gaussian_smooth", "orc_conv3d_fwd", "orc_conv3d_bwd_data", "orc_conv3d_bwd_weight"):
         getattr(lib, f).restype = C.c_int
     _LIB = lib
     return lib
@@ -161,6 +162,21 @@ def resample(src, dst_shape: Sequence[int], value_scale: float = 1.0):
     lib.orc_resample(_ptr(src), sD, sH, sW, _ptr(out), dD, dH, dW, Cn, value_scale)
     return out[0] if squeeze else out
 
+
+
+def gaussian_smooth(src, sigma: float):
+    """src [C][D][H][W] or [D][H][W] float32 -> float64 Gaussian-smoothed field
+    (direct (2R+1)^3 sum, R = ceil(3 sigma), edge replication)."""
+    lib = load()
+    src = _f32(src)
+    squeeze = src.ndim == 3
+    if squeeze:
+        src = src[None]
+    Cn, D, H, W = src.shape
+    out = np.empty((Cn, D, H, W), np.float64)
+    if lib.orc_gaussian_smooth(_ptr(src), D, H, W, Cn, float(sigma), _ptr(out)) != 0:
+        raise ValueError("sigma must be > 0")
+    return out[0] if squeeze else out
 
 def _f64(a):
     if a is None:

@@ -20,7 +20,7 @@ OUT = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libffdp.so")
 ARCH = "gfx950"
 
-SOURCES = ["lncc.hip", "mi.hip", "elementwise.hip", "conv3d.hip", "api.cpp"]
+SOURCES = ["lncc.hip", "mi.hip", "elementwise.hip", "smooth.hip", "conv3d.hip", "api.cpp"]
 
 # Packed fp32 instructions are switched off (ordinary float code only).
 HIPFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
@@ -49,7 +49,7 @@ def _compile(src: str, verbose: bool) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

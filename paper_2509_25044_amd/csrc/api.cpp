@@ -327,6 +327,29 @@ int ffdp_adam_step(float* x, const float* g, float* m, float* v, int64_t n, floa
                       "ffdp_adam_step");
 }
 
+int ffdp_gaussian_smooth(const float* in, float* out, int64_t D, int64_t H, int64_t W, int32_t channels, float sigma,
+                         void* stream)
+{
+    int s;
+    if ((s = check_dims(D, H, W))) return s;
+    if (channels < 1 || channels > 65535) return fail(FFDP_ERR_PARAM, "channels must be in [1, 65535]");
+    if (!(sigma > 0.0f && sigma <= 2.0f)) return fail(FFDP_ERR_PARAM, "sigma must be in (0, 2]");
+    if ((s = check_ptrs("in,out", 2, (const void*)in, (const void*)out))) return s;
+    const char* a0 = (const char*)in;
+    const char* a1 = a0 + (size_t)channels * D * H * W * sizeof(float);
+    const char* b0 = (const char*)out;
+    const char* b1 = b0 + (size_t)channels * D * H * W * sizeof(float);
+    if (a0 < b1 && b0 < a1) return fail(FFDP_ERR_PARAM, "in and out overlap");
+    // taps exp(-t^2 / (2 sigma^2)) for |t| <= ceil(3 sigma), normalised in double
+    const int R = (int)ceil(3.0 * (double)sigma);
+    SmoothWeights w{};
+    double tot = 0.0, e[2 * SMOOTH_MAX_R + 1];
+    for (int t = -R; t <= R; ++t) tot += (e[t + R] = exp(-(double)t * t / (2.0 * (double)sigma * sigma)));
+    for (int k = 0; k <= 2 * R; ++k) w.w[k] = (float)(e[k] / tot);
+    return hip_status(smooth_launch(in, out, (int)D, (int)H, (int)W, channels, w, R, (hipStream_t)stream),
+                      "ffdp_gaussian_smooth");
+}
+
 }  // extern "C"
 
 namespace {

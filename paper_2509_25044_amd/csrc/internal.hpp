@@ -64,6 +64,14 @@ hipError_t resample_launch(const float* src, int sD, int sH, int sW, float* dst,
 hipError_t adam_launch(float* x, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, int64_t step, hipStream_t st);
 
+// separable Gaussian smoothing: normalised taps w[0..2R], w[R] the centre
+constexpr int SMOOTH_MAX_R = 6;
+struct SmoothWeights {
+    float w[2 * SMOOTH_MAX_R + 1];
+};
+hipError_t smooth_launch(const float* in, float* out, int D, int H, int W, int channels, const SmoothWeights& w,
+                         int R, hipStream_t st);
+
 // 3x3x3 convolutions of the warm-start network
 struct ConvGeom {
     int N;

@@ -208,6 +208,19 @@ def adam_step(x, g, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
     return x
 
 
+
+def gaussian_smooth(src: torch.Tensor, sigma: float, out=None) -> torch.Tensor:
+    """Separable Gaussian smoothing of [C, D, H, W] or [D, H, W], taps to
+    radius ceil(3 sigma), edge replication (ffdp_gaussian_smooth)."""
+    squeeze = src.dim() == 3
+    s4 = src[None] if squeeze else src
+    _vol(s4, "src", 4)
+    o4 = torch.empty_like(s4) if out is None else out.view(s4.shape)
+    check("ffdp_gaussian_smooth", _lib.lib().ffdp_gaussian_smooth(_ptr(s4), _ptr(o4), s4.shape[1], s4.shape[2],
+                                                                   s4.shape[3], s4.shape[0], float(sigma),
+                                                                   _stream(src)))
+    return o4[0] if squeeze else o4
+
 # ------------------------------------------------------------ U-Net kernels --
 def _dev_t(t, name, dtype):
     if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous():

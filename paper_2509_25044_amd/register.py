@@ -1,13 +1,15 @@
 """Deformable registration driver: multi-scale pyramid, fused loss + adjoint,
 per-voxel Adam on the displacement, checkpoint/resume.
 
-The loop is the paper's registration iteration without the optional
-smoothing steps (Sec. "Grid Parallel" keeps optimiser states m1, m2 per
-voxel of the displacement; the experiments run per-scale iteration lists on
-image pyramids).  Every iteration is two library calls on the current HIP
-stream -- the fused loss+adjoint kernel and the Adam kernel -- and the loss
-of each iteration is written into a device buffer, so the loop never waits
-on the host.
+The loop is the paper's registration iteration (Sec. "Grid Parallel" keeps
+optimiser states m1, m2 per voxel of the displacement and smooths the
+gradient and the displacement; the experiments run per-scale iteration lists
+on image pyramids with sigma_grad = 1 and sigma_warp = 0.5 voxels).  Every
+iteration is library calls on the current HIP stream -- the fused
+loss+adjoint kernel, the optional Gaussian smoothing of the gradient, the
+Adam kernel, the optional smoothing of the displacement -- and the loss of
+each iteration is written into a device buffer, so the loop never waits on
+the host.  Smoothing is off by default (sigma 0).
 
 Pyramid: level factors f (e.g. 0.25, 0.5, 1.0) give shapes round(f * shape);
 images are resampled with the library's corner-aligned trilinear resize;
@@ -39,6 +41,8 @@ class RegConfig:
     adam_eps: float = 1e-8
     pad: str = "border"
     roi: Optional[tuple] = None          # full-resolution ROI; coarser levels use the full array
+    sigma_grad: float = 0.0              # Gaussian smoothing of dL/du before Adam (0 = off)
+    sigma_warp: float = 0.0              # Gaussian smoothing of u after Adam (0 = off)
 
 
 def level_shapes(shape: Sequence[int], levels: Sequence[float]) -> List[Tuple[int, int, int]]:
@@ -95,6 +99,7 @@ class Registration:
             raise ValueError("loss must be 'lncc' or 'mi'")
         self.cfg = cfg
         self.shapes = level_shapes(F.shape, cfg.levels)
+        self._tmp = {}  # smoothing output buffers, one per level shape
         self.F = []
         self.M = []
         for shp in self.shapes:
@@ -135,9 +140,23 @@ class Registration:
             _, state = ops.warp_mi_fwd(F, M, st.u, bins=c.bins, pad=c.pad, roi=self._roi(lv), loss=loss_out)
             grad = ops.warp_mi_bwd(F, M, st.u, state, bins=c.bins, pad=c.pad, roi=self._roi(lv), grad_u=grad)
         st.step += 1
-        ops.adam_step(st.u, grad, st.m, st.v, lr=c.lr, beta1=c.betas[0], beta2=c.betas[1], eps=c.adam_eps,
+        g = grad
+        if c.sigma_grad > 0:
+            g = ops.gaussian_smooth(grad, c.sigma_grad, out=self._buffer(st.u))
+        ops.adam_step(st.u, g, st.m, st.v, lr=c.lr, beta1=c.betas[0], beta2=c.betas[1], eps=c.adam_eps,
                       step=st.step)
+        if c.sigma_warp > 0:
+            key = tuple(st.u.shape)
+            su = ops.gaussian_smooth(st.u, c.sigma_warp, out=self._buffer(st.u))
+            self._tmp[key], st.u = st.u, su
         return grad
+
+    def _buffer(self, like: torch.Tensor) -> torch.Tensor:
+        key = tuple(like.shape)
+        b = self._tmp.get(key)
+        if b is None:
+            b = self._tmp[key] = torch.empty_like(like)
+        return b
 
     def evaluate(self, u: torch.Tensor, level: int = -1) -> float:
         """Loss of the current displacement at a level (host sync)."""

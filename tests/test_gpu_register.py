@@ -23,14 +23,17 @@ def c1():
 
 def test_lncc_registration_lowers_the_loss(c1):
     """50 plain Adam steps (lr 0.1, no smoothing) on the 64^3 pair: the loss
-    drops and the field stays finite and within lr * steps of the start."""
+    drops and the field stays finite and within Adam's step bound: with
+    (1 - b1) > sqrt(1 - b2) one step moves an element by at most
+    lr (1 - b1) / sqrt(1 - b2), about 3.16 lr."""
     print("[register c1 lncc 50 it]", flush=True)
     F, M, d = c1
     cfg = RegConfig(loss="lncc", window=5, iters=(50,), lr=0.1)
     st = register(F, M, cfg)
     losses = st.losses[0].cpu().numpy()
     assert losses[-1] < losses[0] - 1e-3, (losses[0], losses[-1])
-    assert torch.isfinite(st.u).all() and float(st.u.abs().max()) <= 0.1 * 50 + 1e-3
+    bound = 0.1 * 50 * (1 - 0.9) / (1 - 0.999) ** 0.5
+    assert torch.isfinite(st.u).all() and float(st.u.abs().max()) <= bound
 
 
 def test_mi_registration_on_multimodal_pair():
@@ -101,3 +104,63 @@ def test_adam_trajectory_matches_oracle():
     du = (ug - u)[mask]
     assert mask.mean() > 0.2
     assert np.linalg.norm(du) <= 1e-3 * np.linalg.norm(u[mask]), np.linalg.norm(du) / np.linalg.norm(u[mask])
+
+
+def test_smoothed_trajectory_matches_oracle():
+    """10 iterations with the paper's smoothing (sigma_grad 1, sigma_warp 0.5)
+    on a 20^3 pair against the oracle's loss, gradient, smoothing and Adam in
+    FP64, in the same order: smooth the gradient, Adam step, smooth u.  The
+    smoothed gradient has few near-zero elements, so u is compared over the
+    whole array; a 1e-5 relative perturbation of the oracle gradient moves u
+    by under 6e-4 in relative norm, applying the warp smoothing before the
+    Adam step instead of after moves it by about 5e-2."""
+    print("[register smoothed trajectory vs oracle]", flush=True)
+    spec = synth.PairSpec((20, 20, 20), (3.0, 5.0), 2.0)
+    p = synth.make_pair(spec, seed=2030)
+    F, M = p["F"], p["M"]
+    cfg = RegConfig(loss="lncc", window=5, iters=(10,), lr=0.05, sigma_grad=1.0, sigma_warp=0.5)
+    st = Registration(F.to(DEV), M.to(DEV), cfg).run()
+    gl = st.losses[0].cpu().numpy().astype(np.float64)
+    u = np.zeros((3, 20, 20, 20), np.float64)
+    m = np.zeros_like(u)
+    v = np.zeros_like(u)
+    Fn, Mn = F.numpy(), M.numpy()
+    for t in range(1, 11):
+        l, g = oracle.lncc(Fn, Mn, u.astype(np.float32), window=5, eps=1e-5)
+        assert abs(gl[t - 1] - l) <= 1e-4 * abs(l), (t, gl[t - 1], l)
+        gs = oracle.gaussian_smooth(g.astype(np.float32), 1.0)
+        oracle.adam(u.reshape(-1), np.ascontiguousarray(gs.reshape(-1)), m.reshape(-1), v.reshape(-1), lr=0.05,
+                    step=t)
+        u = oracle.gaussian_smooth(u.astype(np.float32), 0.5)
+    ug = st.u.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(ug - u) / np.linalg.norm(u)
+    assert rel <= 3e-3, rel
+
+
+def test_smoothing_regularises_the_field(c1):
+    """On the 64^3 pair with a known deformation, 50 LNCC iterations with the
+    paper's smoothing give a smoother field (lower mean squared forward
+    difference) that lies closer to the true inverse displacement than the
+    same run without smoothing.  (On these smooth blob images a 5^3 LNCC
+    window sees little of the true motion -- LNCC ignores the local offset a
+    shifted ramp produces -- so neither run gets closer than u = 0; the
+    oracle gives rms errors 1.28 plain and 1.12 smoothed against 0.76.)"""
+    print("[register smoothing vs plain, inverse error]", flush=True)
+    from paper_2509_25044_amd.warmstart import inverse_target
+    F, M, d = c1
+    tgt = inverse_target(d)
+    inner = (slice(None), slice(4, -4), slice(4, -4), slice(4, -4))
+
+    def err(u):
+        return float(torch.sqrt(((u - tgt)[inner] ** 2).mean()))
+
+    plain = register(F, M, RegConfig(loss="lncc", window=5, iters=(50,), lr=0.1))
+    smooth = register(F, M, RegConfig(loss="lncc", window=5, iters=(50,), lr=0.1, sigma_grad=1.0, sigma_warp=0.5))
+    def rough(u):
+        return sum(float((torch.diff(u, dim=a) ** 2).mean()) for a in (1, 2, 3))
+
+    e0, ep, es = err(torch.zeros_like(tgt)), err(plain.u), err(smooth.u)
+    print("inverse-field rms error: zero", e0, "plain", ep, "smoothed", es, flush=True)
+    assert es < ep, (e0, ep, es)
+    assert rough(smooth.u) < 0.5 * rough(plain.u), (rough(smooth.u), rough(plain.u))
+    assert smooth.losses[0][-1] < smooth.losses[0][0]
