@@ -18,12 +18,17 @@
 //    streams z slices through a pipeline of LDS stages;
 //  * stage A samples F and Mw on the tile plus a halo of 2r (r for the
 //    forward) and keeps the last w slices of every column in registers; for
-//    the tile's own voxel (one per thread) it also keeps dMw/dp, so the output stage never
-//    samples again.  It writes the five z-window sums to LDS;
+//    the tile's own voxel (one per thread) it also keeps dMw/dp in a
+//    thread-private LDS ring, so the output stage never samples again.  It
+//    writes the five z-window sums to LDS;
+//  * loads are software-pipelined over slices: the eight M corners, the
+//    cell fractions and F of slice z+1 are fetched while slice z goes
+//    through stages B-F, so stage A only interpolates;
 //  * stage B sums x-windows, stage C y-windows, forms A, B, C, the loss term
-//    and a, c, e; stages D/E box a, c, e in x, y and (register ring) z; stage
-//    F combines them with the stored F, Mw and dMw/dp of the slice 2r behind
-//    the sampling front and writes grad_u.
+//    and a, c, e; stage D boxes a, c, e in x; stage E boxes them in y and
+//    scatters F(zo) a - Mw(zo) c + e into the accumulators of the 2r+1
+//    pending output slices of the thread's column (the z-window), and the
+//    oldest one becomes grad_u with dMw/dp from the ring;
 //  * the x- and y-window passes read and write 2 floats per LDS access;
 //  * statistics use values shifted by a per-block constant (F and M at the
 //    tile centre).  With padded voxels shifted too, A, B, C and the adjoint
@@ -59,7 +64,13 @@ struct LnccTile {
     static constexpr int RB = Y2 * X1p / 2;          // 2-wide runs, stage B
     static constexpr int RC = Y1 * X1p / 2;          // 2-wide runs, stage C (adjoint mode)
     static constexpr int RD = Y1 * TX / 2;           // 2-wide runs, stage D
-    static constexpr int LDS_FLOATS = 5 * NA + 5 * NB;
+    static constexpr int NG = (MODE != MODE_FWD) ? 3 * WIN * NT : 0;  // dMw/dp ring, thread-private
+    // adjoint: the loss accumulator (one double per thread) also lives in LDS
+    static constexpr int NE = 0;
+    static constexpr int NL = (MODE == MODE_BWD) ? 2 * NT : 0;
+    static constexpr int OG = 5 * NA + 5 * NB;          // float offset of the thread-private rings
+    static constexpr int OL = (OG + NG + NE + 1) & ~1;  // float offset of the loss doubles
+    static constexpr int LDS_FLOATS = OL + NL;
     static_assert(TX * TY == NT, "one tile voxel per thread");
     static_assert(3 * NC <= 5 * NA && 3 * ND <= 5 * NB, "aliased LDS buffers must fit");
 };
@@ -85,12 +96,83 @@ __device__ __forceinline__ float2 xwin2(const float* row)
     return make_float2(o0, o1);
 }
 
-template <int PAD, bool DERIV, bool BIG>
-__device__ __forceinline__ Tri sample(const float* __restrict__ M, int D, int H, int W, int HW, int x, int y, int z,
-                                      float ux, float uy, float uz)
+// One load at element index idx: 32-bit byte offsets from the base unless BIG
+// (volumes of 2^30 voxels or more).
+template <bool BIG>
+__device__ __forceinline__ float ld(const float* __restrict__ base, unsigned idx)
 {
-    if (PAD == PAD_BORDER) return trilinear_clamped<DERIV, BIG>(M, D, H, W, HW, x, y, z, ux, uy, uz);
-    return trilinear<PAD_ZEROS, DERIV>(M, D, H, W, x, y, z, ux, uy, uz);
+    if (BIG) return base[idx];
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + idx * 4u);
+}
+
+template <bool BIG>
+__device__ __forceinline__ void st(float* __restrict__ base, unsigned idx, float v)
+{
+    if (BIG) base[idx] = v;
+    else *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + idx * 4u) = v;
+}
+
+// Loads of one stage-A point for one slice, issued a slice ahead of their use.
+// Border padding: the eight clamped M corners of the trilinear cell, the cell
+// fractions and the derivative flags (sample point exactly on index 0 of an
+// axis), plus F.  Zero padding: u and F only (the corners are fetched with
+// their validity masks when the slice is consumed).
+struct Pend {
+    float c[8];
+    float ax, ay, az;
+    unsigned fl;
+    float f;
+};
+
+template <int PAD, bool BIG>
+__device__ __forceinline__ void issue_point(Pend& g, const float* __restrict__ M, const float* __restrict__ F,
+                                            int D, int H, int W, int HW, int x, int y, int z, unsigned fidx,
+                                            float ux, float uy, float uz)
+{
+    g.f = ld<BIG>(F, fidx);
+    if (PAD != PAD_BORDER) {
+        g.c[0] = ux; g.c[1] = uy; g.c[2] = uz;
+        return;
+    }
+    const float fx = fminf(fmaxf(floorf(ux), -268435456.0f), 268435456.0f);
+    const float fy = fminf(fmaxf(floorf(uy), -268435456.0f), 268435456.0f);
+    const float fz = fminf(fmaxf(floorf(uz), -268435456.0f), 268435456.0f);
+    g.ax = ux - fx; g.ay = uy - fy; g.az = uz - fz;
+    const int ix = x + (int)fx, iy = y + (int)fy, iz = z + (int)fz;
+    const int x0 = min(max(ix, 0), W - 1), x1 = min(max(ix + 1, 0), W - 1);
+    const int y0 = min(max(iy, 0), H - 1), y1 = min(max(iy + 1, 0), H - 1);
+    const int z0 = min(max(iz, 0), D - 1), z1 = min(max(iz + 1, 0), D - 1);
+    const unsigned r00 = (unsigned)(z0 * HW + y0 * W), r01 = (unsigned)(z0 * HW + y1 * W);
+    const unsigned r10 = (unsigned)(z1 * HW + y0 * W), r11 = (unsigned)(z1 * HW + y1 * W);
+    g.c[0] = ld<BIG>(M, r00 + x0); g.c[1] = ld<BIG>(M, r00 + x1);
+    g.c[2] = ld<BIG>(M, r01 + x0); g.c[3] = ld<BIG>(M, r01 + x1);
+    g.c[4] = ld<BIG>(M, r10 + x0); g.c[5] = ld<BIG>(M, r10 + x1);
+    g.c[6] = ld<BIG>(M, r11 + x0); g.c[7] = ld<BIG>(M, r11 + x1);
+    g.fl = ((ix == 0 && g.ax == 0.0f) ? 1u : 0u) | ((iy == 0 && g.ay == 0.0f) ? 2u : 0u) |
+           ((iz == 0 && g.az == 0.0f) ? 4u : 0u);
+}
+
+// Value (and dvalue/dp) of a pending border-mode point; the same arithmetic
+// as trilinear_clamped.
+template <bool DERIV>
+__device__ __forceinline__ Tri interp_pending(const Pend& g)
+{
+    const float e00 = g.c[1] - g.c[0], e01 = g.c[3] - g.c[2], e10 = g.c[5] - g.c[4], e11 = g.c[7] - g.c[6];
+    const float c00 = fmaf(g.ax, e00, g.c[0]), c01 = fmaf(g.ax, e01, g.c[2]);
+    const float c10 = fmaf(g.ax, e10, g.c[4]), c11 = fmaf(g.ax, e11, g.c[6]);
+    const float f0 = c01 - c00, f1 = c11 - c10;
+    const float c0 = fmaf(g.ay, f0, c00), c1 = fmaf(g.ay, f1, c10);
+    Tri t;
+    t.v = fmaf(g.az, c1 - c0, c0);
+    if (DERIV) {
+        const float gx0 = fmaf(g.ay, e01 - e00, e00), gx1 = fmaf(g.ay, e11 - e10, e10);
+        t.dx = (g.fl & 1u) ? 0.0f : fmaf(g.az, gx1 - gx0, gx0);
+        t.dy = (g.fl & 2u) ? 0.0f : fmaf(g.az, f1 - f0, f0);
+        t.dz = (g.fl & 4u) ? 0.0f : (c1 - c0);
+    } else {
+        t.dx = t.dy = t.dz = 0.0f;
+    }
+    return t;
 }
 
 // Windows up to 5 are held to 128 VGPRs so two 512-thread blocks share a CU.
@@ -106,10 +188,12 @@ lncc_kernel(LnccArgs a)
     constexpr bool DER = (MODE != MODE_FWD);  // keep dMw/dp of the tile voxel
     constexpr float inv = 1.0f / float(WIN * WIN * WIN);
     __shared__ __attribute__((aligned(16))) float lds[T::LDS_FLOATS];
-    float* sA = lds;               // [5][Y2][X2p]  z-window sums
-    float* sB = lds + 5 * T::NA;   // [5][Y2][X1p]  + x-window
-    float* sC = lds;               // [3][Y1][X1p]  a, c, e (aliases sA)
-    float* sD = lds + 5 * T::NA;   // [3][Y1][TX]   x-window of a, c, e (aliases sB)
+    float* sA = lds;                           // [5][Y2][X2p]  z-window sums
+    float* sB = lds + 5 * T::NA;               // [5][Y2][X1p]  + x-window
+    float* sC = sA;                            // [3][Y1][X1p]  a, c, e (aliases sA)
+    float* sD = sB;                            // [3][Y1][TX]   x-window of a, c, e (aliases sB)
+    float* sG = lds + T::OG;                   // [WIN][3][NT] dMw/dp of each thread's voxel
+    double* sL = reinterpret_cast<double*>(lds + T::OL);  // [NT] loss accumulators (adjoint)
 
     const int D = a.D, H = a.H, W = a.W;
     const int HW = H * W;
@@ -150,9 +234,11 @@ lncc_kernel(LnccArgs a)
     const float eps = a.eps;
 
     float rF[1 + T::PH][WIN], rM[1 + T::PH][WIN];  // shifted F, Mw: last w slices
-    float rG[DER ? 3 : 1][WIN];                    // dMw/dp of the tile voxel
-    float rE[MODE == MODE_BWD ? 3 : 1][WIN];       // xy-windowed a, c, e of the tile voxel
+    float zacc[MODE == MODE_BWD ? WIN : 1];        // pending outputs of the tile column
+#pragma unroll
+    for (int q = 0; q < (MODE == MODE_BWD ? WIN : 1); ++q) zacc[q] = 0.f;
     double lsum = 0.0;
+    if (MODE == MODE_BWD) sL[tid] = 0.0;
 
     // stage-A points of this thread: k = 0 the tile voxel, k >= 1 halo points
     constexpr int P = 1 + T::PH;
@@ -167,22 +253,50 @@ lncc_kernel(LnccArgs a)
         pin[k] = lx >= 0 && pgx[k] >= 0 && pgx[k] < W && pgy[k] >= 0 && pgy[k] < H;
         pxy[k] = pin[k] ? pgy[k] * W + pgx[k] : 0;
     }
-    // u and F of the next slice are loaded one step ahead, so their HBM
-    // latency overlaps the LDS stages of the current slice.  Loads are
-    // unconditional (slice index clamped, off-array points read voxel 0) and
-    // the results are selected later, so the loop has no per-point branches.
-    float pu[P][3], pf[P];
-    auto prefetch = [&](int zs) {
-        const size_t zoff = (size_t)min(max(zs, 0), D - 1) * HW;
+    // Software pipeline over slices.  While slice zi is consumed, the loads
+    // of slice zi+1 (F and, for border padding, the eight M corners) and u of
+    // slice zi+2 are in flight, so HBM and L2 latency overlaps the LDS
+    // stages.  Every load is in bounds (slice index clamped, off-array
+    // points read voxel 0, corner indices clamped) and results are selected
+    // when consumed, so the loop has no per-point branches.
+    float pu[P][3];
+    Pend pend[P];
+    auto load_u = [&](int zs, int k0, int k1) {
+        const unsigned zoff = (unsigned)(min(max(zs, 0), D - 1) * HW);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const size_t idx = zoff + pxy[k];
-            pf[k] = F[idx];
-            if (U) { pu[k][0] = U[idx]; pu[k][1] = U[N + idx]; pu[k][2] = U[2 * N + idx]; }
-            else { pu[k][0] = 0.f; pu[k][1] = 0.f; pu[k][2] = 0.f; }
+        for (int k = k0; k < k1; ++k) {
+            if (k > 0 && hx[k - 1] < 0) continue;
+            if (U) {
+                pu[k][0] = ld<BIG>(U, zoff + pxy[k]);
+                pu[k][1] = ld<BIG>(U + N, zoff + pxy[k]);
+                pu[k][2] = ld<BIG>(U + 2 * N, zoff + pxy[k]);
+            } else {
+                pu[k][0] = 0.f; pu[k][1] = 0.f; pu[k][2] = 0.f;
+            }
         }
     };
-    prefetch(z0 - R2);
+    auto issue = [&](int zs, int k0, int k1) {  // uses pu = u of slice zs
+        const unsigned zoff = (unsigned)(min(max(zs, 0), D - 1) * HW);
+#pragma unroll
+        for (int k = k0; k < k1; ++k)
+            if (k == 0 || hx[k - 1] >= 0)
+                issue_point<PAD, BIG>(pend[k], M, F, D, H, W, HW, pgx[k], pgy[k], zs, zoff + pxy[k], pu[k][0],
+                                      pu[k][1], pu[k][2]);
+    };
+    // Schedule: the gathers of slice zi+1 are issued at the end of stage A of
+    // slice zi.  Forward and ANTs kernels load the u they need two slices
+    // ahead, in stage C of slice zi-1.  The adjoint kernel, whose registers
+    // are at the limit, loads the tile point's u at the start of stage A, and
+    // its halo points load u of zi+1 at the start of stage D and issue their
+    // gathers at the end of the slice (they are consumed after the tile point
+    // in the next stage A); this keeps them out of stages B and C, the peak
+    // of register pressure.  (Measured: the two-slice-ahead load slows the
+    // adjoint kernel by 9% and speeds the others.)
+    constexpr int KH = (MODE == MODE_BWD) ? 1 : P;  // points issued right after stage A
+    constexpr bool AHEAD2 = MODE != MODE_BWD;
+    load_u(z0 - R2, 0, P);
+    issue(z0 - R2, 0, P);
+    if (AHEAD2) load_u(z0 - R2 + 1, 0, KH);
 
     const int nsteps = (z1 - z0) + 2 * R2;
     for (int base = 0; base < nsteps; base += WIN) {
@@ -192,6 +306,7 @@ lncc_kernel(LnccArgs a)
             if (s >= nsteps) break;
             const int zi = z0 - R2 + s;  // slice entering the rings
             const bool zin = (zi >= 0) && (zi < D);
+            if (!AHEAD2) load_u(zi + 1, 0, KH);
             // ---- stage A: sample, push into the rings, z-window sums ----
 #pragma unroll
             for (int k = 0; k < P; ++k) {
@@ -199,18 +314,26 @@ lncc_kernel(LnccArgs a)
                     const bool ok = zin && pin[k];
                     float f = -sF, m = -sM;  // padded voxels are 0 before the shift
                     float d0 = 0.f, d1 = 0.f, d2 = 0.f;
+                    Tri t{0.f, 0.f, 0.f, 0.f};
+                    if (PAD == PAD_BORDER) {
+                        t = (DER && k == 0) ? interp_pending<DER>(pend[k]) : interp_pending<false>(pend[k]);
+                    } else if (ok) {
+                        t = (DER && k == 0)
+                                ? trilinear<PAD_ZEROS, DER>(M, D, H, W, pgx[k], pgy[k], zi, pend[k].c[0], pend[k].c[1], pend[k].c[2])
+                                : trilinear<PAD_ZEROS, false>(M, D, H, W, pgx[k], pgy[k], zi, pend[k].c[0], pend[k].c[1], pend[k].c[2]);
+                    }
                     if (ok) {
-                        f = pf[k] - sF;
-                        if (DER && k == 0) {
-                            const Tri t = sample<PAD, DER, BIG>(M, D, H, W, HW, pgx[k], pgy[k], zi, pu[k][0], pu[k][1], pu[k][2]);
-                            m = t.v - sM; d0 = t.dx; d1 = t.dy; d2 = t.dz;
-                        } else {
-                            m = sample<PAD, false, BIG>(M, D, H, W, HW, pgx[k], pgy[k], zi, pu[k][0], pu[k][1], pu[k][2]).v - sM;
-                        }
+                        f = pend[k].f - sF;
+                        m = t.v - sM;
+                        if (DER && k == 0) { d0 = t.dx; d1 = t.dy; d2 = t.dz; }
                     }
                     rF[k][j] = f;
                     rM[k][j] = m;
-                    if (DER && k == 0) { rG[0][j] = d0; rG[1][j] = d1; rG[2][j] = d2; }
+                    if (DER && k == 0) {
+                        sG[(j * 3 + 0) * NT + tid] = d0;
+                        sG[(j * 3 + 1) * NT + tid] = d1;
+                        sG[(j * 3 + 2) * NT + tid] = d2;
+                    }
                     if (s >= 2 * r) {
                         float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
 #pragma unroll
@@ -233,8 +356,15 @@ lncc_kernel(LnccArgs a)
                     }
                 }
             }
-            prefetch(zi + 1);
-            if (s < 2 * r) continue;  // rings not yet full (uniform over the block)
+            issue(zi + 1, 0, KH);
+            if (s < 2 * r) {  // rings not yet full (uniform over the block)
+                if (AHEAD2) load_u(zi + 2, 0, KH);
+                if (KH < P) {
+                    load_u(zi + 1, KH, P);
+                    issue(zi + 1, KH, P);
+                }
+                continue;
+            }
             __syncthreads();
             // ---- stage B: x-window, 2 outputs per thread ----
             for (int q = tid; q < T::RB; q += NT) {
@@ -246,6 +376,7 @@ lncc_kernel(LnccArgs a)
             }
             __syncthreads();
             // ---- stage C: y-window, statistics, loss term, adjoint fields ----
+            if (AHEAD2) load_u(zi + 2, 0, KH);
             const int zc = zi - r;
             const bool zroi = zc >= a.roi[0] && zc < a.roi[1];
             const bool zown = zc >= z0 && zc < z1;
@@ -269,6 +400,7 @@ lncc_kernel(LnccArgs a)
                     const bool yroi = zroi && gy >= a.roi[2] && gy < a.roi[3];
                     const bool yown = zown && ly >= R1 && ly < R1 + TY;
                     float oa[2], oc[2], oe[2];
+                    float lpart = 0.f;
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
                         const int lx = lx0 + e;
@@ -281,12 +413,17 @@ lncc_kernel(LnccArgs a)
                         const float rD = __builtin_amdgcn_rcpf(fmaf(B, C, eps));  // 1 ulp reciprocal
                         float ac = 0.f, cc = 0.f, ec = 0.f;
                         if (inroi) {
-                            if (yown && lx >= R1 && lx < R1 + TX) lsum += (double)(A * A * rD);
+                            if (yown && lx >= R1 && lx < R1 + TX) lpart += A * A * rD;
                             ac = 2.0f * gi * A * rD;
                             cc = ac * A * B * rD;
                             ec = fmaf(cc, mm, -ac * mf);
                         }
                         oa[e] = ac; oc[e] = cc; oe[e] = ec;
+                    }
+                    if (lpart != 0.f) {
+                        int t = tid;
+                        asm volatile("" : "+v"(t));  // recompute the slot address here
+                        sL[t] += (double)lpart;
                     }
                     const int o = ly * X1p + lx0;
                     *reinterpret_cast<float2*>(sC + 0 * T::NC + o) = make_float2(oa[0], oa[1]);
@@ -319,16 +456,19 @@ lncc_kernel(LnccArgs a)
                         const float ac = 2.0f * gi * A * rD;
                         const float cc = ac * A * B * rD;
                         const float gm = ac * (rF[0][sl] - mf) - cc * (rM[0][sl] - mm);
-                        g0 = gm * rG[0][sl]; g1 = gm * rG[1][sl]; g2 = gm * rG[2][sl];
+                        g0 = gm * sG[(sl * 3 + 0) * NT + tid];
+                        g1 = gm * sG[(sl * 3 + 1) * NT + tid];
+                        g2 = gm * sG[(sl * 3 + 2) * NT + tid];
                     }
-                    const size_t idx = (size_t)zc * HW + (size_t)gy * W + gx;
-                    a.gu[idx] = g0;
-                    a.gu[N + idx] = g1;
-                    a.gu[2 * N + idx] = g2;
+                    const unsigned idx = (unsigned)(zc * HW + gy * W + gx);
+                    st<BIG>(a.gu, idx, g0);
+                    st<BIG>(a.gu + N, idx, g1);
+                    st<BIG>(a.gu + 2 * N, idx, g2);
                 }
             }
             if (MODE != MODE_BWD) continue;
             __syncthreads();
+            load_u(zi + 1, KH, P);
             // ---- stage D: x-window of a, c, e ----
             for (int q = tid; q < T::RD; q += NT) {
                 const int ly = q / (TX / 2), lx0 = 2 * (q - ly * (TX / 2));
@@ -338,37 +478,40 @@ lncc_kernel(LnccArgs a)
                         xwin2<WIN, T::NV>(sC + c * T::NC + ly * X1p + lx0);
             }
             __syncthreads();
-            // ---- stages E/F: y-window into the ring, z-window, gradient ----
+            // ---- stages E/F: y-window, z-window by scatter, gradient ----
+            // The xy-windowed a, c, e of slice zc enter the pending outputs
+            // zo = zc - r .. zc + r of the thread's column, each as
+            // F(zo) a - Mw(zo) c + e with that output's own (shifted) F and Mw
+            // from the ring, so the z-window needs one accumulator per pending
+            // output slice instead of a ring per field.
             {
                 const int zo = zc - r;
                 const int so = (j + 1) % WIN;  // ring slot of slice zo (the oldest)
+                float ya = 0.f, yc = 0.f, ye = 0.f;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float acc = 0.f;
-#pragma unroll
-                    for (int d = 0; d < WIN; ++d) acc += sD[c * T::ND + (iy + d) * TX + ix];
-                    rE[c][j] = acc;
+                for (int d = 0; d < WIN; ++d) {
+                    ya += sD[0 * T::ND + (iy + d) * TX + ix];
+                    yc += sD[1 * T::ND + (iy + d) * TX + ix];
+                    ye += sD[2 * T::ND + (iy + d) * TX + ix];
                 }
+#pragma unroll
+                for (int q = 0; q < WIN; ++q) zacc[q] = fmaf(rF[0][q], ya, fmaf(-rM[0][q], yc, zacc[q] + ye));
                 const int gx = gx0 + ix, gy = gy0 + iy;
                 if (s >= 4 * r && zo >= z0 && zo < z1 && gx < W && gy < H) {
-                    float ba = 0.f, bc = 0.f, be = 0.f;
-#pragma unroll
-                    for (int q = 0; q < WIN; ++q) {
-                        ba += rE[0][q];
-                        bc += rE[1][q];
-                        be += rE[2][q];
-                    }
-                    const float gm = (rF[0][so] * ba - rM[0][so] * bc + be) * inv;
-                    const size_t idx = (size_t)zo * HW + (size_t)gy * W + gx;
-                    a.gu[idx] = gm * rG[0][so];
-                    a.gu[N + idx] = gm * rG[1][so];
-                    a.gu[2 * N + idx] = gm * rG[2][so];
+                    const float gm = zacc[so] * inv;
+                    const unsigned idx = (unsigned)(zo * HW + gy * W + gx);
+                    st<BIG>(a.gu, idx, gm * sG[(so * 3 + 0) * NT + tid]);
+                    st<BIG>(a.gu + N, idx, gm * sG[(so * 3 + 1) * NT + tid]);
+                    st<BIG>(a.gu + 2 * N, idx, gm * sG[(so * 3 + 2) * NT + tid]);
                 }
+                zacc[so] = 0.f;  // the slot of the next new pending output
             }
+            issue(zi + 1, KH, P);
         }
     }
     // ---- block loss partial (fixed-order tree) ----
     __syncthreads();
+    if (MODE == MODE_BWD) lsum = sL[tid];
     double tot = block_sum<NT>(lsum, reinterpret_cast<double*>(lds));
     if (tid == 0) a.partial[blockIdx.x] = tot;
 }
