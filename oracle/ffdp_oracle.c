@@ -342,7 +342,14 @@ int orc_lncc_grad_u_at(const float* F, const float* M, const float* u, i64 D, i6
 /* units of the bin width, kappa_m(v) = beta3(s - m) with s = clamp(v,0,1) B  */
 /* - 1/2.  Support falling outside [0, B-1] is folded onto the edge bin so   */
 /* that sum_m kappa_m(v) = 1 for every v.  omega = d kappa / dv.             */
-/* hard: kappa_m(v) = 1[m = min(floor(v B), B-1)] (box kernel, omega = 0).   */
+/* hard = 1: kappa_m(v) = 1[m = min(floor(v B), B-1)] (box kernel, omega = 0). */
+/* hard = 2: the paper's approximate estimator (App. "Implicit MI", An        */
+/* approximate histogram estimator): every sample counts once in its bin     */
+/* min(floor(v B), B-1); the count histogram, divided by the sample count,   */
+/* is convolved in both axes with kappa evaluated at bin-centre offsets,     */
+/* K[m][m'] = kappa_m(b_m') (folded like kappa).  The gradient uses the      */
+/* soft kernel's kappa and omega at the sample values with dL/dp taken at    */
+/* the approximate p; where p[m][n] = 0, log p - log pM is taken as 0.       */
 /* ------------------------------------------------------------------------ */
 static double beta3(double t)
 {
@@ -398,6 +405,39 @@ int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, 
     double* dM = grad_u ? (double*)malloc(sizeof(double) * 3 * N) : NULL;
     orc_warp(M, u, D, H, W, pad, Mw, dM);
     double* p = (double*)calloc((size_t)B * B, sizeof(double));
+    const int approx = hard == 2;
+    if (approx) hard = 0; /* soft kernel for the gradient */
+    if (approx) {
+        double* cnt = (double*)calloc((size_t)B * B, sizeof(double));
+        for (i64 z = R[0]; z < R[1]; ++z)
+            for (i64 y = R[2]; y < R[3]; ++y)
+                for (i64 x = R[4]; x < R[5]; ++x) {
+                    i64 k = AT(z, y, x);
+                    double vf = (double)F[k], vm = Mw[k];
+                    vf = vf < 0.0 ? 0.0 : (vf > 1.0 ? 1.0 : vf);
+                    vm = vm < 0.0 ? 0.0 : (vm > 1.0 ? 1.0 : vm);
+                    i64 m = (i64)floor(vf * B), nn = (i64)floor(vm * B);
+                    if (m > B - 1) m = B - 1;
+                    if (nn > B - 1) nn = B - 1;
+                    cnt[m * B + nn] += 1.0;
+                }
+        /* K[m][j] = kappa_m(b_j), then p = K (cnt / N) K^T */
+        double* K = (double*)malloc(sizeof(double) * B * B);
+        double* kc = (double*)malloc(sizeof(double) * B);
+        double* oc = (double*)malloc(sizeof(double) * B);
+        for (int j = 0; j < B; ++j) {
+            parzen_all(((double)j + 0.5) / (double)B, B, 0, kc, oc);
+            for (int m = 0; m < B; ++m) K[m * B + j] = kc[m];
+        }
+        for (int m = 0; m < B; ++m)
+            for (int nn = 0; nn < B; ++nn) {
+                double acc = 0.0;
+                for (int a = 0; a < B; ++a)
+                    for (int b = 0; b < B; ++b) acc += K[m * B + a] * K[nn * B + b] * cnt[a * B + b];
+                p[m * B + nn] = acc;
+            }
+        free(cnt); free(K); free(kc); free(oc);
+    } else {
 #pragma omp parallel
     {
         double* pl = (double*)calloc((size_t)B * B, sizeof(double));
@@ -420,6 +460,7 @@ int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, 
 #pragma omp critical
         for (int q = 0; q < B * B; ++q) p[q] += pl[q];
         free(pl); free(kf); free(km); free(of); free(om);
+    }
     }
     for (int q = 0; q < B * B; ++q) p[q] /= nroi;
     double* pF = (double*)calloc(B, sizeof(double));
@@ -454,7 +495,9 @@ int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, 
                                 for (int nn = 0; nn < B; ++nn) {
                                     double wgt = kf[m] * om[nn];
                                     if (wgt == 0.0) continue;
-                                    double dmi = log(p[m * B + nn]) - log(pF[m]) - log(pM[nn]) - 1.0;
+                                    const double q = p[m * B + nn];
+                                    const double t = q > 0.0 ? log(q) - log(pM[nn]) : 0.0;
+                                    double dmi = t - log(pF[m]) - 1.0;
                                     s += -wgt / nroi * dmi;
                                 }
                         }

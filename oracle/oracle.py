@@ -119,8 +119,10 @@ def lncc_grad_u_at(F, M, u, idx, roi=None, window: int = 5, eps: float = 1e-5, a
     return out
 
 
-def mi(F, M, u=None, roi=None, bins: int = 32, hard: bool = False, pad: int = 0, with_grad: bool = True):
-    """(loss = -MI, joint PMF p[B][B], dloss/du or None)."""
+def mi(F, M, u=None, roi=None, bins: int = 32, hard: int = 0, pad: int = 0, with_grad: bool = True):
+    """(loss = -MI, joint PMF p[B][B], dloss/du or None).  hard: 0 exact
+    Parzen, 1 box kernel, 2 the approximate estimator (hard-bin counts
+    convolved with the kernel)."""
     lib = load()
     F, M, u = _f32(F), _f32(M), _f32(u)
     D, H, W = F.shape
