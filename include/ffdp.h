@@ -79,7 +79,14 @@ typedef struct ffdp_lncc_params {
  *  bins      B in [8, 64]; bin centres (m + 1/2)/B on [0, 1]; intensities
  *            are clamped to [0, 1].  The kernel is the cubic B-spline of one
  *            bin width; support beyond the first/last bin folds onto it.
- *  hard_bins 1: box kernel (one bin per voxel, zero gradient) — test mode.
+ *  hard_bins 0: the Parzen estimate above.
+ *            1: box kernel (one bin per voxel, zero gradient) — test mode.
+ *            2: the approximate estimator (App. "Implicit MI implementation",
+ *               approximate histogram estimator): each voxel counts once in
+ *               bin min(floor(v B), B-1) (fp32); the count histogram over the
+ *               ROI is normalised and convolved with the kernel at bin-centre
+ *               offsets (taps 1/6, 2/3, 1/6, folded like the kernel).  The
+ *               backward pass is the hard_bins = 0 one evaluated with this p.
  *  pad_mode  as for LNCC. */
 typedef struct ffdp_mi_params {
     int32_t bins;

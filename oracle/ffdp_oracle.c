@@ -366,14 +366,23 @@ static double dbeta3(double t)
     return 0.0;
 }
 
+/* Hard bin of a value already clamped to [0, 1]: min(floor(v B), B-1), with
+ * v B formed in fp32, the precision of the device kernels, so that both
+ * sides take the same integer decision for the same fp32 value. */
+static i64 hard_bin(double vc, int B)
+{
+    const float t = (float)vc * (float)B;
+    i64 m = (i64)floorf(t);
+    return m > B - 1 ? B - 1 : m;
+}
+
 /* kappa_m(v) and omega_m(v) for every m in [0, B). */
 static void parzen_all(double v, int B, int hard, double* kap, double* om)
 {
     for (int m = 0; m < B; ++m) { kap[m] = 0.0; om[m] = 0.0; }
     double vc = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
     if (hard) {
-        i64 m = (i64)floor(vc * B);
-        if (m > B - 1) m = B - 1;
+        i64 m = hard_bin(vc, B);
         kap[m] = 1.0;
         return;
     }
@@ -416,10 +425,7 @@ int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, 
                     double vf = (double)F[k], vm = Mw[k];
                     vf = vf < 0.0 ? 0.0 : (vf > 1.0 ? 1.0 : vf);
                     vm = vm < 0.0 ? 0.0 : (vm > 1.0 ? 1.0 : vm);
-                    i64 m = (i64)floor(vf * B), nn = (i64)floor(vm * B);
-                    if (m > B - 1) m = B - 1;
-                    if (nn > B - 1) nn = B - 1;
-                    cnt[m * B + nn] += 1.0;
+                    cnt[hard_bin(vf, B) * B + hard_bin((double)(float)vm, B)] += 1.0;
                 }
         /* K[m][j] = kappa_m(b_j), then p = K (cnt / N) K^T */
         double* K = (double*)malloc(sizeof(double) * B * B);

@@ -73,7 +73,7 @@ int check_mi(const ffdp_mi_params* p)
 {
     if (!p) return fail(FFDP_ERR_NULL, "mi params are NULL");
     if (p->bins < 8 || p->bins > 64) return fail(FFDP_ERR_PARAM, "bins must be in [8, 64] (got %d)", p->bins);
-    if (p->hard_bins != 0 && p->hard_bins != 1) return fail(FFDP_ERR_PARAM, "hard_bins must be 0 or 1");
+    if (p->hard_bins < 0 || p->hard_bins > 2) return fail(FFDP_ERR_PARAM, "hard_bins must be 0, 1 or 2");
     if (p->pad_mode != FFDP_PAD_BORDER && p->pad_mode != FFDP_PAD_ZEROS)
         return fail(FFDP_ERR_PARAM, "pad_mode must be 0 (border) or 1 (zeros)");
     if (p->reserved != 0) return fail(FFDP_ERR_PARAM, "reserved must be 0");

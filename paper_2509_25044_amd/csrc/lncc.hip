@@ -52,8 +52,12 @@ struct LnccTile {
     static constexpr int R1 = (MODE == MODE_BWD) ? r : 0;      // stage-C halo
     static constexpr int X2 = TX + 2 * R2, Y2 = TY + 2 * R2;
     static constexpr int X1 = TX + 2 * R1, Y1 = TY + 2 * R1;
-    static constexpr int X1p = round4(X1);           // LDS row pitch of x-windowed data
-    static constexpr int X2p = round4(X1p + 2 * r);  // LDS row pitch of stage-A data
+    // One LDS row pitch for stage-A data and its x-windowed copy, so that the
+    // 2-wide runs of stages B and C map consecutive lanes to consecutive
+    // addresses (no bank conflicts where a wave crosses rows).  Runs past X1
+    // read the next row and produce values that are never used.
+    static constexpr int X2p = round4(X2 > X1 + 2 * r ? X2 : X1 + 2 * r);
+    static constexpr int X1p = X2p;
     static constexpr int NV = (WIN + 2) / 2;         // float2 reads per 2-wide x-window run
     static constexpr int NA = Y2 * X2p;              // floats per channel, stage A
     static constexpr int NB = Y2 * X1p;              // x-window

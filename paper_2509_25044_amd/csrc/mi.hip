@@ -21,6 +21,14 @@
 // then forms p, the marginals, MI and the log table T.
 // Backward: T in LDS, 4 x 4 weighted lookups per voxel, then the sampler's
 // derivative; grad_u written over the whole array (zero outside the ROI).
+//
+// Approximate forward (App. "Implicit MI implementation", the approximate
+// histogram estimator): each voxel adds one count to its hard bin pair
+// (min(floor(v B), B-1) in fp32) -- runs of equal bin pairs along a column
+// are merged in a register before the LDS atomic -- and the one-block
+// finalize convolves the count histogram with the kernel at bin-centre
+// offsets (taps 1/6, 2/3, 1/6, folded at the edges) before forming p.  Its
+// backward is the exact one above, fed with the approximate p.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -134,6 +142,140 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
         if (v) atomicAdd(&ghist[q], v);
     }
     if (threadIdx.x == 0 && nanflag) atomicOr(gflag, 1ull);
+}
+
+template <int PAD>
+__global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long long* __restrict__ ghist,
+                                                         unsigned long long* __restrict__ gflag)
+{
+    extern __shared__ unsigned int cnt[];  // [B*B]
+    const int B = a.bins, BB = B * B;
+    for (int q = threadIdx.x; q < BB; q += MI_NT) cnt[q] = 0u;
+    __shared__ int nanflag;
+    if (threadIdx.x == 0) nanflag = 0;
+    __syncthreads();
+
+    const int bid = xcd_remap(blockIdx.x, a.nblocks);
+    const int tx = bid % a.ntx, rest = bid / a.ntx, ty = rest % a.nty, ch = rest / a.nty;
+    const int x = a.roi[4] + tx * MI_TX + (threadIdx.x % MI_TX);
+    const int y = a.roi[2] + ty * MI_TY + (threadIdx.x / MI_TX);
+    const int zb = a.roi[0] + ch * a.zchunk;
+    const int ze = min(a.roi[1], zb + a.zchunk);
+    const int H = a.H, W = a.W, HW = H * W;
+    const size_t N = (size_t)a.D * HW;
+    const bool active = x < a.roi[5] && y < a.roi[3];
+    const float fB = (float)B;
+    int cur = -1;
+    unsigned run = 0u;
+    bool bad = false;
+    if (active) {
+        for (int z = zb; z < ze; ++z) {
+            const int idx = z * HW + y * W + x;
+            float ux = 0.f, uy = 0.f, uz = 0.f;
+            if (a.u) { ux = a.u[idx]; uy = a.u[N + idx]; uz = a.u[2 * N + idx]; }
+            const float fv = a.F[idx];
+            const float mv = trilinear<PAD, false>(a.M, a.D, H, W, x, y, z, ux, uy, uz).v;
+            bad |= (fv != fv) || (mv != mv);
+            const int bf = min((int)floorf(fminf(fmaxf(fv, 0.0f), 1.0f) * fB), B - 1);
+            const int bm = min((int)floorf(fminf(fmaxf(mv, 0.0f), 1.0f) * fB), B - 1);
+            const int q = bf * B + bm;
+            if (q != cur) {
+                if (run) atomicAdd(&cnt[cur], run);
+                cur = q;
+                run = 0u;
+            }
+            ++run;
+        }
+        if (run) atomicAdd(&cnt[cur], run);
+    }
+    if (bad) nanflag = 1;
+    __syncthreads();
+    for (int q = threadIdx.x; q < BB; q += MI_NT) {
+        const unsigned int v = cnt[q];
+        if (v) atomicAdd(&ghist[q], (unsigned long long)v);
+    }
+    if (threadIdx.x == 0 && nanflag) atomicOr(gflag, 1ull);
+}
+
+// Weight that bin m receives from a sample at the centre of bin j (cubic
+// B-spline taps 2/3 at the centre and 1/6 at distance one, folded at the
+// edges like the soft kernel).
+__device__ __forceinline__ double centre_tap(int m, int j, int B)
+{
+    double w = 0.0;
+#pragma unroll
+    for (int off = -1; off <= 1; ++off)
+        if (fold(j + off, B) == m) w += off == 0 ? 2.0 / 3.0 : 1.0 / 6.0;
+    return w;
+}
+
+// One block: the approximate PMF p = K (counts / total) K^T, marginals, MI and
+// the log table, with the same state layout as mi_finalize.
+__global__ void __launch_bounds__(1024) mi_finalize_approx(const unsigned long long* __restrict__ hist,
+                                                           const unsigned long long* __restrict__ flag, int B,
+                                                           float* __restrict__ state, float* __restrict__ loss)
+{
+    __shared__ double P[64 * 64];
+    __shared__ double pF[64], pM[64];
+    __shared__ unsigned long long rowsum[64];
+    __shared__ double red[1024];
+    const int BB = B * B;
+    for (int t = threadIdx.x; t < B; t += 1024) {
+        unsigned long long rs = 0;
+        for (int n = 0; n < B; ++n) rs += hist[t * B + n];
+        rowsum[t] = rs;
+    }
+    __syncthreads();
+    unsigned long long total = 0;
+    for (int t = 0; t < B; ++t) total += rowsum[t];
+    const double sc = total ? 1.0 / (double)total : 0.0;
+    for (int q = threadIdx.x; q < BB; q += 1024) {
+        const int m = q / B, n = q - m * B;
+        double acc = 0.0;
+        for (int i = max(m - 1, 0); i <= min(m + 1, B - 1); ++i) {
+            const double wi = centre_tap(m, i, B);
+            if (wi == 0.0) continue;
+            double row = 0.0;
+            for (int j = max(n - 1, 0); j <= min(n + 1, B - 1); ++j)
+                row += centre_tap(n, j, B) * (double)hist[i * B + j];
+            acc += wi * row;
+        }
+        P[q] = acc * sc;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < B; t += 1024) {
+        double rf = 0.0, cm = 0.0;
+        for (int n = 0; n < B; ++n) { rf += P[t * B + n]; cm += P[n * B + t]; }
+        pF[t] = rf;
+        pM[t] = cm;
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int q = threadIdx.x; q < BB; q += 1024) {
+        const int m = q / B, n = q - m * B;
+        const double p = P[q];
+        float tv = 0.0f;
+        if (p > 0.0) {
+            part += p * log(p / (pF[m] * pM[n]));
+            tv = (float)(log(p) - log(pM[n]));
+        }
+        state[q] = tv;
+        state[BB + q] = (float)p;
+    }
+    for (int t = threadIdx.x; t < B; t += 1024) {
+        state[2 * BB + t] = (float)pF[t];
+        state[2 * BB + B + t] = (float)pM[t];
+    }
+    const double mi = block_sum<1024>(part, red);
+    if (threadIdx.x == 0) {
+        const float l = (*flag) ? __int_as_float(0x7fc00000) : (float)(-mi);
+        float* hdr = state + 2 * BB + 2 * B;
+        hdr[0] = l;
+        hdr[1] = (float)mi;
+        hdr[2] = (float)B;
+        for (int k = 3; k < 16; ++k) hdr[k] = 0.0f;  // reserved
+        *loss = l;
+    }
 }
 
 __global__ void __launch_bounds__(256) mi_zero(unsigned long long* p, int n)
@@ -273,6 +415,15 @@ hipError_t mi_fwd_launch(const MiArgs& a, int hard, int pad, unsigned long long*
     if (e != hipSuccess) return e;
     const size_t lds = sizeof(unsigned long long) * BB;
     dim3 grid(a.nblocks), block(MI_NT);
+    if (hard == 2) {
+        const size_t lds32 = sizeof(unsigned int) * BB;
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_count_kernel<PAD_BORDER>), grid, block, lds32, st, a, hist, flag);
+        else hipLaunchKernelGGL((mi_count_kernel<PAD_ZEROS>), grid, block, lds32, st, a, hist, flag);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(mi_finalize_approx, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, state, loss);
+        return hipGetLastError();
+    }
     if (hard) {
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER>), grid, block, lds, st, a, hist, flag);
         else hipLaunchKernelGGL((mi_hist_kernel<true, PAD_ZEROS>), grid, block, lds, st, a, hist, flag);
@@ -292,7 +443,7 @@ hipError_t mi_bwd_launch(const MiArgs& a, int hard, int pad, const float* state,
     const size_t lds = sizeof(float) * a.bins * a.bins;
     dim3 grid(a.nblocks), block(MI_NT);
     const float nin = (float)(-1.0 / nroi);
-    if (hard) {
+    if (hard == 1) {
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<true, PAD_BORDER>), grid, block, lds, st, a, state, grad_scale, nin, gu);
         else hipLaunchKernelGGL((mi_grad_kernel<true, PAD_ZEROS>), grid, block, lds, st, a, state, grad_scale, nin, gu);
     } else {

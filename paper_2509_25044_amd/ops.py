@@ -90,9 +90,16 @@ def lncc_params(window=5, eps=1e-5, ants=False, pad="border") -> LnccParams:
     return p
 
 
+MI_ESTIMATORS = {"parzen": 0, "box": 1, "approx": 2}
+
+
 def mi_params(bins=32, hard=False, pad="border") -> MiParams:
+    """hard: False/"parzen" exact Parzen window, True/"box" box kernel (test
+    mode), "approx" the approximate estimator (hard-bin counts convolved
+    with the kernel; exact-kernel backward)."""
     p = MiParams()
-    p.bins, p.hard_bins, p.pad_mode, p.reserved = int(bins), int(bool(hard)), PAD[pad], 0
+    mode = MI_ESTIMATORS[hard] if isinstance(hard, str) else int(bool(hard))
+    p.bins, p.hard_bins, p.pad_mode, p.reserved = int(bins), mode, PAD[pad], 0
     return p
 
 

@@ -118,7 +118,7 @@ def test_lncc_bwd_validation(L):
                                 1 << 20, None) == 3
 
 
-@pytest.mark.parametrize("mp,code", [(_mp(bins=7), 3), (_mp(bins=65), 3), (_mp(hard=2), 3), (_mp(pad=5), 3),
+@pytest.mark.parametrize("mp,code", [(_mp(bins=7), 3), (_mp(bins=65), 3), (_mp(hard=3), 3), (_mp(hard=-1), 3), (_mp(pad=5), 3),
                                      (_mp(reserved=1), 3)])
 def test_mi_validation(L, mp, code):
     g = _grid()

@@ -77,7 +77,7 @@ def test_trained_network_gives_a_head_start():
         e_zero = float(torch.sqrt((tgt ** 2).mean()))
         gains.append(e_zero - e_net)
         r = time_to_target(model, p["F"], p["M"], RegConfig(loss="lncc", window=5, levels=(0.5, 1.0), iters=(60,),
-                                                             lr=0.1), max_iters=120)
+                                                             lr=0.1))
         print(k, e_net, e_zero, r, flush=True)
         res.append(r)
     assert sum(gains) > 0, gains
