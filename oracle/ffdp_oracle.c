@@ -398,21 +398,17 @@ static void parzen_all(double v, int B, int hard, double* kap, double* om)
     }
 }
 
-/* MI of (F, Mw) over the ROI; loss = -MI.  p [B][B] (row: F bin m, column:
- * Mw bin n) receives the joint PMF if non-NULL.  If grad_u != NULL it gets
- * dloss/du over the whole array (zero outside the ROI):
+/* MI of (F, Mw) over the ROI for an already warped Mw; loss = -MI.  p [B][B]
+ * (row: F bin m, column: Mw bin n) receives the joint PMF if non-NULL.  If
+ * dldmw != NULL it gets dloss/dMw over the whole array (zero outside the ROI):
  *   dMI/dp[m][n] = ln p[m][n] - ln pF[m] - ln pM[n] - 1   (marginals as sums)
  *   dp[m][n]/dMw_k = kappa_m(F_k) omega_n(Mw_k) / N_roi                     */
-int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, const i64* roi,
-           int B, int hard, int pad, double* loss, double* p_out, double* grad_u)
+static int mi_core(const float* F, const double* Mw, i64 D, i64 H, i64 W, const i64* roi, int B, int hard,
+                   double* loss, double* p_out, double* dldmw)
 {
-    const i64 N = D * H * W;
     i64 R[6];
     roi_or_full(roi, D, H, W, R);
     const double nroi = (double)((R[1] - R[0]) * (R[3] - R[2]) * (R[5] - R[4]));
-    double* Mw = (double*)malloc(sizeof(double) * N);
-    double* dM = grad_u ? (double*)malloc(sizeof(double) * 3 * N) : NULL;
-    orc_warp(M, u, D, H, W, pad, Mw, dM);
     double* p = (double*)calloc((size_t)B * B, sizeof(double));
     const int approx = hard == 2;
     if (approx) hard = 0; /* soft kernel for the gradient */
@@ -481,7 +477,7 @@ int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, 
         }
     if (loss) *loss = -mi;
     if (p_out) memcpy(p_out, p, sizeof(double) * B * B);
-    if (grad_u) {
+    if (dldmw) {
 #pragma omp parallel
         {
             double* kf = (double*)malloc(sizeof(double) * B);
@@ -507,15 +503,122 @@ int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, 
                                     s += -wgt / nroi * dmi;
                                 }
                         }
-                        grad_u[k] = s * dM[k];
-                        grad_u[N + k] = s * dM[N + k];
-                        grad_u[2 * N + k] = s * dM[2 * N + k];
+                        dldmw[k] = s;
                     }
             free(kf); free(km); free(of); free(om);
         }
     }
-    free(p); free(pF); free(pM); free(Mw);
+    free(p); free(pF); free(pM);
+    return 0;
+}
+
+
+int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, const i64* roi,
+           int B, int hard, int pad, double* loss, double* p_out, double* grad_u)
+{
+    const i64 N = D * H * W;
+    double* Mw = (double*)malloc(sizeof(double) * N);
+    double* dM = grad_u ? (double*)malloc(sizeof(double) * 3 * N) : NULL;
+    double* s = grad_u ? (double*)malloc(sizeof(double) * N) : NULL;
+    orc_warp(M, u, D, H, W, pad, Mw, dM);
+    mi_core(F, Mw, D, H, W, roi, B, hard, loss, p_out, s);
+    if (grad_u)
+        for (i64 k = 0; k < N; ++k) {
+            grad_u[k] = s[k] * dM[k];
+            grad_u[N + k] = s[k] * dM[N + k];
+            grad_u[2 * N + k] = s[k] * dM[2 * N + k];
+        }
+    free(Mw);
     if (dM) free(dM);
+    if (s) free(s);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O7. Composite implicit grid sampler (Sec. "Composite Implicit Grid        */
+/* Sampler", the affine form of Alg. gridsampler): the sample point of the   */
+/* target voxel X = (x, y, z) is p(X) = A X + t + S u(X), in voxel units,    */
+/* A and S row-major 3x3 acting on (x, y, z) components; out(X) = M(p(X)).   */
+/* Adjoint for an upstream gradient gout(X) = dL/dout(X):                    */
+/*   dL/du(X) = S^T g(X),  dL/dA = sum_X g(X) X^T,  dL/dt = sum_X g(X),       */
+/*   g(X) = gout(X) dM/dp(p(X)).                                             */
+/* ------------------------------------------------------------------------ */
+static void affine_point(const double* A, const double* t, const double* S, const float* u, i64 N, i64 k,
+                         i64 x, i64 y, i64 z, double p[3])
+{
+    const double X[3] = {(double)x, (double)y, (double)z};
+    double uu[3] = {0.0, 0.0, 0.0};
+    if (u) { uu[0] = (double)u[k]; uu[1] = (double)u[N + k]; uu[2] = (double)u[2 * N + k]; }
+    for (int i = 0; i < 3; ++i)
+        p[i] = A[3 * i] * X[0] + A[3 * i + 1] * X[1] + A[3 * i + 2] * X[2] + t[i] +
+               S[3 * i] * uu[0] + S[3 * i + 1] * uu[1] + S[3 * i + 2] * uu[2];
+}
+
+int orc_warp_affine(const float* M, const float* u, i64 D, i64 H, i64 W, const double* A, const double* t,
+                    const double* S, int pad, double* out, double* dout)
+{
+    const i64 N = D * H * W;
+#pragma omp parallel for schedule(static)
+    for (i64 z = 0; z < D; ++z)
+        for (i64 y = 0; y < H; ++y)
+            for (i64 x = 0; x < W; ++x) {
+                const i64 k = AT(z, y, x);
+                double p[3], dv[3];
+                affine_point(A, t, S, u, N, k, x, y, z, p);
+                out[k] = sample_point(M, D, H, W, p, pad, dv);
+                if (dout) { dout[k] = dv[0]; dout[N + k] = dv[1]; dout[2 * N + k] = dv[2]; }
+            }
+    return 0;
+}
+
+/* dL/du (nullable) and gAt[12] = (dL/dA row-major, dL/dt) from gout [N] and
+ * the sampler derivative dM [3][N]. */
+static void affine_adjoint(const double* S, const double* gout, const double* dM, i64 D, i64 H, i64 W,
+                           double* grad_u, double* gAt)
+{
+    const i64 N = D * H * W;
+    for (int q = 0; q < 12; ++q) gAt[q] = 0.0;
+    for (i64 z = 0; z < D; ++z)
+        for (i64 y = 0; y < H; ++y)
+            for (i64 x = 0; x < W; ++x) {
+                const i64 k = AT(z, y, x);
+                const double X[3] = {(double)x, (double)y, (double)z};
+                const double g[3] = {gout[k] * dM[k], gout[k] * dM[N + k], gout[k] * dM[2 * N + k]};
+                for (int i = 0; i < 3; ++i) {
+                    for (int j = 0; j < 3; ++j) gAt[3 * i + j] += g[i] * X[j];
+                    gAt[9 + i] += g[i];
+                }
+                if (grad_u)
+                    for (int j = 0; j < 3; ++j)
+                        grad_u[j * N + k] = S[j] * g[0] + S[3 + j] * g[1] + S[6 + j] * g[2];
+            }
+}
+
+int orc_warp_affine_bwd(const float* M, const float* u, i64 D, i64 H, i64 W, const double* A, const double* t,
+                        const double* S, int pad, const double* gout, double* grad_u, double* gAt)
+{
+    const i64 N = D * H * W;
+    double* out = (double*)malloc(sizeof(double) * N);
+    double* dM = (double*)malloc(sizeof(double) * 3 * N);
+    orc_warp_affine(M, u, D, H, W, A, t, S, pad, out, dM);
+    affine_adjoint(S, gout, dM, D, H, W, grad_u, gAt);
+    free(out); free(dM);
+    return 0;
+}
+
+/* MI of (F, M(A X + t + S u)) with loss, PMF and the adjoint to u, A, t. */
+int orc_mi_affine(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, const i64* roi,
+                  const double* A, const double* t, const double* S, int B, int hard, int pad, double* loss,
+                  double* p_out, double* grad_u, double* gAt)
+{
+    const i64 N = D * H * W;
+    double* Mw = (double*)malloc(sizeof(double) * N);
+    double* dM = (double*)malloc(sizeof(double) * 3 * N);
+    double* s = (double*)malloc(sizeof(double) * N);
+    orc_warp_affine(M, u, D, H, W, A, t, S, pad, Mw, dM);
+    mi_core(F, Mw, D, H, W, roi, B, hard, loss, p_out, s);
+    if (gAt) affine_adjoint(S, s, dM, D, H, W, grad_u, gAt);
+    free(Mw); free(dM); free(s);
     return 0;
 }
 

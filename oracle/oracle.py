@@ -41,11 +41,15 @@ def load():
     lib.orc_adam.argtypes = [vp, vp, vp, vp, _i64, C.c_double, C.c_double, C.c_double, C.c_double, _i64]
     lib.orc_resample.argtypes = [vp, _i64, _i64, _i64, vp, _i64, _i64, _i64, C.c_int, C.c_double]
     lib.orc_gaussian_smooth.argtypes = [vp, _i64, _i64, _i64, C.c_int, C.c_double, vp]
+    lib.orc_warp_affine.argtypes = [vp, vp, _i64, _i64, _i64, vp, vp, vp, C.c_int, vp, vp]
+    lib.orc_warp_affine_bwd.argtypes = [vp, vp, _i64, _i64, _i64, vp, vp, vp, C.c_int, vp, vp, vp]
+    lib.orc_mi_affine.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, vp, vp,
+                                  vp, vp]
     lib.orc_conv3d_fwd.argtypes = [vp, vp, vp, vp] + [_i64] * 9 + [C.c_int, C.c_double, vp]
     lib.orc_conv3d_bwd_data.argtypes = [vp, vp] + [_i64] * 8 + [vp]
     lib.orc_conv3d_bwd_weight.argtypes = [vp, vp, vp] + [_i64] * 9 + [vp, vp]
     for f in ("orc_warp", "orc_lncc", "orc_lncc_grad_u_at", "orc_mi", "orc_parzen", "orc_adam", "orc_resample",
-              "orc_gaussian_smooth", "orc_conv3d_fwd", "orc_conv3d_bwd_data", "orc_conv3d_bwd_weight"):
+              "orc_gaussian_smooth", "orc_warp_affine", "orc_warp_affine_bwd", "orc_mi_affine", "orc_conv3d_fwd", "orc_conv3d_bwd_data", "orc_conv3d_bwd_weight"):
         getattr(lib, f).restype = C.c_int
     _LIB = lib
     return lib
@@ -179,6 +183,56 @@ def gaussian_smooth(src, sigma: float):
     if lib.orc_gaussian_smooth(_ptr(src), D, H, W, Cn, float(sigma), _ptr(out)) != 0:
         raise ValueError("sigma must be > 0")
     return out[0] if squeeze else out
+
+
+def _affine3(A, t, S):
+    A = np.ascontiguousarray(np.eye(3) if A is None else A, dtype=np.float64).reshape(9)
+    t = np.ascontiguousarray(np.zeros(3) if t is None else t, dtype=np.float64).reshape(3)
+    S = np.ascontiguousarray(np.eye(3) if S is None else S, dtype=np.float64).reshape(9)
+    return A, t, S
+
+
+def warp_affine(M, u=None, A=None, t=None, S=None, pad: int = 0, with_grad: bool = False):
+    """M(A X + t + S u(X)), X = (x, y, z) voxel coordinates -> float64 [D][H][W]
+    (and dM/dp [3][D][H][W] at the sample points if with_grad)."""
+    lib = load()
+    M, u = _f32(M), _f32(u)
+    D, H, W = M.shape
+    A, t, S = _affine3(A, t, S)
+    out = np.empty((D, H, W), np.float64)
+    d = np.empty((3, D, H, W), np.float64) if with_grad else None
+    lib.orc_warp_affine(_ptr(M), _ptr(u), D, H, W, _ptr(A), _ptr(t), _ptr(S), pad, _ptr(out), _ptr(d))
+    return (out, d) if with_grad else out
+
+
+def warp_affine_bwd(M, gout, u=None, A=None, t=None, S=None, pad: int = 0):
+    """(dL/du [3][D][H][W], dL/dA [3][3], dL/dt [3]) for the upstream gradient gout [D][H][W]."""
+    lib = load()
+    M, u = _f32(M), _f32(u)
+    D, H, W = M.shape
+    A, t, S = _affine3(A, t, S)
+    gout = np.ascontiguousarray(gout, dtype=np.float64)
+    gu = np.empty((3, D, H, W), np.float64)
+    gAt = np.empty(12, np.float64)
+    lib.orc_warp_affine_bwd(_ptr(M), _ptr(u), D, H, W, _ptr(A), _ptr(t), _ptr(S), pad, _ptr(gout), _ptr(gu),
+                            _ptr(gAt))
+    return gu, gAt[:9].reshape(3, 3), gAt[9:]
+
+
+def mi_affine(F, M, u=None, A=None, t=None, S=None, roi=None, bins: int = 32, hard: int = 0, pad: int = 0):
+    """MI of (F, M(A X + t + S u)): (loss, p, dL/du, dL/dA [3][3], dL/dt [3])."""
+    lib = load()
+    F, M, u = _f32(F), _f32(M), _f32(u)
+    D, H, W = F.shape
+    A, t, S = _affine3(A, t, S)
+    r = _roi(roi)
+    loss = np.zeros(1, np.float64)
+    p = np.empty((bins, bins), np.float64)
+    gu = np.empty((3, D, H, W), np.float64)
+    gAt = np.empty(12, np.float64)
+    lib.orc_mi_affine(_ptr(F), _ptr(M), _ptr(u), D, H, W, _ptr(r), _ptr(A), _ptr(t), _ptr(S), bins, int(hard), pad,
+                      _ptr(loss), _ptr(p), _ptr(gu), _ptr(gAt))
+    return float(loss[0]), p, gu, gAt[:9].reshape(3, 3), gAt[9:]
 
 def _f64(a):
     if a is None:
