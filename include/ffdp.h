@@ -160,6 +160,55 @@ int ffdp_warp_mi_bwd(const float* F, const float* M, const float* u, const ffdp_
                      const float* mi_state, const float* grad_scale, float* grad_u, void* ws, size_t ws_bytes,
                      void* stream);
 
+/* Affine part of the composite implicit grid sampler (Sec. "Composite
+ * Implicit Grid Sampler"): the sample point of target voxel X = (x, y, z) is
+ *   p(X) = A X + t + S u(X)       (voxel units; A, S row-major 3x3 acting on
+ *                                  (x, y, z) and (u_x, u_y, u_z) components)
+ * A = S = I, t = 0 is the identity sampler of the other entry points.  All
+ * values must be finite. */
+typedef struct ffdp_affine {
+    float A[9];
+    float t[3];
+    float S[9];
+} ffdp_affine;
+
+/* Bytes of the caller workspace for the composite-sampler adjoints
+ * (per-block partial sums of dL/dA and dL/dt; grows with the block count). */
+size_t ffdp_affine_workspace_bytes(const ffdp_grid* g);
+
+/* Composite sampler forward: out(X) = M(p(X)) by trilinear interpolation
+ * (eq. interp), never materialising p.  M, out [D][H][W]; u [3][D][H][W] or
+ * NULL (affine only); the ROI fields of g are ignored. */
+int ffdp_warp_affine(const float* M, const float* u, const ffdp_grid* g, const ffdp_affine* aff, int32_t pad_mode,
+                     float* out, void* stream);
+
+/* Composite sampler adjoint for an upstream gradient gout = dL/dout
+ * [D][H][W] (the affine form of Alg. gridsampler Backward):
+ *   grad_u(X) = S^T g(X)  with g(X) = gout(X) dM/dp(p(X))   (skipped if NULL)
+ *   grad_At[0..8] = sum_X g(X) X^T (dL/dA, row-major), grad_At[9..11] = sum_X g(X)
+ * grad_At: 12 device doubles, overwritten, summed in a fixed order
+ * (bitwise reproducible).  ws: ffdp_affine_workspace_bytes(g), 8-byte aligned. */
+int ffdp_warp_affine_bwd(const float* M, const float* u, const ffdp_grid* g, const ffdp_affine* aff,
+                         int32_t pad_mode, const float* gout, float* grad_u, double* grad_At, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* Warp + MI forward through the composite sampler (the affine MI stage of
+ * the paper's pipeline): as ffdp_warp_mi_fwd with Mw(X) = M(p(X)).
+ * ws: ffdp_mi_workspace_bytes. */
+int ffdp_warp_mi_affine_fwd(const float* F, const float* M, const float* u, const ffdp_grid* g,
+                            const ffdp_affine* aff, const ffdp_mi_params* p, float* loss, float* mi_state, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* MI adjoint through the composite sampler: grad_u (nullable) as
+ * ffdp_warp_mi_bwd times S^T, grad_At (12 device doubles) = dL/dA, dL/dt
+ * as in ffdp_warp_affine_bwd with gout = dL/dMw.  mi_state from
+ * ffdp_warp_mi_affine_fwd with the same arguments.
+ * ws: ffdp_affine_workspace_bytes(g). */
+int ffdp_warp_mi_affine_bwd(const float* F, const float* M, const float* u, const ffdp_grid* g,
+                            const ffdp_affine* aff, const ffdp_mi_params* p, const float* mi_state,
+                            const float* grad_scale, float* grad_u, double* grad_At, void* ws, size_t ws_bytes,
+                            void* stream);
+
 /* Per-element Adam with bias correction, the optimiser with first and second
  * moment states that the paper shards with the displacement (Sec. "Grid
  * Parallel"), in place on x, m, v over n elements:

@@ -30,6 +30,10 @@ class MiParams(C.Structure):
     _fields_ = [("bins", C.c_int32), ("hard_bins", C.c_int32), ("pad_mode", C.c_int32), ("reserved", C.c_int32)]
 
 
+class Affine(C.Structure):
+    _fields_ = [("A", C.c_float * 9), ("t", C.c_float * 3), ("S", C.c_float * 9)]
+
+
 class ConvGeom(C.Structure):
     _fields_ = [("N", C.c_int32), ("Di", C.c_int32), ("Hi", C.c_int32), ("Wi", C.c_int32), ("Ca", C.c_int32),
                 ("Cb", C.c_int32), ("Cout", C.c_int32), ("stride", C.c_int32), ("ups", C.c_int32)]
@@ -56,6 +60,7 @@ def lib():
     vp, i32, i64, f32, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
     gp, lp, mp = C.POINTER(Grid), C.POINTER(LnccParams), C.POINTER(MiParams)
     cg = C.POINTER(ConvGeom)
+    ap = C.POINTER(Affine)
     sig = {
         "ffdp_version": ([], C.c_int),
         "ffdp_status_string": ([C.c_int], C.c_char_p),
@@ -69,6 +74,11 @@ def lib():
         "ffdp_warp_lncc_bwd": ([vp, vp, vp, gp, lp, vp, vp, vp, vp, sz, vp], C.c_int),
         "ffdp_warp_mi_fwd": ([vp, vp, vp, gp, mp, vp, vp, vp, sz, vp], C.c_int),
         "ffdp_warp_mi_bwd": ([vp, vp, vp, gp, mp, vp, vp, vp, vp, sz, vp], C.c_int),
+        "ffdp_affine_workspace_bytes": ([gp], sz),
+        "ffdp_warp_affine": ([vp, vp, gp, ap, i32, vp, vp], C.c_int),
+        "ffdp_warp_affine_bwd": ([vp, vp, gp, ap, i32, vp, vp, vp, vp, sz, vp], C.c_int),
+        "ffdp_warp_mi_affine_fwd": ([vp, vp, vp, gp, ap, mp, vp, vp, vp, sz, vp], C.c_int),
+        "ffdp_warp_mi_affine_bwd": ([vp, vp, vp, gp, ap, mp, vp, vp, vp, vp, vp, sz, vp], C.c_int),
         "ffdp_adam_step": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i64, vp], C.c_int),
         "ffdp_gaussian_smooth": ([vp, vp, i64, i64, i64, i32, f32, vp], C.c_int),
         "ffdp_conv3d_fwd": ([vp, vp, vp, vp, cg, i32, f32, vp, vp, vp], C.c_int),

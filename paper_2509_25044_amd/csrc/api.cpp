@@ -159,15 +159,19 @@ int lncc_common(const float* F, const float* M, const float* u, const ffdp_grid*
     return FFDP_OK;
 }
 
+size_t affine_ws(const ffdp_grid* g);
+
+// ws_kind 0: the MI histogram workspace (forward); 1: the affine partials
+// (composite-sampler adjoint).
 int mi_common(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_mi_params* p,
-              void* ws, size_t ws_bytes, MiArgs& a)
+              void* ws, size_t ws_bytes, MiArgs& a, int ws_kind = 0)
 {
     int s = check_grid(g);
     if (s) return s;
     if ((s = check_mi(p))) return s;
     if ((s = check_ptrs("F,M", 2, (const void*)F, (const void*)M))) return s;
     if ((s = check_opt_ptr(u, "u"))) return s;
-    const size_t need = mi_ws(p);
+    const size_t need = ws_kind ? affine_ws(g) : mi_ws(p);
     if (!ws || ws_bytes < need)
         return fail(FFDP_ERR_WORKSPACE, "workspace of %zu bytes required (got %zu%s)", need, ws_bytes,
                     ws ? "" : ", NULL");
@@ -176,6 +180,36 @@ int mi_common(const float* F, const float* M, const float* u, const ffdp_grid* g
     a.D = (int)g->D; a.H = (int)g->H; a.W = (int)g->W;
     fill_roi(g, a.roi);
     a.bins = p->bins;
+    a.affine = 0;
+    a.aff = Affine{};
+    a.apart = nullptr;
+    return FFDP_OK;
+}
+
+// Validated device form of the composite sampler's affine part.
+int affine_from(const ffdp_affine* f, Affine& o)
+{
+    if (!f) return fail(FFDP_ERR_NULL, "affine is NULL");
+    for (int i = 0; i < 9; ++i)
+        if (!isfinite(f->A[i]) || !isfinite(f->S[i])) return fail(FFDP_ERR_PARAM, "A and S must be finite");
+    for (int i = 0; i < 3; ++i)
+        if (!isfinite(f->t[i])) return fail(FFDP_ERR_PARAM, "t must be finite");
+    for (int i = 0; i < 9; ++i) {
+        o.Am[i] = (float)((double)f->A[i] - (i % 4 == 0 ? 1.0 : 0.0));
+        o.S[i] = f->S[i];
+    }
+    for (int i = 0; i < 3; ++i) o.t[i] = f->t[i];
+    return FFDP_OK;
+}
+
+size_t affine_ws(const ffdp_grid* g) { return (size_t)12 * sizeof(double) * mi_plan((int)g->D, (int)g->H, (int)g->W).nblocks; }
+
+int check_ws(void* ws, size_t ws_bytes, size_t need)
+{
+    if (!ws || ws_bytes < need)
+        return fail(FFDP_ERR_WORKSPACE, "workspace of %zu bytes required (got %zu%s)", need, ws_bytes,
+                    ws ? "" : ", NULL");
+    if (((uintptr_t)ws) & 7u) return fail(FFDP_ERR_ALIGN, "workspace must be 8-byte aligned");
     return FFDP_OK;
 }
 
@@ -310,6 +344,93 @@ int ffdp_warp_mi_bwd(const float* F, const float* M, const float* u, const ffdp_
     return hip_status(mi_bwd_launch(a, p->hard_bins, p->pad_mode, mi_state, grad_scale, grad_u, roi_voxels(g),
                                     (hipStream_t)stream),
                       "ffdp_warp_mi_bwd");
+}
+
+size_t ffdp_affine_workspace_bytes(const ffdp_grid* g)
+{
+    if (!g || g->D < 1 || g->H < 1 || g->W < 1) return 0;
+    return affine_ws(g);
+}
+
+int ffdp_warp_affine(const float* M, const float* u, const ffdp_grid* g, const ffdp_affine* aff, int32_t pad_mode,
+                     float* out, void* stream)
+{
+    if (!g) return fail(FFDP_ERR_NULL, "grid is NULL");
+    int s = check_dims(g->D, g->H, g->W);
+    if (s) return s;
+    if (pad_mode != FFDP_PAD_BORDER && pad_mode != FFDP_PAD_ZEROS)
+        return fail(FFDP_ERR_PARAM, "pad_mode must be 0 (border) or 1 (zeros)");
+    if ((s = check_ptrs("M,out", 2, (const void*)M, (const void*)out))) return s;
+    if ((s = check_opt_ptr(u, "u"))) return s;
+    if (out == M) return fail(FFDP_ERR_PARAM, "out must not alias M");
+    Affine f;
+    if ((s = affine_from(aff, f))) return s;
+    return hip_status(warp_affine_launch(M, u, (int)g->D, (int)g->H, (int)g->W, f, pad_mode, out,
+                                         (hipStream_t)stream),
+                      "ffdp_warp_affine");
+}
+
+int ffdp_warp_affine_bwd(const float* M, const float* u, const ffdp_grid* g, const ffdp_affine* aff,
+                         int32_t pad_mode, const float* gout, float* grad_u, double* grad_At, void* ws,
+                         size_t ws_bytes, void* stream)
+{
+    if (!g) return fail(FFDP_ERR_NULL, "grid is NULL");
+    int s = check_dims(g->D, g->H, g->W);
+    if (s) return s;
+    if (pad_mode != FFDP_PAD_BORDER && pad_mode != FFDP_PAD_ZEROS)
+        return fail(FFDP_ERR_PARAM, "pad_mode must be 0 (border) or 1 (zeros)");
+    if ((s = check_ptrs("M,gout", 2, (const void*)M, (const void*)gout))) return s;
+    if ((s = check_opt_ptr(u, "u"))) return s;
+    if ((s = check_opt_ptr(grad_u, "grad_u"))) return s;
+    if (!grad_At) return fail(FFDP_ERR_NULL, "grad_At is NULL");
+    if (((uintptr_t)grad_At) & 7u) return fail(FFDP_ERR_ALIGN, "grad_At must be 8-byte aligned");
+    if ((s = check_ws(ws, ws_bytes, affine_ws(g)))) return s;
+    Affine f;
+    if ((s = affine_from(aff, f))) return s;
+    return hip_status(warp_affine_bwd_launch(M, u, (int)g->D, (int)g->H, (int)g->W, f, pad_mode, gout, grad_u,
+                                             (double*)ws, grad_At, (hipStream_t)stream),
+                      "ffdp_warp_affine_bwd");
+}
+
+int ffdp_warp_mi_affine_fwd(const float* F, const float* M, const float* u, const ffdp_grid* g,
+                            const ffdp_affine* aff, const ffdp_mi_params* p, float* loss, float* mi_state, void* ws,
+                            size_t ws_bytes, void* stream)
+{
+    MiArgs a;
+    int s = mi_common(F, M, u, g, p, ws, ws_bytes, a);
+    if (s) return s;
+    if ((s = check_ptrs("loss,mi_state", 2, (const void*)loss, (const void*)mi_state))) return s;
+    if ((s = affine_from(aff, a.aff))) return s;
+    a.affine = 1;
+    MiLaunch L = mi_plan(a.roi[1] - a.roi[0], a.roi[3] - a.roi[2], a.roi[5] - a.roi[4]);
+    a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk; a.nblocks = L.nblocks;
+    return hip_status(mi_fwd_launch(a, p->hard_bins, p->pad_mode, (unsigned long long*)ws, mi_state, loss,
+                                    roi_voxels(g), (hipStream_t)stream),
+                      "ffdp_warp_mi_affine_fwd");
+}
+
+int ffdp_warp_mi_affine_bwd(const float* F, const float* M, const float* u, const ffdp_grid* g,
+                            const ffdp_affine* aff, const ffdp_mi_params* p, const float* mi_state,
+                            const float* grad_scale, float* grad_u, double* grad_At, void* ws, size_t ws_bytes,
+                            void* stream)
+{
+    MiArgs a;
+    int s = mi_common(F, M, u, g, p, ws, ws_bytes, a, 1);
+    if (s) return s;
+    if ((s = check_ptrs("mi_state", 1, (const void*)mi_state))) return s;
+    if ((s = check_opt_ptr(grad_scale, "grad_scale"))) return s;
+    if ((s = check_opt_ptr(grad_u, "grad_u"))) return s;
+    if (!grad_At) return fail(FFDP_ERR_NULL, "grad_At is NULL");
+    if (((uintptr_t)grad_At) & 7u) return fail(FFDP_ERR_ALIGN, "grad_At must be 8-byte aligned");
+    if ((s = affine_from(aff, a.aff))) return s;
+    a.affine = 1;
+    a.apart = (double*)ws;
+    MiLaunch L = mi_plan(a.D, a.H, a.W);
+    a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk; a.nblocks = L.nblocks;
+    hipError_t e = mi_bwd_launch(a, p->hard_bins, p->pad_mode, mi_state, grad_scale, grad_u, roi_voxels(g),
+                                 (hipStream_t)stream);
+    if (e == hipSuccess) e = affine_reduce_launch(a.apart, a.nblocks, grad_At, (hipStream_t)stream);
+    return hip_status(e, "ffdp_warp_mi_affine_bwd");
 }
 
 int ffdp_adam_step(float* x, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,

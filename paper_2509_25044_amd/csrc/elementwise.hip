@@ -31,6 +31,115 @@ hipError_t warp_launch(const float* M, const float* u, int D, int H, int W, int 
     return hipGetLastError();
 }
 
+// Composite implicit sampler, forward: out(X) = M(X + Am X + t + S u(X)).
+template <int PAD>
+__global__ void __launch_bounds__(256) warp_affine_kernel(const float* __restrict__ M, const float* __restrict__ u,
+                                                          int D, int H, int W, Affine f, float* __restrict__ out)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int y = blockIdx.y;
+    const int HW = H * W;
+    const size_t N = (size_t)D * HW;
+    if (x >= W) return;
+    for (int z = blockIdx.z; z < D; z += gridDim.z) {
+        const int idx = z * HW + y * W + x;
+        float ux = 0.f, uy = 0.f, uz = 0.f;
+        if (u) { ux = u[idx]; uy = u[N + idx]; uz = u[2 * N + idx]; }
+        float dx, dy, dz;
+        affine_disp(f, x, y, z, ux, uy, uz, dx, dy, dz);
+        out[idx] = trilinear<PAD, false>(M, D, H, W, x, y, z, dx, dy, dz).v;
+    }
+}
+
+hipError_t warp_affine_launch(const float* M, const float* u, int D, int H, int W, const Affine& f, int pad,
+                              float* out, hipStream_t st)
+{
+    dim3 grid((W + 255) / 256, H, D < 64 ? D : 64), block(256);
+    if (pad == PAD_BORDER) hipLaunchKernelGGL((warp_affine_kernel<PAD_BORDER>), grid, block, 0, st, M, u, D, H, W, f, out);
+    else hipLaunchKernelGGL((warp_affine_kernel<PAD_ZEROS>), grid, block, 0, st, M, u, D, H, W, f, out);
+    return hipGetLastError();
+}
+
+// Composite sampler adjoint for an upstream gradient gout: dL/du = S^T g
+// (written when gu is given), and per-block partial sums of g X^T and g,
+// g = gout dM/dp, in the MI tiling (64 x 4 columns, z-chunks).
+template <int PAD>
+__global__ void __launch_bounds__(MI_NT) warp_affine_bwd_kernel(const float* __restrict__ M,
+                                                                const float* __restrict__ u, int D, int H, int W,
+                                                                Affine f, const float* __restrict__ gout,
+                                                                float* __restrict__ gu, double* __restrict__ part,
+                                                                int ntx, int nty, int zchunk, int nblocks)
+{
+    const int bid = xcd_remap(blockIdx.x, nblocks);
+    const int tx = bid % ntx, rest = bid / ntx, ty = rest % nty, ch = rest / nty;
+    const int x = tx * MI_TX + (threadIdx.x % MI_TX);
+    const int y = ty * MI_TY + (threadIdx.x / MI_TX);
+    const int zb = ch * zchunk, ze = min(D, zb + zchunk);
+    const int HW = H * W;
+    const size_t N = (size_t)D * HW;
+    const bool active = x < W && y < H;
+    double acc[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+    for (int z = zb; active && z < ze; ++z) {
+        const int idx = z * HW + y * W + x;
+        float ux = 0.f, uy = 0.f, uz = 0.f;
+        if (u) { ux = u[idx]; uy = u[N + idx]; uz = u[2 * N + idx]; }
+        float dx, dy, dz;
+        affine_disp(f, x, y, z, ux, uy, uz, dx, dy, dz);
+        const Tri t = trilinear<PAD, true>(M, D, H, W, x, y, z, dx, dy, dz);
+        const float go = gout[idx];
+        float gx, gy, gz;
+        affine_adjoint(f, x, y, z, go * t.dx, go * t.dy, go * t.dz, acc, gx, gy, gz);
+        if (gu) {
+            gu[idx] = gx;
+            gu[N + idx] = gy;
+            gu[2 * N + idx] = gz;
+        }
+    }
+    __shared__ double red[MI_NT];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const double v = block_sum<MI_NT>(acc[q], red);
+        if (threadIdx.x == 0) part[12 * (size_t)blockIdx.x + q] = v;
+    }
+}
+
+// out[q] = sum_b part[12 b + q] in a fixed order (one block of 256 threads)
+__global__ void __launch_bounds__(256) affine_reduce_kernel(const double* __restrict__ part, int nblocks,
+                                                            double* __restrict__ out)
+{
+    __shared__ double red[256];
+    for (int q = 0; q < 12; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += 256) s += part[12 * (size_t)b + q];
+        s = block_sum<256>(s, red);
+        if (threadIdx.x == 0) out[q] = s;
+    }
+}
+
+hipError_t affine_reduce_launch(const double* part, int nblocks, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(affine_reduce_kernel, dim3(1), dim3(256), 0, st, part, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t warp_affine_bwd_launch(const float* M, const float* u, int D, int H, int W, const Affine& f, int pad,
+                                  const float* gout, float* gu, double* part, double* gAt, hipStream_t st)
+{
+    const MiLaunch L = mi_plan(D, H, W);
+    dim3 grid(L.nblocks), block(MI_NT);
+    if (pad == PAD_BORDER)
+        hipLaunchKernelGGL((warp_affine_bwd_kernel<PAD_BORDER>), grid, block, 0, st, M, u, D, H, W, f, gout, gu, part,
+                           L.ntx, L.nty, L.zchunk, L.nblocks);
+    else
+        hipLaunchKernelGGL((warp_affine_bwd_kernel<PAD_ZEROS>), grid, block, 0, st, M, u, D, H, W, f, gout, gu, part,
+                           L.ntx, L.nty, L.zchunk, L.nblocks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return affine_reduce_launch(part, L.nblocks, gAt, st);
+}
+
 // Corner-aligned trilinear resize: dst j samples src at j (n_s - 1)/(n_d - 1).
 __global__ void __launch_bounds__(256) resample_kernel(const float* __restrict__ src, int sD, int sH, int sW,
                                                        float* __restrict__ dst, int dD, int dH, int dW, float fz,

@@ -32,6 +32,47 @@ struct LnccLaunch {
 LnccLaunch lncc_plan(int D, int H, int W);
 hipError_t lncc_launch(int mode, int win, int pad, const LnccArgs& a, float* loss, double nroi, hipStream_t st);
 
+// Composite sampler, affine part: the sample point of voxel X = (x, y, z) is
+// X + d with d = Am X + t + S u(X) and Am = A - I formed on the host in
+// double, so that the identity transform gives d = u exactly.
+struct Affine {
+    float Am[9];  // row-major, acting on (x, y, z)
+    float t[3];
+    float S[9];   // row-major, acting on (u_x, u_y, u_z)
+};
+
+__device__ __forceinline__ void affine_disp(const Affine& f, int x, int y, int z, float ux, float uy, float uz,
+                                            float& dx, float& dy, float& dz)
+{
+    const float X = (float)x, Y = (float)y, Z = (float)z;
+    dx = fmaf(f.Am[0], X, fmaf(f.Am[1], Y, fmaf(f.Am[2], Z, f.t[0]))) + fmaf(f.S[0], ux, fmaf(f.S[1], uy, f.S[2] * uz));
+    dy = fmaf(f.Am[3], X, fmaf(f.Am[4], Y, fmaf(f.Am[5], Z, f.t[1]))) + fmaf(f.S[3], ux, fmaf(f.S[4], uy, f.S[5] * uz));
+    dz = fmaf(f.Am[6], X, fmaf(f.Am[7], Y, fmaf(f.Am[8], Z, f.t[2]))) + fmaf(f.S[6], ux, fmaf(f.S[7], uy, f.S[8] * uz));
+}
+
+// Adjoint of the affine part for one voxel: with g = dL/dMw dMw/dp, adds
+// g X^T to acc[0..8] (row-major dL/dA) and g to acc[9..11] (dL/dt), and
+// returns S^T g (dL/du) in gx, gy, gz.
+__device__ __forceinline__ void affine_adjoint(const Affine& f, int x, int y, int z, float g0, float g1, float g2,
+                                               double acc[12], float& gx, float& gy, float& gz)
+{
+    const double X = x, Y = y, Z = z;
+    const double G[3] = {g0, g1, g2};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        acc[3 * i + 0] = fma(G[i], X, acc[3 * i + 0]);
+        acc[3 * i + 1] = fma(G[i], Y, acc[3 * i + 1]);
+        acc[3 * i + 2] = fma(G[i], Z, acc[3 * i + 2]);
+        acc[9 + i] += G[i];
+    }
+    gx = fmaf(f.S[0], g0, fmaf(f.S[3], g1, f.S[6] * g2));
+    gy = fmaf(f.S[1], g0, fmaf(f.S[4], g1, f.S[7] * g2));
+    gz = fmaf(f.S[2], g0, fmaf(f.S[5], g1, f.S[8] * g2));
+}
+
+// dL/dA, dL/dt: fixed-order sum of per-block partials part[12 * b + q] -> out[12]
+hipError_t affine_reduce_launch(const double* part, int nblocks, double* out, hipStream_t st);
+
 // MI
 constexpr int MI_TX = 64;
 constexpr int MI_TY = 4;
@@ -50,6 +91,9 @@ struct MiArgs {
     int roi[6];
     int bins;
     int ntx, nty, zchunk, nblocks;
+    int affine;      // 1: composite sampler with aff
+    Affine aff;
+    double* apart;   // [nblocks][12] partial dL/dA, dL/dt (affine adjoint)
 };
 
 hipError_t mi_fwd_launch(const MiArgs& a, int hard, int pad, unsigned long long* hist, float* state, float* loss,
@@ -59,6 +103,12 @@ hipError_t mi_bwd_launch(const MiArgs& a, int hard, int pad, const float* state,
 
 // elementwise
 hipError_t warp_launch(const float* M, const float* u, int D, int H, int W, int pad, float* out, hipStream_t st);
+hipError_t warp_affine_launch(const float* M, const float* u, int D, int H, int W, const Affine& f, int pad,
+                              float* out, hipStream_t st);
+// adjoint of the composite warp for an upstream gradient gout; gu nullable;
+// part: [nblocks][12] with nblocks = mi_plan(D, H, W).nblocks
+hipError_t warp_affine_bwd_launch(const float* M, const float* u, int D, int H, int W, const Affine& f, int pad,
+                                  const float* gout, float* gu, double* part, double* gAt, hipStream_t st);
 hipError_t resample_launch(const float* src, int sD, int sH, int sW, float* dst, int dD, int dH, int dW, int ch,
                            float scale, hipStream_t st);
 hipError_t adam_launch(float* x, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,

@@ -68,12 +68,24 @@ __device__ __forceinline__ void parzen4(float v, int B, int& j0, float w[4], flo
 
 __device__ __forceinline__ int fold(int j, int B) { return min(max(j, 0), B - 1); }
 
+// Offset from voxel (x, y, z) to its sample point: u, or with the composite
+// sampler Am X + t + S u.
+template <bool AFF>
+__device__ __forceinline__ void sample_disp(const MiArgs& a, int x, int y, int z, int idx, size_t N, float& dx,
+                                            float& dy, float& dz)
+{
+    float ux = 0.f, uy = 0.f, uz = 0.f;
+    if (a.u) { ux = a.u[idx]; uy = a.u[N + idx]; uz = a.u[2 * N + idx]; }
+    if (AFF) affine_disp(a.aff, x, y, z, ux, uy, uz, dx, dy, dz);
+    else { dx = ux; dy = uy; dz = uz; }
+}
+
 __device__ __forceinline__ unsigned long long to_fix(float x)
 {
     return (unsigned long long)fma((double)x, FIX_ONE, 0.5);
 }
 
-template <bool HARD, int PAD>
+template <bool HARD, int PAD, bool AFF>
 __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long long* __restrict__ ghist,
                                                         unsigned long long* __restrict__ gflag)
 {
@@ -113,8 +125,8 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
     if (active) {
         for (int z = zb; z < ze; ++z) {
             const int idx = z * HW + y * W + x;
-            float ux = 0.f, uy = 0.f, uz = 0.f;
-            if (a.u) { ux = a.u[idx]; uy = a.u[N + idx]; uz = a.u[2 * N + idx]; }
+            float ux, uy, uz;
+            sample_disp<AFF>(a, x, y, z, idx, N, ux, uy, uz);
             const float fv = a.F[idx];
             const float mv = trilinear<PAD, false>(a.M, a.D, H, W, x, y, z, ux, uy, uz).v;
             bad |= (fv != fv) || (mv != mv);
@@ -144,7 +156,7 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
     if (threadIdx.x == 0 && nanflag) atomicOr(gflag, 1ull);
 }
 
-template <int PAD>
+template <int PAD, bool AFF>
 __global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long long* __restrict__ ghist,
                                                          unsigned long long* __restrict__ gflag)
 {
@@ -171,8 +183,8 @@ __global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long
     if (active) {
         for (int z = zb; z < ze; ++z) {
             const int idx = z * HW + y * W + x;
-            float ux = 0.f, uy = 0.f, uz = 0.f;
-            if (a.u) { ux = a.u[idx]; uy = a.u[N + idx]; uz = a.u[2 * N + idx]; }
+            float ux, uy, uz;
+            sample_disp<AFF>(a, x, y, z, idx, N, ux, uy, uz);
             const float fv = a.F[idx];
             const float mv = trilinear<PAD, false>(a.M, a.D, H, W, x, y, z, ux, uy, uz).v;
             bad |= (fv != fv) || (mv != mv);
@@ -340,7 +352,7 @@ __global__ void __launch_bounds__(1024) mi_finalize(const unsigned long long* __
     }
 }
 
-template <bool HARD, int PAD>
+template <bool HARD, int PAD, bool AFF>
 __global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* __restrict__ state,
                                                         const float* __restrict__ grad_scale, float neg_inv_nroi,
                                                         float* __restrict__ gu)
@@ -358,14 +370,17 @@ __global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* _
     const int zb = ch * a.zchunk, ze = min(a.D, zb + a.zchunk);
     const int H = a.H, W = a.W, HW = H * W;
     const size_t N = (size_t)a.D * HW;
-    if (x >= W || y >= H) return;
-    const bool colroi = x >= a.roi[4] && x < a.roi[5] && y >= a.roi[2] && y < a.roi[3];
-    for (int z = zb; z < ze; ++z) {
+    const bool active = x < W && y < H;
+    const bool colroi = active && x >= a.roi[4] && x < a.roi[5] && y >= a.roi[2] && y < a.roi[3];
+    double acc[AFF ? 12 : 1];
+#pragma unroll
+    for (int q = 0; q < (AFF ? 12 : 1); ++q) acc[q] = 0.0;
+    for (int z = zb; active && z < ze; ++z) {
         const int idx = z * HW + y * W + x;
         float g0 = 0.f, g1 = 0.f, g2 = 0.f;
         if (!HARD && colroi && z >= a.roi[0] && z < a.roi[1]) {
-            float ux = 0.f, uy = 0.f, uz = 0.f;
-            if (a.u) { ux = a.u[idx]; uy = a.u[N + idx]; uz = a.u[2 * N + idx]; }
+            float ux, uy, uz;
+            sample_disp<AFF>(a, x, y, z, idx, N, ux, uy, uz);
             const Tri t = trilinear<PAD, true>(a.M, a.D, H, W, x, y, z, ux, uy, uz);
             int jf, jm;
             float wf[4], wm[4], dm[4], dd[4];
@@ -382,10 +397,21 @@ __global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* _
             }
             const float gm = g * S;
             g0 = gm * t.dx; g1 = gm * t.dy; g2 = gm * t.dz;
+            if (AFF) affine_adjoint(a.aff, x, y, z, g0, g1, g2, acc, g0, g1, g2);
         }
-        gu[idx] = g0;
-        gu[N + idx] = g1;
-        gu[2 * N + idx] = g2;
+        if (!AFF || gu) {
+            gu[idx] = g0;
+            gu[N + idx] = g1;
+            gu[2 * N + idx] = g2;
+        }
+    }
+    if (AFF) {
+        __shared__ double red[MI_NT];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const double v = block_sum<MI_NT>(acc[AFF ? q : 0], red);
+            if (threadIdx.x == 0) a.apart[12 * (size_t)blockIdx.x + q] = v;
+        }
     }
 }
 
@@ -405,52 +431,70 @@ MiLaunch mi_plan(int rz, int ry, int rx)
     return L;
 }
 
+template <bool AFF>
+static hipError_t mi_fwd_dispatch(const MiArgs& a, int hard, int pad, unsigned long long* hist,
+                                  unsigned long long* flag, float* state, float* loss, hipStream_t st)
+{
+    const int BB = a.bins * a.bins;
+    dim3 grid(a.nblocks), block(MI_NT);
+    if (hard == 2) {
+        const size_t lds32 = sizeof(unsigned int) * BB;
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_count_kernel<PAD_BORDER, AFF>), grid, block, lds32, st, a, hist, flag);
+        else hipLaunchKernelGGL((mi_count_kernel<PAD_ZEROS, AFF>), grid, block, lds32, st, a, hist, flag);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(mi_finalize_approx, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, state, loss);
+        return hipGetLastError();
+    }
+    const size_t lds = sizeof(unsigned long long) * BB;
+    if (hard) {
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER, AFF>), grid, block, lds, st, a, hist, flag);
+        else hipLaunchKernelGGL((mi_hist_kernel<true, PAD_ZEROS, AFF>), grid, block, lds, st, a, hist, flag);
+    } else {
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<false, PAD_BORDER, AFF>), grid, block, lds, st, a, hist, flag);
+        else hipLaunchKernelGGL((mi_hist_kernel<false, PAD_ZEROS, AFF>), grid, block, lds, st, a, hist, flag);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mi_finalize, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, state, loss);
+    return hipGetLastError();
+}
+
 hipError_t mi_fwd_launch(const MiArgs& a, int hard, int pad, unsigned long long* hist, float* state, float* loss,
                          double nroi, hipStream_t st)
 {
+    (void)nroi;
     const int BB = a.bins * a.bins;
     unsigned long long* flag = hist + BB;
     hipLaunchKernelGGL(mi_zero, dim3((BB + 1 + 255) / 256), dim3(256), 0, st, hist, BB + 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = sizeof(unsigned long long) * BB;
+    return a.affine ? mi_fwd_dispatch<true>(a, hard, pad, hist, flag, state, loss, st)
+                    : mi_fwd_dispatch<false>(a, hard, pad, hist, flag, state, loss, st);
+}
+
+template <bool AFF>
+static hipError_t mi_bwd_dispatch(const MiArgs& a, int hard, int pad, const float* state, const float* grad_scale,
+                                  float nin, float* gu, hipStream_t st)
+{
+    const size_t lds = sizeof(float) * a.bins * a.bins;
     dim3 grid(a.nblocks), block(MI_NT);
-    if (hard == 2) {
-        const size_t lds32 = sizeof(unsigned int) * BB;
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_count_kernel<PAD_BORDER>), grid, block, lds32, st, a, hist, flag);
-        else hipLaunchKernelGGL((mi_count_kernel<PAD_ZEROS>), grid, block, lds32, st, a, hist, flag);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(mi_finalize_approx, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, state, loss);
-        return hipGetLastError();
-    }
-    if (hard) {
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER>), grid, block, lds, st, a, hist, flag);
-        else hipLaunchKernelGGL((mi_hist_kernel<true, PAD_ZEROS>), grid, block, lds, st, a, hist, flag);
+    if (hard == 1) {
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<true, PAD_BORDER, AFF>), grid, block, lds, st, a, state, grad_scale, nin, gu);
+        else hipLaunchKernelGGL((mi_grad_kernel<true, PAD_ZEROS, AFF>), grid, block, lds, st, a, state, grad_scale, nin, gu);
     } else {
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<false, PAD_BORDER>), grid, block, lds, st, a, hist, flag);
-        else hipLaunchKernelGGL((mi_hist_kernel<false, PAD_ZEROS>), grid, block, lds, st, a, hist, flag);
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<false, PAD_BORDER, AFF>), grid, block, lds, st, a, state, grad_scale, nin, gu);
+        else hipLaunchKernelGGL((mi_grad_kernel<false, PAD_ZEROS, AFF>), grid, block, lds, st, a, state, grad_scale, nin, gu);
     }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mi_finalize, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, state, loss);
     return hipGetLastError();
 }
 
 hipError_t mi_bwd_launch(const MiArgs& a, int hard, int pad, const float* state, const float* grad_scale,
                          float* gu, double nroi, hipStream_t st)
 {
-    const size_t lds = sizeof(float) * a.bins * a.bins;
-    dim3 grid(a.nblocks), block(MI_NT);
     const float nin = (float)(-1.0 / nroi);
-    if (hard == 1) {
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<true, PAD_BORDER>), grid, block, lds, st, a, state, grad_scale, nin, gu);
-        else hipLaunchKernelGGL((mi_grad_kernel<true, PAD_ZEROS>), grid, block, lds, st, a, state, grad_scale, nin, gu);
-    } else {
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<false, PAD_BORDER>), grid, block, lds, st, a, state, grad_scale, nin, gu);
-        else hipLaunchKernelGGL((mi_grad_kernel<false, PAD_ZEROS>), grid, block, lds, st, a, state, grad_scale, nin, gu);
-    }
-    return hipGetLastError();
+    return a.affine ? mi_bwd_dispatch<true>(a, hard, pad, state, grad_scale, nin, gu, st)
+                    : mi_bwd_dispatch<false>(a, hard, pad, state, grad_scale, nin, gu, st);
 }
 
 }  // namespace ffdp

@@ -9,10 +9,11 @@ from __future__ import annotations
 import ctypes as C
 from typing import Optional, Sequence, Tuple
 
+import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ConvGeom, Grid, LnccParams, MiParams, check
+from ._lib import Affine, ConvGeom, Grid, LnccParams, MiParams, check
 
 PAD = {"border": 0, "zeros": 1, 0: 0, 1: 1}
 
@@ -201,6 +202,96 @@ def warp_mi_bwd(F, M, u, state, bins=32, hard=False, pad="border", roi=None, gra
                                                   _ptr(grad_scale), _ptr(grad_u), _ptr(ws), ws.numel(), _stream(F)))
     return grad_u
 
+
+
+# ------------------------------------------------- composite (affine) sampler --
+def affine_params(A=None, t=None, S=None) -> Affine:
+    """ffdp_affine from host values: A, S 3x3 (row-major, acting on (x, y, z)),
+    t 3-vector, in voxel units; None means identity / zero."""
+    def flat(v, n, default):
+        if v is None:
+            return default
+        if isinstance(v, torch.Tensor):
+            v = v.detach().cpu().double()
+        v = [float(x) for x in np.asarray(v, dtype=np.float64).reshape(-1)]
+        if len(v) != n:
+            raise ValueError(f"expected {n} values, got {len(v)}")
+        return v
+    eye = [1.0, 0, 0, 0, 1.0, 0, 0, 0, 1.0]
+    a = Affine()
+    a.A[:] = flat(A, 9, eye)
+    a.t[:] = flat(t, 3, [0.0, 0.0, 0.0])
+    a.S[:] = flat(S, 9, eye)
+    return a
+
+
+def warp_affine(M, u=None, A=None, t=None, S=None, pad="border", out=None) -> torch.Tensor:
+    """Composite sampler forward M(A X + t + S u(X)) (ffdp_warp_affine)."""
+    _vol(M, "M")
+    if u is not None and tuple(u.shape) != (3,) + tuple(M.shape):
+        raise ValueError("u must be [3, D, H, W]")
+    out = torch.empty_like(M) if out is None else out
+    g = make_grid(M.shape)
+    f = affine_params(A, t, S)
+    check("ffdp_warp_affine", _lib.lib().ffdp_warp_affine(_ptr(M), _ptr(u), C.byref(g), C.byref(f), PAD[pad],
+                                                           _ptr(out), _stream(M)))
+    return out
+
+
+def warp_affine_bwd(M, gout, u=None, A=None, t=None, S=None, pad="border", want_grad_u=True, grad_u=None, ws=None):
+    """Composite sampler adjoint: (dL/du [3,D,H,W] or None, dL/dA [3,3], dL/dt [3]) as float64 device
+    tensors for dL/dA, dL/dt (ffdp_warp_affine_bwd)."""
+    _vol(M, "M")
+    _vol(gout, "gout")
+    g = make_grid(M.shape)
+    f = affine_params(A, t, S)
+    L = _lib.lib()
+    ws = _workspace(int(L.ffdp_affine_workspace_bytes(C.byref(g))), M.device, ws)
+    if want_grad_u and grad_u is None:
+        grad_u = torch.empty((3,) + tuple(M.shape), dtype=torch.float32, device=M.device)
+    gAt = torch.empty(12, dtype=torch.float64, device=M.device)
+    check("ffdp_warp_affine_bwd", L.ffdp_warp_affine_bwd(_ptr(M), _ptr(u), C.byref(g), C.byref(f), PAD[pad],
+                                                          _ptr(gout), _ptr(grad_u if want_grad_u else None),
+                                                          _ptr(gAt), _ptr(ws), ws.numel(), _stream(M)))
+    return (grad_u if want_grad_u else None), gAt[:9].view(3, 3), gAt[9:]
+
+
+def warp_mi_affine_fwd(F, M, u=None, A=None, t=None, S=None, bins=32, hard=False, pad="border", roi=None,
+                       state=None, loss=None, ws=None):
+    """MI through the composite sampler: (loss = -MI [1], mi_state) (ffdp_warp_mi_affine_fwd)."""
+    _check_pair(F, M, u)
+    g = make_grid(F.shape, roi)
+    p = mi_params(bins, hard, pad)
+    f = affine_params(A, t, S)
+    L = _lib.lib()
+    ws = _workspace(int(L.ffdp_mi_workspace_bytes(C.byref(g), C.byref(p))), F.device, ws)
+    if state is None:
+        state = torch.empty(int(L.ffdp_mi_state_floats(int(bins))), dtype=torch.float32, device=F.device)
+    loss = torch.empty(1, dtype=torch.float32, device=F.device) if loss is None else loss
+    check("ffdp_warp_mi_affine_fwd", L.ffdp_warp_mi_affine_fwd(_ptr(F), _ptr(M), _ptr(u), C.byref(g), C.byref(f),
+                                                                C.byref(p), _ptr(loss), _ptr(state), _ptr(ws),
+                                                                ws.numel(), _stream(F)))
+    return loss, state
+
+
+def warp_mi_affine_bwd(F, M, u, state, A=None, t=None, S=None, bins=32, hard=False, pad="border", roi=None,
+                       grad_scale=None, want_grad_u=False, grad_u=None, ws=None):
+    """MI adjoint through the composite sampler: (dL/du or None, dL/dA [3,3], dL/dt [3]) (float64 for
+    the affine part) (ffdp_warp_mi_affine_bwd)."""
+    _check_pair(F, M, u)
+    g = make_grid(F.shape, roi)
+    p = mi_params(bins, hard, pad)
+    f = affine_params(A, t, S)
+    L = _lib.lib()
+    ws = _workspace(int(L.ffdp_affine_workspace_bytes(C.byref(g))), F.device, ws)
+    if want_grad_u and grad_u is None:
+        grad_u = torch.empty((3,) + tuple(F.shape), dtype=torch.float32, device=F.device)
+    gAt = torch.empty(12, dtype=torch.float64, device=F.device)
+    check("ffdp_warp_mi_affine_bwd", L.ffdp_warp_mi_affine_bwd(_ptr(F), _ptr(M), _ptr(u), C.byref(g), C.byref(f),
+                                                                C.byref(p), _ptr(state), _ptr(grad_scale),
+                                                                _ptr(grad_u if want_grad_u else None), _ptr(gAt),
+                                                                _ptr(ws), ws.numel(), _stream(F)))
+    return (grad_u if want_grad_u else None), gAt[:9].view(3, 3), gAt[9:]
 
 def adam_step(x, g, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
     """In-place Adam on x, m, v (ffdp_adam_step)."""

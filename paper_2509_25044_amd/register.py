@@ -22,6 +22,7 @@ from __future__ import annotations
 import dataclasses
 from typing import Callable, List, Optional, Sequence, Tuple
 
+import numpy as np
 import torch
 
 from . import ops
@@ -204,3 +205,71 @@ class Registration:
 def register(F: torch.Tensor, M: torch.Tensor, cfg: RegConfig, u0: Optional[torch.Tensor] = None) -> RegState:
     """Register F and M; returns the final state (u at full resolution, losses per level)."""
     return Registration(F, M, cfg).run(u0=u0)
+
+
+# ------------------------------------------------------------ affine MI stage --
+@dataclasses.dataclass
+class AffineConfig:
+    """Affine MI registration settings (the paper's affine stage runs MI on a
+    pyramid before the deformable stage)."""
+    bins: int = 32
+    hard: object = False                 # MI estimator: False (Parzen) or "approx"
+    levels: Tuple[float, ...] = (0.5, 1.0)
+    iters: Tuple[int, ...] = (100,)      # per level (one value is used for every level)
+    lr_A: float = 0.005
+    lr_t: float = 0.2
+    pad: str = "border"
+
+
+def _centre(shape):
+    D, H, W = shape
+    return np.array([(W - 1) / 2.0, (H - 1) / 2.0, (D - 1) / 2.0])
+
+
+def register_affine(F: torch.Tensor, M: torch.Tensor, cfg: AffineConfig):
+    """Affine MI registration of F and M: (A, t, losses) with M(A X + t) ~ F
+    in F's voxel coordinates X = (x, y, z).  The transform is optimised as
+    p = A (X - c) + c + t' about the volume centre c (so that rotation and
+    translation decouple); every loss and gradient comes from the
+    composite-sampler MI kernels, the 12 parameters take Adam steps on the
+    device, and each level starts from the previous one's transform."""
+    shapes = level_shapes(F.shape, cfg.levels)
+    dev = F.device
+    prm = torch.zeros(12, dtype=torch.float32, device=dev)  # A - I (row-major), t'
+    losses = []
+    prev = None
+    for lv, shp in enumerate(shapes):
+        Fl = F if tuple(shp) == tuple(F.shape) else ops.resample(F, shp)
+        Ml = M if tuple(shp) == tuple(M.shape) else ops.resample(M, shp)
+        if prev is not None:  # move (A, t') to this grid: A' = s A s^-1, t'' = s t'
+            s = np.array(axis_scales(prev, shp))
+            h = prm.double().cpu().numpy()
+            A = np.eye(3) + h[:9].reshape(3, 3)
+            A = (s[:, None] * A) / s[None, :]
+            prm = torch.tensor(np.concatenate([(A - np.eye(3)).reshape(-1), s * h[9:]]), dtype=torch.float32,
+                               device=dev)
+        c = _centre(shp)
+        m = torch.zeros_like(prm)
+        v = torch.zeros_like(prm)
+        g = torch.zeros_like(prm)
+        n = cfg.iters[lv] if len(cfg.iters) > 1 else cfg.iters[0]
+        hist = []
+        for it in range(1, n + 1):
+            h = prm.double().cpu().numpy()
+            A = np.eye(3) + h[:9].reshape(3, 3)
+            t = h[9:] + c - A @ c
+            loss, state = ops.warp_mi_affine_fwd(Fl, Ml, None, A=A, t=t, bins=cfg.bins, hard=cfg.hard, pad=cfg.pad)
+            _, gA, gt = ops.warp_mi_affine_bwd(Fl, Ml, None, state, A=A, t=t, bins=cfg.bins, hard=cfg.hard,
+                                               pad=cfg.pad)
+            # t depends on A through t = t' + c - A c
+            gAc = gA - torch.outer(gt, torch.tensor(c, dtype=torch.float64, device=dev))
+            g.copy_(torch.cat([gAc.reshape(-1), gt]).float())
+            ops.adam_step(prm[:9], g[:9], m[:9], v[:9], lr=cfg.lr_A, step=it)
+            ops.adam_step(prm[9:], g[9:], m[9:], v[9:], lr=cfg.lr_t, step=it)
+            hist.append(loss)
+        losses.append(torch.cat(hist))
+        prev = shp
+    h = prm.double().cpu().numpy()
+    A = np.eye(3) + h[:9].reshape(3, 3)
+    c = _centre(F.shape)
+    return A, h[9:] + c - A @ c, losses

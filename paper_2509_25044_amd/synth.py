@@ -206,6 +206,38 @@ def make_pair(spec: PairSpec, seed: int = BASE_SEED, device="cpu",
     return out
 
 
+
+def make_affine_pair(spec: PairSpec, B, c, seed: int = BASE_SEED, device="cpu"):
+    """Pair related by a known affine map: F(X) = G(X), M(X) = G(B X + c)
+    (X = (x, y, z) voxel coordinates, B 3x3 row-major, c 3-vector; blobs,
+    texture and independent noise as in make_pair).  Returns dict(F, M, A, t)
+    with A = B^-1, t = -B^-1 c, the transform for which M(A X + t) = G(X)."""
+    st = _streams(seed)
+    D, H, W = spec.shape
+    dt = torch.float64
+    z, y, x = _coords(spec.shape, device, dt)
+    B = np.asarray(B, dtype=np.float64).reshape(3, 3)
+    c = np.asarray(c, dtype=np.float64).reshape(3)
+    blobs = _blob_params(st["blobs"], spec)
+    _disp_modes(st["disp"], spec)  # keeps the stream layout of make_pair
+    tmodes = _texture_modes(st["texture"], spec) if spec.texture_std > 0 else None
+    px = B[0, 0] * x + B[0, 1] * y + B[0, 2] * z + c[0]
+    py = B[1, 0] * x + B[1, 1] * y + B[1, 2] * z + c[1]
+    pz = B[2, 0] * x + B[2, 1] * y + B[2, 2] * z + c[2]
+    shape = (D, H, W)
+    Fv = _eval_blobs(blobs, z, y, x, torch.zeros(shape, device=device, dtype=dt))
+    Mv = _eval_blobs(blobs, pz, py, px, torch.zeros(shape, device=device, dtype=dt))
+    if tmodes is not None:
+        Fv.add_(_eval_modes(tmodes, z, y, x, shape, device, dt), alpha=spec.texture_std)
+        Mv.add_(_eval_modes(tmodes, pz, py, px, shape, device, dt), alpha=spec.texture_std)
+    Fv.add_(_noise(st["noise"], shape, spec.noise_std, device))
+    Mv.add_(_noise(st["noise"], shape, spec.noise_std, device))
+    _minmax_(Fv)
+    _minmax_(Mv)
+    Bi = np.linalg.inv(B)
+    return {"F": Fv.to(torch.float32).contiguous(), "M": Mv.to(torch.float32).contiguous(),
+            "A": Bi, "t": -Bi @ c}
+
 def random_volume(shape: Sequence[int], seed: int, device="cpu", lo=0.0, hi=1.0):
     """i.i.d. uniform volume (edge-case and tiny-shape tests)."""
     g = torch.Generator(device="cpu").manual_seed(int(seed))

@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=2000)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--shape", type=int, nargs=3, default=(160, 192, 224))
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--eval-pairs", type=int, default=4)
     ap.add_argument("--plain-iters", type=int, default=200)
     ap.add_argument("--converged-every", type=int, default=16)
