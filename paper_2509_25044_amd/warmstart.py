@@ -19,6 +19,7 @@ excluded and reported separately.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import time
 from typing import Optional
@@ -71,11 +72,21 @@ def train(model: UNet3D, spec: synth.PairSpec, pairs: int, batch: int = 4, lr: f
     return {"steps": steps, "pairs": steps * batch, "seconds": time.perf_counter() - t0, "history": hist}
 
 
-def time_to_target(model: UNet3D, F: torch.Tensor, M: torch.Tensor, plain_cfg: RegConfig, check_every: int = 5):
-    """Wall-clock seconds for the plain pyramid to finish, and for the same
-    pyramid started from the network's prediction to reach the plain run's
-    final loss (checked every check_every iterations on the finest level;
-    the network's forward pass is included in the warm time)."""
+WARM_SCHEDULES = {
+    # name: (levels, iterations per level) of the warm-started run; None: the plain run's own schedule
+    "same": None,
+    "fine": ((1.0,), (600,)),
+    "half+fine": ((0.5, 1.0), (100, 600)),
+}
+
+
+def time_to_target(model: UNet3D, F: torch.Tensor, M: torch.Tensor, plain_cfg: RegConfig, check_every: int = 5,
+                   schedules=None):
+    """Wall-clock seconds for the plain pyramid to finish, and for runs started
+    from the network's prediction to reach the plain run's final loss
+    (checked every check_every iterations on their finest level; the network's
+    forward pass is included in every warm time).  schedules: names of
+    WARM_SCHEDULES (default: all)."""
     dev = F.device
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
@@ -84,33 +95,34 @@ def time_to_target(model: UNet3D, F: torch.Tensor, M: torch.Tensor, plain_cfg: R
     target = plain.evaluate(st.u)  # synchronises
     t_plain = time.perf_counter() - t0
     plain_iters = sum(plain.iters(l) for l in range(len(plain.shapes)))
-    last = len(plain.shapes) - 1
-
-    torch.cuda.synchronize(dev)
-    t1 = time.perf_counter()
     u0 = model.predict(F, M)
-    warm = Registration(F, M, plain_cfg)
-    done = {"iters": 0, "reached": False}
+    out = {"target_loss": target, "plain_iters": plain_iters, "plain_seconds": t_plain,
+           "zero_loss": plain.evaluate(torch.zeros_like(u0)), "warm_u0_loss": plain.evaluate(u0), "warm": {}}
+    for name in (schedules or list(WARM_SCHEDULES)):
+        sched = WARM_SCHEDULES[name]
+        cfg = plain_cfg if sched is None else dataclasses.replace(plain_cfg, levels=sched[0], iters=sched[1])
+        torch.cuda.synchronize(dev)
+        t1 = time.perf_counter()
+        u0 = model.predict(F, M)
+        warm = Registration(F, M, cfg)
+        last = len(warm.shapes) - 1
+        done = {"iters": 0, "reached": False}
 
-    def until(level, step, loss_dev):
-        done["iters"] += 1
-        if level != last or step % check_every:
+        def until(level, step, loss_dev):
+            done["iters"] += 1
+            if level != last or step % check_every:
+                return False
+            if float(loss_dev.item()) <= target:  # loss of the iterate before this step
+                done["reached"] = True
+                return True
             return False
-        if float(loss_dev.item()) <= target:  # loss of the iterate before this step
-            done["reached"] = True
-            return True
-        return False
 
-    st2 = warm.run(u0=u0, until=until)
-    final = warm.evaluate(st2.u)
-    if final <= target:
-        done["reached"] = True
-    torch.cuda.synchronize(dev)
-    t_warm = time.perf_counter() - t1
-    zero_loss = plain.evaluate(torch.zeros_like(u0))
-    return {"target_loss": target, "plain_iters": plain_iters, "plain_seconds": t_plain,
-            "zero_loss": zero_loss, "warm_u0_loss": warm.evaluate(u0), "warm_iters": done["iters"],
-            "warm_seconds": t_warm, "warm_reached": done["reached"], "warm_final_loss": final}
+        st2 = warm.run(u0=u0, until=until)
+        final = warm.evaluate(st2.u)
+        torch.cuda.synchronize(dev)
+        out["warm"][name] = {"iters": done["iters"], "seconds": time.perf_counter() - t1,
+                             "reached": done["reached"] or final <= target, "final_loss": final}
+    return out
 
 
 def main():
@@ -126,6 +138,8 @@ def main():
     ap.add_argument("--sigma-grad", type=float, default=0.0)
     ap.add_argument("--sigma-warp", type=float, default=0.0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--save", default=None, help="write the trained network's weights here")
+    ap.add_argument("--load", default=None, help="skip training and load weights from here")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     spec = synth.PairSpec(tuple(args.shape), (4.0, 12.0), 3.0, texture_std=args.texture)
@@ -133,8 +147,14 @@ def main():
     plain_cfg = RegConfig(loss="lncc", window=7, levels=(0.25, 0.5, 1.0), iters=(args.plain_iters,), lr=0.1, **sm)
     conv_cfg = RegConfig(loss="lncc", window=7, levels=(0.25, 0.5, 1.0), iters=(50,), lr=0.1, **sm)
     model = UNet3D(dev, seed=0)
-    tr = train(model, spec, args.pairs, args.batch, args.lr, converged_every=args.converged_every, reg_cfg=conv_cfg,
-               log=lambda s: print(s, flush=True))
+    if args.load:
+        model.load_state_dict(torch.load(args.load, map_location="cpu", weights_only=True))
+        tr = {"steps": 0, "pairs": 0, "seconds": 0.0, "history": []}
+    else:
+        tr = train(model, spec, args.pairs, args.batch, args.lr, converged_every=args.converged_every,
+                   reg_cfg=conv_cfg, log=lambda s: print(s, flush=True))
+        if args.save:
+            torch.save(model.state_dict(), args.save)
     print(f"trained {tr['pairs']} pairs in {tr['seconds']:.1f} s", flush=True)
     res = []
     for k in range(args.eval_pairs):
@@ -151,11 +171,11 @@ def main():
     if args.out:
         with open(args.out, "w") as f:
             json.dump(out, f, indent=1)
-    print(json.dumps({"summary": {
-        "plain_seconds_mean": sum(r["plain_seconds"] for r in res) / len(res),
-        "warm_seconds_mean": sum(r["warm_seconds"] for r in res) / len(res),
-        "plain_iters": res[0]["plain_iters"],
-        "warm_iters_mean": sum(r["warm_iters"] for r in res) / len(res)}}), flush=True)
+    summ = {"plain_seconds_mean": sum(r["plain_seconds"] for r in res) / len(res), "plain_iters": res[0]["plain_iters"]}
+    for name in WARM_SCHEDULES:
+        summ[f"warm_{name}_seconds_mean"] = sum(r["warm"][name]["seconds"] for r in res) / len(res)
+        summ[f"warm_{name}_reached"] = sum(bool(r["warm"][name]["reached"]) for r in res)
+    print(json.dumps({"summary": summ}), flush=True)
 
 
 if __name__ == "__main__":
