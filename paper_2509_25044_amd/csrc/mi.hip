@@ -85,6 +85,124 @@ __device__ __forceinline__ unsigned long long to_fix(float x)
     return (unsigned long long)fma((double)x, FIX_ONE, 0.5);
 }
 
+// Loads of one voxel's sample, issued one z-step ahead of their use (the
+// thread walks its column along z): F, the eight corner values of M's cell
+// (indices clamped into the array, so every load is in bounds), the cell
+// fractions, and flags.  Border padding: a flag per axis for a sample exactly
+// on index 0 (zero derivative there, as trilinear<PAD_BORDER>; the clamped
+// corners make value and derivative right elsewhere).  Zero padding: one
+// validity bit per corner, applied when the values are consumed.
+struct MiPend {
+    float c[8];
+    float ax, ay, az;
+    unsigned fl;
+    float f;
+};
+
+template <int PAD>
+__device__ __forceinline__ void mi_issue(const MiArgs& a, int x, int y, int z, float dx, float dy, float dz, int idx,
+                                         MiPend& g)
+{
+    const int D = a.D, H = a.H, W = a.W;
+    g.f = a.F[idx];
+    const float fx = fminf(fmaxf(floorf(dx), -268435456.0f), 268435456.0f);
+    const float fy = fminf(fmaxf(floorf(dy), -268435456.0f), 268435456.0f);
+    const float fz = fminf(fmaxf(floorf(dz), -268435456.0f), 268435456.0f);
+    g.ax = dx - fx; g.ay = dy - fy; g.az = dz - fz;
+    const int ix = x + (int)fx, iy = y + (int)fy, iz = z + (int)fz;
+    const int x0 = min(max(ix, 0), W - 1), x1 = min(max(ix + 1, 0), W - 1);
+    const int y0 = min(max(iy, 0), H - 1), y1 = min(max(iy + 1, 0), H - 1);
+    const int z0 = min(max(iz, 0), D - 1), z1 = min(max(iz + 1, 0), D - 1);
+    const int r00 = (z0 * H + y0) * W, r01 = (z0 * H + y1) * W, r10 = (z1 * H + y0) * W, r11 = (z1 * H + y1) * W;
+    g.c[0] = a.M[r00 + x0]; g.c[1] = a.M[r00 + x1]; g.c[2] = a.M[r01 + x0]; g.c[3] = a.M[r01 + x1];
+    g.c[4] = a.M[r10 + x0]; g.c[5] = a.M[r10 + x1]; g.c[6] = a.M[r11 + x0]; g.c[7] = a.M[r11 + x1];
+    if (PAD == PAD_BORDER) {
+        g.fl = ((ix == 0 && g.ax == 0.0f) ? 1u : 0u) | ((iy == 0 && g.ay == 0.0f) ? 2u : 0u) |
+               ((iz == 0 && g.az == 0.0f) ? 4u : 0u);
+    } else {
+        unsigned m = 0u;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int cx = ix + (b & 1), cy = iy + ((b >> 1) & 1), cz = iz + (b >> 2);
+            if ((unsigned)cx < (unsigned)W && (unsigned)cy < (unsigned)H && (unsigned)cz < (unsigned)D) m |= 1u << b;
+        }
+        g.fl = m;
+    }
+}
+
+// Value and (with DERIV) dvalue/dp of a pending sample; the arithmetic of
+// trilinear<PAD, DERIV>.
+template <int PAD, bool DERIV>
+__device__ __forceinline__ Tri mi_interp(const MiPend& g)
+{
+    float c[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) c[b] = (PAD == PAD_ZEROS && !((g.fl >> b) & 1u)) ? 0.0f : g.c[b];
+    const float e00 = c[1] - c[0], e01 = c[3] - c[2], e10 = c[5] - c[4], e11 = c[7] - c[6];
+    const float c00 = fmaf(g.ax, e00, c[0]), c01 = fmaf(g.ax, e01, c[2]);
+    const float c10 = fmaf(g.ax, e10, c[4]), c11 = fmaf(g.ax, e11, c[6]);
+    const float f0 = c01 - c00, f1 = c11 - c10;
+    const float c0 = fmaf(g.ay, f0, c00), c1 = fmaf(g.ay, f1, c10);
+    Tri t;
+    t.v = fmaf(g.az, c1 - c0, c0);
+    if (DERIV) {
+        const bool bx = PAD == PAD_BORDER && (g.fl & 1u), by = PAD == PAD_BORDER && (g.fl & 2u);
+        const bool bz = PAD == PAD_BORDER && (g.fl & 4u);
+        const float gx0 = fmaf(g.ay, e01 - e00, e00), gx1 = fmaf(g.ay, e11 - e10, e10);
+        t.dx = bx ? 0.0f : fmaf(g.az, gx1 - gx0, gx0);
+        t.dy = by ? 0.0f : fmaf(g.az, f1 - f0, f0);
+        t.dz = bz ? 0.0f : (c1 - c0);
+    } else {
+        t.dx = t.dy = t.dz = 0.0f;
+    }
+    return t;
+}
+
+// Software pipeline of one thread's walk down its (x, y) column over
+// [z0, z1): the corners of z+1 are gathered while z is processed, and u of
+// z+2 is loaded meanwhile, so gather latency overlaps the per-voxel work.
+template <int PAD, bool AFF>
+struct ColumnSampler {
+    const MiArgs& a;
+    int x, y, HW, z1;
+    size_t N;
+    MiPend pend;
+    float un[3];
+
+    __device__ ColumnSampler(const MiArgs& a_, int x_, int y_, int z0, int z1_)
+        : a(a_), x(x_), y(y_), HW(a_.H * a_.W), z1(z1_), N((size_t)a_.D * a_.H * a_.W)
+    {
+        if (z0 >= z1) return;  // empty column: no loads
+        float u0[3];
+        load_u(z0, u0);
+        issue(z0, u0);
+        if (z0 + 1 < z1) load_u(z0 + 1, un);
+    }
+    __device__ void load_u(int zz, float* o)
+    {
+        const int id = zz * HW + y * a.W + x;
+        if (a.u) { o[0] = a.u[id]; o[1] = a.u[N + id]; o[2] = a.u[2 * N + id]; }
+        else { o[0] = 0.f; o[1] = 0.f; o[2] = 0.f; }
+    }
+    __device__ void issue(int zz, const float* uu)
+    {
+        float dx, dy, dz;
+        if (AFF) affine_disp(a.aff, x, y, zz, uu[0], uu[1], uu[2], dx, dy, dz);
+        else { dx = uu[0]; dy = uu[1]; dz = uu[2]; }
+        mi_issue<PAD>(a, x, y, zz, dx, dy, dz, zz * HW + y * a.W + x, pend);
+    }
+    // the loads of z (issued one step ago); issues those of z + 1
+    __device__ MiPend next(int z)
+    {
+        const MiPend cur = pend;
+        if (z + 1 < z1) {
+            issue(z + 1, un);
+            if (z + 2 < z1) load_u(z + 2, un);
+        }
+        return cur;
+    }
+};
+
 template <bool HARD, int PAD, bool AFF>
 __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long long* __restrict__ ghist,
                                                         unsigned long long* __restrict__ gflag)
@@ -122,13 +240,12 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
             }
     };
 
-    if (active) {
+    if (active && zb < ze) {
+        ColumnSampler<PAD, AFF> cs(a, x, y, zb, ze);
         for (int z = zb; z < ze; ++z) {
-            const int idx = z * HW + y * W + x;
-            float ux, uy, uz;
-            sample_disp<AFF>(a, x, y, z, idx, N, ux, uy, uz);
-            const float fv = a.F[idx];
-            const float mv = trilinear<PAD, false>(a.M, a.D, H, W, x, y, z, ux, uy, uz).v;
+            const MiPend sp = cs.next(z);
+            const float fv = sp.f;
+            const float mv = mi_interp<PAD, false>(sp).v;
             bad |= (fv != fv) || (mv != mv);
             int jf, jm;
             float wf[4], wm[4], dd[4];
@@ -180,13 +297,12 @@ __global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long
     int cur = -1;
     unsigned run = 0u;
     bool bad = false;
-    if (active) {
+    if (active && zb < ze) {
+        ColumnSampler<PAD, AFF> cs(a, x, y, zb, ze);
         for (int z = zb; z < ze; ++z) {
-            const int idx = z * HW + y * W + x;
-            float ux, uy, uz;
-            sample_disp<AFF>(a, x, y, z, idx, N, ux, uy, uz);
-            const float fv = a.F[idx];
-            const float mv = trilinear<PAD, false>(a.M, a.D, H, W, x, y, z, ux, uy, uz).v;
+            const MiPend sp = cs.next(z);
+            const float fv = sp.f;
+            const float mv = mi_interp<PAD, false>(sp).v;
             bad |= (fv != fv) || (mv != mv);
             const int bf = min((int)floorf(fminf(fmaxf(fv, 0.0f), 1.0f) * fB), B - 1);
             const int bm = min((int)floorf(fminf(fmaxf(mv, 0.0f), 1.0f) * fB), B - 1);
@@ -375,16 +491,18 @@ __global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* _
     double acc[AFF ? 12 : 1];
 #pragma unroll
     for (int q = 0; q < (AFF ? 12 : 1); ++q) acc[q] = 0.0;
+    const int zr0 = max(zb, a.roi[0]), zr1 = min(ze, a.roi[1]);  // ROI part of this column
+    const bool samp = !HARD && colroi && zr0 < zr1;
+    ColumnSampler<PAD, AFF> cs(a, x, y, samp ? zr0 : 0, samp ? zr1 : 0);
     for (int z = zb; active && z < ze; ++z) {
         const int idx = z * HW + y * W + x;
         float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-        if (!HARD && colroi && z >= a.roi[0] && z < a.roi[1]) {
-            float ux, uy, uz;
-            sample_disp<AFF>(a, x, y, z, idx, N, ux, uy, uz);
-            const Tri t = trilinear<PAD, true>(a.M, a.D, H, W, x, y, z, ux, uy, uz);
+        if (samp && z >= zr0 && z < zr1) {
+            const MiPend cur = cs.next(z);
+            const Tri t = mi_interp<PAD, true>(cur);
             int jf, jm;
             float wf[4], wm[4], dm[4], dd[4];
-            parzen4<false, false>(a.F[idx], B, jf, wf, dd);
+            parzen4<false, false>(cur.f, B, jf, wf, dd);
             parzen4<false, true>(t.v, B, jm, wm, dm);
             float S = 0.0f;
 #pragma unroll
