@@ -52,15 +52,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(workload: str):
     """HBM bytes per launch of the fused LNCC kernel from the committed
-    rocprofv3 counter summary, or None if the kernel changed since."""
+    rocprofv3 counter summary, or None if the kernel changed since or the
+    counters were taken on another workload."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
-    if c.get("source_hash") != kernel_source_hash():
+    if c.get("source_hash") != kernel_source_hash() or c.get("workload") != workload:
         return None
     return c.get("hbm_bytes_per_launch")
 
@@ -186,7 +187,7 @@ def main():
     ms_step = wall * 1e3 / args.steps
     gvox = nroi / (t_lncc * 1e-3) / 1e9
     achieved = LNCC_BYTES_PER_VOXEL * nroi / (t_lncc * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(wl.name)
     out = {
         "metric": "fused warp+LNCC fwd+bwd Gvoxel/s & %HBM peak; time-to-LNCC target vs plain",
         "value": round(gvox, 3),
