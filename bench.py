@@ -25,6 +25,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -100,6 +101,48 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 3):
                       "GBps_read_plus_write": 2 * nbytes / dt / 1e9}), flush=True)
 
 
+def extras(F, M, u, scratch, roi, nroi, wl, reps: int = 5):
+    """Per-call times of the kernels outside the step, on the same volumes
+    (HIP events on the current stream; not part of ms_per_step): Gaussian
+    smoothing of the 3-channel field, the approximate MI forward, and the
+    composite sampler (a small rotation about the centre with the
+    displacement added) in MI forward and adjoint.  Algorithmic bytes per
+    unit: smoothing 8 per element, MI forward 20 per ROI voxel, MI adjoint
+    through the composite sampler 20 per voxel (grad_u not written)."""
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    n_el = u.numel()
+    D, H, W = F.shape
+    c = [(W - 1) / 2, (H - 1) / 2, (D - 1) / 2]
+    ang = 0.05
+    A = [[math.cos(ang), -math.sin(ang), 0.0], [math.sin(ang), math.cos(ang), 0.0], [0.0, 0.0, 1.0]]
+    t = [c[0] - (A[0][0] * c[0] + A[0][1] * c[1]), c[1] - (A[1][0] * c[0] + A[1][1] * c[1]), 0.0]
+    res = {}
+    for sig in (1.0, 0.5):
+        ms = timed(lambda: ops.gaussian_smooth(u, sig, out=scratch))
+        res[f"smooth_sigma{sig:g}"] = {"ms": round(ms, 4), "frac": round(8 * n_el / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    ms = timed(lambda: ops.warp_mi_fwd(F, M, u, bins=wl.mi_bins, roi=roi, hard="approx"))
+    res["mi_fwd_approx"] = {"ms": round(ms, 4), "frac": round(20 * nroi / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    _, st = ops.warp_mi_affine_fwd(F, M, u, A=A, t=t, bins=wl.mi_bins, roi=roi)
+    ms = timed(lambda: ops.warp_mi_affine_fwd(F, M, u, A=A, t=t, bins=wl.mi_bins, roi=roi, state=st))
+    res["mi_affine_fwd"] = {"ms": round(ms, 4), "frac": round(20 * nroi / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    ms = timed(lambda: ops.warp_mi_affine_bwd(F, M, u, st, A=A, t=t, bins=wl.mi_bins, roi=roi))
+    res["mi_affine_bwd_At"] = {"ms": round(ms, 4),
+                               "frac": round(20 * F.numel() / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +151,9 @@ def main():
     ap.add_argument("--workload", default=C3.name)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slab", type=int, default=0, help="oracle z-slab depth (0 = whole volume)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the timings of the kernels outside the step (smoothing, approximate MI, "
+                         "composite sampler)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -220,6 +266,7 @@ def main():
         "loss": {"lncc_first": l0, "lncc_last": l1, "mi_last": mi1},
         "kernel_source_hash": kernel_source_hash(),
     }
+    out["extras"] = None if args.no_extras else extras(F, M, u_m, g_m, roi, nroi, wl)
     if not args.no_cpu_baseline:
         slab = F.shape[0] if args.cpu_slab <= 0 else min(args.cpu_slab, F.shape[0])
         out["cpu_baseline"] = cpu_baseline(F, M, u_l, wl.lncc_window, slab)
