@@ -91,6 +91,7 @@ struct MiArgs {
     int roi[6];
     int bins;
     int ntx, nty, zchunk, nblocks;
+    int ncopy;       // LDS histogram copies, a power of two (set by mi_fwd_launch)
     int affine;      // 1: composite sampler with aff
     Affine aff;
     double* apart;   // [nblocks][12] partial dL/dA, dL/dt (affine adjoint)

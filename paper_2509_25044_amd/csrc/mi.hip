@@ -17,7 +17,10 @@
 // same 4 x 4 patch, so the thread accumulates the patch in registers and
 // flushes it to an LDS histogram only when the patch moves.  LDS and global
 // histograms hold unsigned 64-bit fixed point (2^-32 units): integer atomics
-// commute, so the histogram is bitwise reproducible.  A one-block kernel
+// commute, so the histogram is bitwise reproducible.  Neighbouring voxels
+// have similar intensities and so hit the same bins; to keep the lanes of a
+// wave from serialising on one address, a block keeps several LDS copies of
+// its histogram and neighbouring lanes add into different copies.  A one-block kernel
 // then forms p, the marginals, MI and the log table T.
 // Backward: T in LDS, 4 x 4 weighted lookups per voxel, then the sampler's
 // derivative; grad_u written over the whole array (zero outside the ROI).
@@ -207,9 +210,10 @@ template <bool HARD, int PAD, bool AFF>
 __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long long* __restrict__ ghist,
                                                         unsigned long long* __restrict__ gflag)
 {
-    extern __shared__ unsigned long long hist[];  // [B*B]
-    const int B = a.bins, BB = B * B;
-    for (int q = threadIdx.x; q < BB; q += MI_NT) hist[q] = 0ull;
+    extern __shared__ unsigned long long hist[];  // a.ncopy copies of [B*B], stride B*B+1
+    const int B = a.bins, BB = B * B, CS = BB + 1;
+    for (int q = threadIdx.x; q < a.ncopy * CS; q += MI_NT) hist[q] = 0ull;
+    unsigned long long* const mine = hist + (threadIdx.x & (a.ncopy - 1)) * CS;
     __shared__ int nanflag;
     if (threadIdx.x == 0) nanflag = 0;
     __syncthreads();
@@ -236,7 +240,7 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 const unsigned long long v = to_fix(acc[i * 4 + jj]);
-                if (v) atomicAdd(&hist[fold(cm + i, B) * B + fold(cn + jj, B)], v);
+                if (v) atomicAdd(&mine[fold(cm + i, B) * B + fold(cn + jj, B)], v);
             }
     };
 
@@ -267,7 +271,8 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
     if (bad) nanflag = 1;
     __syncthreads();
     for (int q = threadIdx.x; q < BB; q += MI_NT) {
-        const unsigned long long v = hist[q];
+        unsigned long long v = 0ull;
+        for (int c = 0; c < a.ncopy; ++c) v += hist[c * CS + q];
         if (v) atomicAdd(&ghist[q], v);
     }
     if (threadIdx.x == 0 && nanflag) atomicOr(gflag, 1ull);
@@ -277,9 +282,10 @@ template <int PAD, bool AFF>
 __global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long long* __restrict__ ghist,
                                                          unsigned long long* __restrict__ gflag)
 {
-    extern __shared__ unsigned int cnt[];  // [B*B]
-    const int B = a.bins, BB = B * B;
-    for (int q = threadIdx.x; q < BB; q += MI_NT) cnt[q] = 0u;
+    extern __shared__ unsigned int cnt[];  // a.ncopy copies of [B*B], stride B*B+1
+    const int B = a.bins, BB = B * B, CS = BB + 1;
+    for (int q = threadIdx.x; q < a.ncopy * CS; q += MI_NT) cnt[q] = 0u;
+    unsigned int* const mine = cnt + (threadIdx.x & (a.ncopy - 1)) * CS;
     __shared__ int nanflag;
     if (threadIdx.x == 0) nanflag = 0;
     __syncthreads();
@@ -308,19 +314,20 @@ __global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long
             const int bm = min((int)floorf(fminf(fmaxf(mv, 0.0f), 1.0f) * fB), B - 1);
             const int q = bf * B + bm;
             if (q != cur) {
-                if (run) atomicAdd(&cnt[cur], run);
+                if (run) atomicAdd(&mine[cur], run);
                 cur = q;
                 run = 0u;
             }
             ++run;
         }
-        if (run) atomicAdd(&cnt[cur], run);
+        if (run) atomicAdd(&mine[cur], run);
     }
     if (bad) nanflag = 1;
     __syncthreads();
     for (int q = threadIdx.x; q < BB; q += MI_NT) {
-        const unsigned int v = cnt[q];
-        if (v) atomicAdd(&ghist[q], (unsigned long long)v);
+        unsigned long long v = 0ull;
+        for (int c = 0; c < a.ncopy; ++c) v += cnt[c * CS + q];
+        if (v) atomicAdd(&ghist[q], v);
     }
     if (threadIdx.x == 0 && nanflag) atomicOr(gflag, 1ull);
 }
@@ -556,7 +563,7 @@ static hipError_t mi_fwd_dispatch(const MiArgs& a, int hard, int pad, unsigned l
     const int BB = a.bins * a.bins;
     dim3 grid(a.nblocks), block(MI_NT);
     if (hard == 2) {
-        const size_t lds32 = sizeof(unsigned int) * BB;
+        const size_t lds32 = sizeof(unsigned int) * a.ncopy * (BB + 1);
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_count_kernel<PAD_BORDER, AFF>), grid, block, lds32, st, a, hist, flag);
         else hipLaunchKernelGGL((mi_count_kernel<PAD_ZEROS, AFF>), grid, block, lds32, st, a, hist, flag);
         hipError_t e = hipGetLastError();
@@ -564,7 +571,7 @@ static hipError_t mi_fwd_dispatch(const MiArgs& a, int hard, int pad, unsigned l
         hipLaunchKernelGGL(mi_finalize_approx, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, state, loss);
         return hipGetLastError();
     }
-    const size_t lds = sizeof(unsigned long long) * BB;
+    const size_t lds = sizeof(unsigned long long) * a.ncopy * (BB + 1);
     if (hard) {
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER, AFF>), grid, block, lds, st, a, hist, flag);
         else hipLaunchKernelGGL((mi_hist_kernel<true, PAD_ZEROS, AFF>), grid, block, lds, st, a, hist, flag);
@@ -578,10 +585,15 @@ static hipError_t mi_fwd_dispatch(const MiArgs& a, int hard, int pad, unsigned l
     return hipGetLastError();
 }
 
-hipError_t mi_fwd_launch(const MiArgs& a, int hard, int pad, unsigned long long* hist, float* state, float* loss,
+hipError_t mi_fwd_launch(const MiArgs& a0, int hard, int pad, unsigned long long* hist, float* state, float* loss,
                          double nroi, hipStream_t st)
 {
     (void)nroi;
+    MiArgs a = a0;
+    // LDS histogram copies: at most 4, and at most 66 KB of u64 bins (4
+    // copies up to 45 bins, 2 copies up to 64)
+    a.ncopy = 1;
+    while (a.ncopy < 4 && (size_t)2 * a.ncopy * (a.bins * a.bins + 1) * sizeof(unsigned long long) <= 67584) a.ncopy *= 2;
     const int BB = a.bins * a.bins;
     unsigned long long* flag = hist + BB;
     hipLaunchKernelGGL(mi_zero, dim3((BB + 1 + 255) / 256), dim3(256), 0, st, hist, BB + 1);
