@@ -109,6 +109,16 @@ __device__ __forceinline__ float ld(const float* __restrict__ base, unsigned idx
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + idx * 4u);
 }
 
+// Element-index product.  Below 2^30 voxels with H*W < 2^24 (the launcher
+// selects BIG otherwise) every factor fits 24 bits, so the full-rate 24-bit
+// multiplier replaces the quarter-rate 32-bit one.
+template <bool BIG>
+__device__ __forceinline__ unsigned imul(int a, int b)
+{
+    if (BIG) return (unsigned)(a * b);
+    return __umul24((unsigned)a, (unsigned)b);
+}
+
 template <bool BIG>
 __device__ __forceinline__ void st(float* __restrict__ base, unsigned idx, float v)
 {
@@ -146,8 +156,8 @@ __device__ __forceinline__ void issue_point(Pend& g, const float* __restrict__ M
     const int x0 = min(max(ix, 0), W - 1), x1 = min(max(ix + 1, 0), W - 1);
     const int y0 = min(max(iy, 0), H - 1), y1 = min(max(iy + 1, 0), H - 1);
     const int z0 = min(max(iz, 0), D - 1), z1 = min(max(iz + 1, 0), D - 1);
-    const unsigned r00 = (unsigned)(z0 * HW + y0 * W), r01 = (unsigned)(z0 * HW + y1 * W);
-    const unsigned r10 = (unsigned)(z1 * HW + y0 * W), r11 = (unsigned)(z1 * HW + y1 * W);
+    const unsigned q0 = imul<BIG>(z0, HW), q1 = imul<BIG>(z1, HW), p0 = imul<BIG>(y0, W), p1 = imul<BIG>(y1, W);
+    const unsigned r00 = q0 + p0, r01 = q0 + p1, r10 = q1 + p0, r11 = q1 + p1;
     g.c[0] = ld<BIG>(M, r00 + x0); g.c[1] = ld<BIG>(M, r00 + x1);
     g.c[2] = ld<BIG>(M, r01 + x0); g.c[3] = ld<BIG>(M, r01 + x1);
     g.c[4] = ld<BIG>(M, r10 + x0); g.c[5] = ld<BIG>(M, r10 + x1);
@@ -266,7 +276,7 @@ lncc_kernel(LnccArgs a)
     float pu[P][3];
     Pend pend[P];
     auto load_u = [&](int zs, int k0, int k1) {
-        const unsigned zoff = (unsigned)(min(max(zs, 0), D - 1) * HW);
+        const unsigned zoff = imul<BIG>(min(max(zs, 0), D - 1), HW);
 #pragma unroll
         for (int k = k0; k < k1; ++k) {
             if (k > 0 && hx[k - 1] < 0) continue;
@@ -280,7 +290,7 @@ lncc_kernel(LnccArgs a)
         }
     };
     auto issue = [&](int zs, int k0, int k1) {  // uses pu = u of slice zs
-        const unsigned zoff = (unsigned)(min(max(zs, 0), D - 1) * HW);
+        const unsigned zoff = imul<BIG>(min(max(zs, 0), D - 1), HW);
 #pragma unroll
         for (int k = k0; k < k1; ++k)
             if (k == 0 || hx[k - 1] >= 0)
@@ -464,7 +474,7 @@ lncc_kernel(LnccArgs a)
                         g1 = gm * sG[(sl * 3 + 1) * NT + tid];
                         g2 = gm * sG[(sl * 3 + 2) * NT + tid];
                     }
-                    const unsigned idx = (unsigned)(zc * HW + gy * W + gx);
+                    const unsigned idx = imul<BIG>(zc, HW) + imul<BIG>(gy, W) + gx;
                     st<BIG>(a.gu, idx, g0);
                     st<BIG>(a.gu + N, idx, g1);
                     st<BIG>(a.gu + 2 * N, idx, g2);
@@ -503,7 +513,7 @@ lncc_kernel(LnccArgs a)
                 const int gx = gx0 + ix, gy = gy0 + iy;
                 if (s >= 4 * r && zo >= z0 && zo < z1 && gx < W && gy < H) {
                     const float gm = zacc[so] * inv;
-                    const unsigned idx = (unsigned)(zo * HW + gy * W + gx);
+                    const unsigned idx = imul<BIG>(zo, HW) + imul<BIG>(gy, W) + gx;
                     st<BIG>(a.gu, idx, gm * sG[(so * 3 + 0) * NT + tid]);
                     st<BIG>(a.gu + N, idx, gm * sG[(so * 3 + 1) * NT + tid]);
                     st<BIG>(a.gu + 2 * N, idx, gm * sG[(so * 3 + 2) * NT + tid]);
@@ -554,7 +564,7 @@ template <int WIN, int MODE>
 static hipError_t launch_w(int pad, const LnccArgs& a, hipStream_t st)
 {
     dim3 grid(a.nblocks), block(LNCC_NT);
-    const bool big = (long long)a.D * a.H * a.W >= (1LL << 30);
+    const bool big = (long long)a.D * a.H * a.W >= (1LL << 30) || (long long)a.H * a.W >= (1LL << 24);
     if (pad == PAD_BORDER) {
         if (big) hipLaunchKernelGGL((lncc_kernel<WIN, MODE, PAD_BORDER, true>), grid, block, 0, st, a);
         else hipLaunchKernelGGL((lncc_kernel<WIN, MODE, PAD_BORDER, false>), grid, block, 0, st, a);
