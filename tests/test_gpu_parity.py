@@ -175,8 +175,62 @@ def _mi_case(F, M, u, bins=32, hard=False, pad="border", roi=None, what=""):
     np.testing.assert_allclose(st[B * B:2 * B * B].reshape(B, B), pr, rtol=1e-5, atol=atol)
     if mode == 1:
         assert float(g.abs().max()) == 0.0
+    elif mode == 2 and u is not None:
+        _mi_approx_grad(F, M, u, pad, roi, B, st, pr, _np(g), gr, nroi, what)
     else:
         assert_grad(_np(g), gr, f"{what} grad")
+
+
+def _mi_approx_grad(F, M, u, pad, roi, B, st, pr, g, gr, nroi, what):
+    """Approximate-mode gradient with a warped image.  A voxel whose warped
+    value lies within fp32 rounding of a bin edge may be counted in the
+    neighbouring bin on one side (the kernel forms the value in fp32, the
+    oracle in float64), and each such decision changes p, and so the log
+    table T = log p - log p_M, in the 3x3 bins around the two bins it moves
+    between.  Both tables are then correct for their own counts.  The
+    gradient is compared on the voxels where the two tables could move it by
+    less than a tenth of the tolerance; the decisions that differ must be
+    few, those voxels few, and every gradient finite."""
+    dp = np.abs(st[B * B:2 * B * B].reshape(B, B).astype(np.float64) - pr)
+    moved = 0.5 * dp.sum() * nroi  # voxels whose count moved, at least
+    assert moved <= max(3.0, 1e-4 * nroi), f"{what}: {moved:.1f} voxels change bins"
+    pm = pr.sum(axis=0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t_orc = np.where(pr > 0, np.log(pr) - np.log(pm)[None, :], 0.0)
+    dt = np.abs(st[:B * B].reshape(B, B).astype(np.float64) - t_orc)
+    # bound on |g_gpu - g_ref| from dt alone at each voxel:
+    # |dMw/dp| / N_roi * sum_ab kappa_a(F) |dkappa_b/dv(Mw)| dt[a, b]
+    # over the 4x4 cubic B-spline patch (the kernel's form of the sum)
+    mw, dmw = oracle.warp(M.numpy(), u.numpy(), pad=1 if pad == "zeros" else 0, with_grad=True)
+    def patch(v):
+        vc = np.clip(v, 0.0, 1.0)
+        sv = vc * B - 0.5
+        f = np.floor(sv)
+        t = sv - f
+        q = 1.0 - t
+        w = np.stack([q ** 3 / 6, 0.5 * t ** 3 - t * t + 2.0 / 3, 0.5 * q ** 3 - q * q + 2.0 / 3, t ** 3 / 6])
+        ds = np.where((v >= 0.0) & (v <= 1.0), float(B), 0.0)
+        dw = np.abs(np.stack([-0.5 * q * q, 1.5 * t * t - 2 * t, -1.5 * q * q + 2 * q, 0.5 * t * t])) * ds
+        return f.astype(np.int64) - 1, w, dw
+    jf, wf, _ = patch(F.numpy().astype(np.float64))
+    jm, _, dm = patch(mw)
+    bound = np.zeros(F.shape)
+    for a in range(4):
+        for b in range(4):
+            bound += wf[a] * dm[b] * dt[np.clip(jf + a, 0, B - 1), np.clip(jm + b, 0, B - 1)]
+    bound *= np.abs(dmw).max(axis=0) / nroi
+    if roi is not None:
+        inside = np.zeros(F.shape, dtype=bool)
+        inside[tuple(slice(a, b) for a, b in roi)] = True
+        bound *= inside
+    touch = bound > 1e-5 * np.abs(gr).max()
+    assert np.all(np.isfinite(g)), f"{what}: non-finite gradient"
+    frac = touch.mean()
+    print(f"  {what}: >= {moved:.1f} voxels moved bins, {int((dt > 1e-5).sum())} log-table entries differ, "
+          f"{frac:.5f} of the voxels could see it", flush=True)
+    assert frac <= 0.02, f"{what}: {frac:.4f} of the voxels read a log-table entry that differs"
+    keep = ~touch
+    assert_grad(g * keep[None], gr * keep[None], f"{what} grad (voxels with agreeing tables, {1 - frac:.5f})")
 
 
 def test_mi_c1_pair(c1):
@@ -209,6 +263,16 @@ def test_mi_approx_estimator(c1, c2):
     _mi_case(F, M, u * 3, bins=32, hard="approx", pad="zeros", what="c1 approx zeros")
     F2, M2, u2 = c2
     _mi_case(F2, M2, u2, bins=32, hard="approx", what="c2 approx")
+
+
+@pytest.mark.parametrize("bins", [8, 45, 46, 64])
+def test_mi_bin_counts_and_histogram_copies(c1, bins):
+    """Bin counts on both sides of the LDS layout change (4 histogram copies
+    up to 45 bins, 2 copies above, 64 KB of LDS at 64 bins)."""
+    F, M, u = c1
+    _mi_case(F, M, u, bins=bins, what=f"c1 b{bins}")
+    if bins in (45, 64):
+        _mi_case(F, M, u, bins=bins, hard="approx", what=f"c1 approx b{bins}")
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (37, 45, 70)])
