@@ -151,27 +151,43 @@ def _remap_coeffs(rng):
 
 
 def make_pair(spec: PairSpec, seed: int = BASE_SEED, device="cpu",
-              with_disp: bool = True, z_range: Optional[Tuple[int, int]] = None, noise_on_device: bool = False):
+              with_disp: bool = True, z_range: Optional[Tuple[int, int]] = None, noise_on_device: bool = False,
+              grid: Optional[Tuple[int, int, int]] = None):
     """Return dict(F, M, d) as float32 tensors on ``device``.
 
     ``z_range`` restricts evaluation to slices [z0, z1) of the full volume (the
     random parameters and the normalisation constants are those of the full
     volume only when the whole volume is generated; slab generation is for
-    memory-bounded timing samples and uses the slab's own min/max)."""
+    memory-bounded timing samples and uses the slab's own min/max).
+
+    ``grid`` (Dc, Hc, Wc) evaluates the same continuous pair on a coarser
+    corner-aligned grid (point i of an axis sits at i (n - 1)/(nc - 1) voxels
+    of the full volume): the pair a downsampling of the full volume would
+    see, without generating it.  d is then in the coarse grid's voxels, and
+    the displacement scale, noise and normalisation come from the grid's own
+    points."""
     st = _streams(seed)
     D, H, W = spec.shape
-    z0, z1 = (0, D) if z_range is None else z_range
-    shape = (z1 - z0, H, W)
     dt = torch.float64
-    z, y, x = _coords(spec.shape, device, dt)
-    z = z[z0:z1]
+    if grid is not None:
+        if z_range is not None:
+            raise ValueError("grid and z_range are exclusive")
+        shape = tuple(int(g) for g in grid)
+        z, y, x = _coords(shape, device, dt)
+        fs = [(n - 1) / (c - 1) if c > 1 else 0.0 for n, c in zip(spec.shape, shape)]  # full voxels per grid step
+        z, y, x = z * fs[0], y * fs[1], x * fs[2]
+    else:
+        z0, z1 = (0, D) if z_range is None else z_range
+        shape = (z1 - z0, H, W)
+        z, y, x = _coords(spec.shape, device, dt)
+        z = z[z0:z1]
     blobs = _blob_params(st["blobs"], spec)
     dmodes = _disp_modes(st["disp"], spec)
     tmodes = _texture_modes(st["texture"], spec) if spec.texture_std > 0 else None
 
     # known displacement, scaled to max norm; the scale is set on the full volume
     d = torch.stack([_eval_modes(dmodes[c], z, y, x, shape, device, dt) for c in range(3)])
-    if z_range is None:
+    if z_range is None:  # the whole volume, or the coarse grid's points
         peak = torch.sqrt((d * d).sum(0)).max()
     else:  # scale from the full volume, computed slab-wise to bound memory
         peak = torch.zeros((), device=device, dtype=dt)
@@ -202,6 +218,9 @@ def make_pair(spec: PairSpec, seed: int = BASE_SEED, device="cpu",
         _minmax_(Mv)
     out = {"F": Fv.to(torch.float32).contiguous(), "M": Mv.to(torch.float32).contiguous()}
     if with_disp:
+        if grid is not None:  # full-volume voxels -> grid voxels (channel 0 is x)
+            for c, f in enumerate((fs[2], fs[1], fs[0])):
+                d[c].mul_(1.0 / f if f > 0 else 0.0)
         out["d"] = d.to(torch.float32).contiguous()
     return out
 

@@ -43,3 +43,26 @@ def test_moving_image_follows_the_known_displacement():
 
 def test_clinical_shape():
     assert C2.shape == (160, 192, 224)
+
+
+def test_coarse_grid_is_the_subsampled_continuous_pair():
+    """make_pair(grid=...) evaluates the same continuous pair at the corner-
+    aligned coarse points: with noise off, F equals the full volume's every
+    4th voxel once both are min-max normalised over those points, d is the
+    full displacement in coarse voxels up to the max-norm scale (taken over
+    the coarse points), and M differs only through that scale."""
+    spec = synth.PairSpec((33, 41, 49), (2.0, 5.0), 3.0, noise_std=0.0, texture_std=0.05)
+    full = synth.make_pair(spec, seed=11)
+    co = synth.make_pair(spec, seed=11, grid=(9, 11, 13))
+    assert co["F"].shape == (9, 11, 13) and co["d"].shape == (3, 9, 11, 13)
+
+    def renorm(t):
+        t = t.double()
+        return (t - t.min()) / (t.max() - t.min())
+
+    assert torch.allclose(renorm(full["F"][::4, ::4, ::4]), co["F"].double(), atol=2e-6)
+    assert torch.allclose(renorm(full["M"][::4, ::4, ::4]), co["M"].double(), atol=2e-2)
+    ratio = co["d"].double() / (full["d"][:, ::4, ::4, ::4].double() / 4.0)
+    big = full["d"][:, ::4, ::4, ::4].abs() > 0.05
+    r = ratio[big]
+    assert float(r.max() - r.min()) < 1e-5 and abs(float(r.mean()) - 1.0) < 0.05
