@@ -103,12 +103,15 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 3):
 
 def extras(F, M, u, scratch, roi, nroi, wl, reps: int = 5):
     """Per-call times of the kernels outside the step, on the same volumes
-    (HIP events on the current stream; not part of ms_per_step): Gaussian
-    smoothing of the 3-channel field, the approximate MI forward, and the
-    composite sampler (a small rotation about the centre with the
-    displacement added) in MI forward and adjoint.  Algorithmic bytes per
-    unit: smoothing 8 per element, MI forward 20 per ROI voxel, MI adjoint
-    through the composite sampler 20 per voxel (grad_u not written)."""
+    (HIP events on the current stream; not part of ms_per_step): the fused
+    LNCC forward+adjoint at u = 0 (every gather aligned on a voxel, the easy
+    case) and the LNCC forward alone at the step's u, Gaussian smoothing of
+    the 3-channel field, the approximate MI forward, and the composite
+    sampler (a small rotation about the centre with the displacement added)
+    in MI forward and adjoint.  Algorithmic bytes per unit: LNCC
+    forward+adjoint 32 and forward 20 per ROI voxel, smoothing 8 per element,
+    MI forward 20 per ROI voxel, MI adjoint through the composite sampler 20
+    per voxel (grad_u not written)."""
     stream = torch.cuda.current_stream()
 
     def timed(fn):
@@ -129,6 +132,16 @@ def extras(F, M, u, scratch, roi, nroi, wl, reps: int = 5):
     A = [[math.cos(ang), -math.sin(ang), 0.0], [math.sin(ang), math.cos(ang), 0.0], [0.0, 0.0, 1.0]]
     t = [c[0] - (A[0][0] * c[0] + A[0][1] * c[1]), c[1] - (A[1][0] * c[0] + A[1][1] * c[1]), 0.0]
     res = {}
+    u0 = torch.zeros_like(u)
+    ws = torch.empty(ops.lncc_workspace_bytes(F.shape, roi, wl.lncc_window), dtype=torch.uint8, device=u.device)
+    ms = timed(lambda: ops.warp_lncc_bwd(F, M, u0, window=wl.lncc_window, eps=wl.lncc_eps, roi=roi, grad_u=scratch,
+                                         ws=ws))
+    res["lncc_fwd_bwd_u0"] = {"ms": round(ms, 4), "gvoxel_per_s": round(nroi / (ms * 1e-3) / 1e9, 3),
+                              "frac": round(32 * nroi / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del u0
+    ms = timed(lambda: ops.warp_lncc_fwd(F, M, u, window=wl.lncc_window, eps=wl.lncc_eps, roi=roi, ws=ws))
+    res["lncc_fwd"] = {"ms": round(ms, 4), "gvoxel_per_s": round(nroi / (ms * 1e-3) / 1e9, 3),
+                       "frac": round(20 * nroi / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     for sig in (1.0, 0.5):
         ms = timed(lambda: ops.gaussian_smooth(u, sig, out=scratch))
         res[f"smooth_sigma{sig:g}"] = {"ms": round(ms, 4), "frac": round(8 * n_el / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
