@@ -298,19 +298,20 @@ lncc_kernel(LnccArgs a)
                                       pu[k][1], pu[k][2]);
     };
     // Schedule: the gathers of slice zi+1 are issued at the end of stage A of
-    // slice zi.  Forward and ANTs kernels load the u they need two slices
-    // ahead, in stage C of slice zi-1.  The adjoint kernel, whose registers
-    // are at the limit, loads the tile point's u at the start of stage A, and
-    // its halo points load u of zi+1 at the start of stage D and issue their
-    // gathers at the end of the slice (they are consumed after the tile point
-    // in the next stage A); this keeps them out of stages B and C, the peak
-    // of register pressure.  (Measured: the two-slice-ahead load slows the
-    // adjoint kernel by 9% and speeds the others.)
+    // slice zi, from u loaded two slices ahead.  Forward and ANTs kernels load
+    // that u in stage C.  The adjoint kernel, whose registers are at the
+    // limit, keeps every load out of stages B and C (the peak of register
+    // pressure): its halo points load u of zi+1 at the start of stage D and
+    // issue their gathers at the end of the slice (they are consumed after
+    // the tile point in the next stage A), and the tile point's u of zi+2 is
+    // loaded after those gathers.  (Measured on the adjoint: the u load in
+    // stage C is 9% slower, at the start of stage D or E 8-10% slower, at the
+    // start of stage A 3% slower.  The memory counter retires loads in
+    // order, so where a load sits decides which waits it lengthens.)
     constexpr int KH = (MODE == MODE_BWD) ? 1 : P;  // points issued right after stage A
-    constexpr bool AHEAD2 = MODE != MODE_BWD;
     load_u(z0 - R2, 0, P);
     issue(z0 - R2, 0, P);
-    if (AHEAD2) load_u(z0 - R2 + 1, 0, KH);
+    load_u(z0 - R2 + 1, 0, KH);
 
     const int nsteps = (z1 - z0) + 2 * R2;
     for (int base = 0; base < nsteps; base += WIN) {
@@ -320,7 +321,6 @@ lncc_kernel(LnccArgs a)
             if (s >= nsteps) break;
             const int zi = z0 - R2 + s;  // slice entering the rings
             const bool zin = (zi >= 0) && (zi < D);
-            if (!AHEAD2) load_u(zi + 1, 0, KH);
             // ---- stage A: sample, push into the rings, z-window sums ----
             // Raised wave priority while the gathers of this slice are
             // consumed and those of the next are issued: the stage that ends
@@ -378,7 +378,7 @@ lncc_kernel(LnccArgs a)
             issue(zi + 1, 0, KH);
             __builtin_amdgcn_s_setprio(0);
             if (s < 2 * r) {  // rings not yet full (uniform over the block)
-                if (AHEAD2) load_u(zi + 2, 0, KH);
+                load_u(zi + 2, 0, KH);
                 if (KH < P) {
                     load_u(zi + 1, KH, P);
                     issue(zi + 1, KH, P);
@@ -396,7 +396,7 @@ lncc_kernel(LnccArgs a)
             }
             __syncthreads();
             // ---- stage C: y-window, statistics, loss term, adjoint fields ----
-            if (AHEAD2) load_u(zi + 2, 0, KH);
+            if (MODE != MODE_BWD) load_u(zi + 2, 0, KH);
             const int zc = zi - r;
             const bool zroi = zc >= a.roi[0] && zc < a.roi[1];
             const bool zown = zc >= z0 && zc < z1;
@@ -527,6 +527,7 @@ lncc_kernel(LnccArgs a)
                 zacc[so] = 0.f;  // the slot of the next new pending output
             }
             issue(zi + 1, KH, P);
+            load_u(zi + 2, 0, KH);
         }
     }
     // ---- block loss partial (fixed-order tree) ----
