@@ -106,3 +106,20 @@ def test_resample_matches_torch_interpolate(orc):
     ref = torch.nn.functional.interpolate(torch.from_numpy(src.astype(np.float64))[None], size=(9, 13, 11),
                                           mode="trilinear", align_corners=True)[0].numpy() * 2.0
     np.testing.assert_allclose(out, ref, rtol=0, atol=1e-13)
+
+
+def test_ring_sampler_slab_identity(orc):
+    """The ring sampler's decomposition (Sec. "Ring Sampler", eq. interp-h):
+    with zero padding, warping M equals the sum over z-slabs of warping the
+    slab alone (M outside the slab set to zero), because the trilinear value
+    is linear in M and each corner lies in exactly one slab."""
+    shape = (23, 9, 11)
+    M = synth.random_volume(shape, 5).numpy()
+    u = synth.random_disp(shape, 6, 3.0).numpy()
+    full = orc.warp(M, u, pad=1)
+    acc = np.zeros_like(full)
+    for a, b in ((0, 7), (7, 8), (8, 23)):
+        Ms = np.zeros_like(M)
+        Ms[a:b] = M[a:b]
+        acc += orc.warp(Ms, u, pad=1)
+    np.testing.assert_allclose(acc, full, rtol=0, atol=1e-12)
