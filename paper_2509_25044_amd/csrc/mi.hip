@@ -37,8 +37,6 @@
 
 namespace ffdp {
 
-constexpr double FIX_ONE = 4294967296.0;  // 2^32
-
 // Four cubic B-spline weights of v on bins j0..j0+3 (before folding) and, with
 // DERIV, their derivatives with respect to v.  Hard mode: one unit weight.
 template <bool HARD, bool DERIV>
@@ -85,7 +83,16 @@ __device__ __forceinline__ void sample_disp(const MiArgs& a, int x, int y, int z
 
 __device__ __forceinline__ unsigned long long to_fix(float x)
 {
-    return (unsigned long long)fma((double)x, FIX_ONE, 0.5);
+    // round(x 2^32) for 0 <= x < 2^24 in exact fp32 and integer steps (the
+    // same value as the float64 fma x * 2^32 + 0.5 truncated, without
+    // half-rate float64 work): integer part, then the fraction scaled by 2^32
+    // (exact), truncated, plus one where the exact remainder is >= 1/2
+    const unsigned hi = (unsigned)x;
+    const float f = x - (float)hi;
+    const float t = f * 4294967296.0f;
+    const unsigned lo = (unsigned)t;
+    const unsigned up = (t - (float)lo) >= 0.5f ? 1u : 0u;
+    return ((unsigned long long)hi << 32) + (lo + up);
 }
 
 // Loads of one voxel's sample, issued one z-step ahead of their use (the
@@ -240,7 +247,7 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
                 const unsigned long long v = to_fix(acc[i * 4 + jj]);
-                if (v) atomicAdd(&mine[fold(cm + i, B) * B + fold(cn + jj, B)], v);
+                atomicAdd(&mine[fold(cm + i, B) * B + fold(cn + jj, B)], v);  // unconditional: no branch per tap
             }
     };
 
