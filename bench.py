@@ -106,7 +106,8 @@ def extras(F, M, u, scratch, roi, nroi, wl, reps: int = 5):
     (HIP events on the current stream; not part of ms_per_step): the fused
     LNCC forward+adjoint at u = 0 (every gather aligned on a voxel, the easy
     case) and the LNCC forward alone at the step's u, Gaussian smoothing of
-    the 3-channel field, the approximate MI forward, and the composite
+    the 3-channel field, the fused smoothing + Adam step against the two
+    calls, the approximate MI forward, and the composite
     sampler (a small rotation about the centre with the displacement added)
     in MI forward and adjoint.  Algorithmic bytes per unit: LNCC
     forward+adjoint 32 and forward 20 per ROI voxel, smoothing 8 per element,
@@ -145,6 +146,16 @@ def extras(F, M, u, scratch, roi, nroi, wl, reps: int = 5):
     for sig in (1.0, 0.5):
         ms = timed(lambda: ops.gaussian_smooth(u, sig, out=scratch))
         res[f"smooth_sigma{sig:g}"] = {"ms": round(ms, 4), "frac": round(8 * n_el / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    # the registration loop's optimiser step with the gradient smoothed
+    # (sigma_grad = 1): fused, against smoothing then Adam (28 and 8 + 28 B
+    # per element)
+    x, m, v = u.clone(), torch.zeros_like(u), torch.zeros_like(u)
+    ms = timed(lambda: ops.smooth_adam_step(x, u, m, v, 1.0, lr=1e-6))
+    res["smooth_adam_sigma1"] = {"ms": round(ms, 4),
+                                 "frac": round(28 * n_el / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    ms = timed(lambda: ops.adam_step(x, ops.gaussian_smooth(u, 1.0, out=scratch), m, v, lr=1e-6))
+    res["smooth_then_adam_sigma1"] = {"ms": round(ms, 4)}
+    del x, m, v
     ms = timed(lambda: ops.warp_mi_fwd(F, M, u, bins=wl.mi_bins, roi=roi, hard="approx"))
     res["mi_fwd_approx"] = {"ms": round(ms, 4), "frac": round(20 * nroi / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     _, st = ops.warp_mi_affine_fwd(F, M, u, A=A, t=t, bins=wl.mi_bins, roi=roi)

@@ -229,6 +229,17 @@ int ffdp_adam_step(float* x, const float* g, float* m, float* v, int64_t n, floa
 int ffdp_gaussian_smooth(const float* in, float* out, int64_t D, int64_t H, int64_t W, int32_t channels, float sigma,
                          void* stream);
 
+/* One optimiser step of the registration loop with the gradient smoothed
+ * first (Sec. "Grid Parallel"; sigma_grad = 1 in the experiments): exactly
+ * ffdp_gaussian_smooth(g -> s, sigma) followed by ffdp_adam_step(x, s, m, v)
+ * on the same [channels][D][H][W] arrays, bitwise, without writing s.
+ * x, m, v are updated in place; g is read only and must not overlap x, m or
+ * v (nor may x, m, v overlap each other).  Parameter rules as for those two
+ * calls. */
+int ffdp_smooth_adam_step(float* x, const float* g, float* m, float* v, int64_t D, int64_t H, int64_t W,
+                          int32_t channels, float sigma, float lr, float beta1, float beta2, float eps, int64_t step,
+                          void* stream);
+
 /* ------------------------------------------------------------------------
  * Warm-start network (3D U-Net) kernels.  BF16 operands on MFMA with FP32
  * accumulation.  Activations are channels-last bf16 [N][D][H][W][C]

@@ -81,6 +81,7 @@ def lib():
         "ffdp_warp_mi_affine_bwd": ([vp, vp, vp, gp, ap, mp, vp, vp, vp, vp, vp, sz, vp], C.c_int),
         "ffdp_adam_step": ([vp, vp, vp, vp, i64, f32, f32, f32, f32, i64, vp], C.c_int),
         "ffdp_gaussian_smooth": ([vp, vp, i64, i64, i64, i32, f32, vp], C.c_int),
+        "ffdp_smooth_adam_step": ([vp, vp, vp, vp, i64, i64, i64, i32, f32, f32, f32, f32, f32, i64, vp], C.c_int),
         "ffdp_conv3d_fwd": ([vp, vp, vp, vp, cg, i32, f32, vp, vp, vp], C.c_int),
         "ffdp_conv3d_bwd_data": ([vp, vp, f32, vp, cg, vp, i32, vp], C.c_int),
         "ffdp_conv3d_bwd_weight_workspace_bytes": ([cg], sz),

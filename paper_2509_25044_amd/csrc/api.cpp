@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include "../../include/ffdp.h"
+#include "adam.hpp"
 #include "internal.hpp"
 
 using namespace ffdp;
@@ -433,6 +434,32 @@ int ffdp_warp_mi_affine_bwd(const float* F, const float* M, const float* u, cons
     return hip_status(e, "ffdp_warp_mi_affine_bwd");
 }
 
+static int check_adam(float lr, float beta1, float beta2, float eps, int64_t step)
+{
+    if (step < 1) return fail(FFDP_ERR_PARAM, "step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+        return fail(FFDP_ERR_PARAM, "betas must be in [0, 1)");
+    if (!(eps > 0.0f) || !isfinite(eps) || !isfinite(lr)) return fail(FFDP_ERR_PARAM, "eps > 0, lr finite required");
+    return FFDP_OK;
+}
+
+// taps exp(-t^2 / (2 sigma^2)) for |t| <= R = ceil(3 sigma), normalised in double
+static int gaussian_taps(float sigma, float* w)
+{
+    const int R = (int)ceil(3.0 * (double)sigma);
+    double tot = 0.0, e[2 * SMOOTH_MAX_R + 1];
+    for (int t = -R; t <= R; ++t) tot += (e[t + R] = exp(-(double)t * t / (2.0 * (double)sigma * sigma)));
+    for (int k = 0; k <= 2 * R; ++k) w[k] = (float)(e[k] / tot);
+    return R;
+}
+
+static bool overlap(const void* p, const void* q, size_t bytes)
+{
+    const char* a = (const char*)p;
+    const char* b = (const char*)q;
+    return a < b + bytes && b < a + bytes;
+}
+
 int ffdp_adam_step(float* x, const float* g, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
                    float eps, int64_t step, void* stream)
 {
@@ -440,10 +467,7 @@ int ffdp_adam_step(float* x, const float* g, float* m, float* v, int64_t n, floa
     if (n < 0) return fail(FFDP_ERR_SHAPE, "n must be >= 0");
     if (n == 0) return FFDP_OK;
     if ((s = check_ptrs("x,g,m,v", 4, (const void*)x, (const void*)g, (const void*)m, (const void*)v))) return s;
-    if (step < 1) return fail(FFDP_ERR_PARAM, "step must be >= 1");
-    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
-        return fail(FFDP_ERR_PARAM, "betas must be in [0, 1)");
-    if (!(eps > 0.0f) || !isfinite(eps) || !isfinite(lr)) return fail(FFDP_ERR_PARAM, "eps > 0, lr finite required");
+    if ((s = check_adam(lr, beta1, beta2, eps, step))) return s;
     return hip_status(adam_launch(x, g, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream),
                       "ffdp_adam_step");
 }
@@ -456,19 +480,33 @@ int ffdp_gaussian_smooth(const float* in, float* out, int64_t D, int64_t H, int6
     if (channels < 1 || channels > 65535) return fail(FFDP_ERR_PARAM, "channels must be in [1, 65535]");
     if (!(sigma > 0.0f && sigma <= 2.0f)) return fail(FFDP_ERR_PARAM, "sigma must be in (0, 2]");
     if ((s = check_ptrs("in,out", 2, (const void*)in, (const void*)out))) return s;
-    const char* a0 = (const char*)in;
-    const char* a1 = a0 + (size_t)channels * D * H * W * sizeof(float);
-    const char* b0 = (const char*)out;
-    const char* b1 = b0 + (size_t)channels * D * H * W * sizeof(float);
-    if (a0 < b1 && b0 < a1) return fail(FFDP_ERR_PARAM, "in and out overlap");
-    // taps exp(-t^2 / (2 sigma^2)) for |t| <= ceil(3 sigma), normalised in double
-    const int R = (int)ceil(3.0 * (double)sigma);
+    if (overlap(in, out, (size_t)channels * D * H * W * sizeof(float))) return fail(FFDP_ERR_PARAM, "in and out overlap");
     SmoothWeights w{};
-    double tot = 0.0, e[2 * SMOOTH_MAX_R + 1];
-    for (int t = -R; t <= R; ++t) tot += (e[t + R] = exp(-(double)t * t / (2.0 * (double)sigma * sigma)));
-    for (int k = 0; k <= 2 * R; ++k) w.w[k] = (float)(e[k] / tot);
+    const int R = gaussian_taps(sigma, w.w);
     return hip_status(smooth_launch(in, out, (int)D, (int)H, (int)W, channels, w, R, (hipStream_t)stream),
                       "ffdp_gaussian_smooth");
+}
+
+int ffdp_smooth_adam_step(float* x, const float* g, float* m, float* v, int64_t D, int64_t H, int64_t W,
+                          int32_t channels, float sigma, float lr, float beta1, float beta2, float eps, int64_t step,
+                          void* stream)
+{
+    int s;
+    if ((s = check_dims(D, H, W))) return s;
+    if (channels < 1 || channels > 65535) return fail(FFDP_ERR_PARAM, "channels must be in [1, 65535]");
+    if (!(sigma > 0.0f && sigma <= 2.0f)) return fail(FFDP_ERR_PARAM, "sigma must be in (0, 2]");
+    if ((s = check_ptrs("x,g,m,v", 4, (const void*)x, (const void*)g, (const void*)m, (const void*)v))) return s;
+    if ((s = check_adam(lr, beta1, beta2, eps, step))) return s;
+    const size_t bytes = (size_t)channels * D * H * W * sizeof(float);
+    if (overlap(g, x, bytes) || overlap(g, m, bytes) || overlap(g, v, bytes) || overlap(x, m, bytes) ||
+        overlap(x, v, bytes) || overlap(m, v, bytes))
+        return fail(FFDP_ERR_PARAM, "x, g, m and v must not overlap");
+    float taps[2 * SMOOTH_MAX_R + 1];
+    const int R = gaussian_taps(sigma, taps);
+    const AdamK k = adam_constants(lr, beta1, beta2, eps, step);
+    return hip_status(smooth_adam_launch(x, g, m, v, (int)D, (int)H, (int)W, channels, taps, R, k,
+                                         (hipStream_t)stream),
+                      "ffdp_smooth_adam_step");
 }
 
 }  // extern "C"

@@ -1,4 +1,5 @@
 // Streaming kernels: standalone warp, pyramid resample, Adam.
+#include "adam.hpp"
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -185,17 +186,6 @@ hipError_t resample_launch(const float* src, int sD, int sH, int sW, float* dst,
 
 // Adam, 4 elements per thread per iteration when every pointer is 16-byte
 // aligned (the float4 path moves 1 KiB per wave instruction).
-struct AdamK {
-    float b1, b2, eps, step_size, inv_sqrt_bc2;
-};
-
-__device__ __forceinline__ void adam1(float& x, float g, float& m, float& v, const AdamK& k)
-{
-    m = fmaf(k.b1, m, (1.0f - k.b1) * g);
-    v = fmaf(k.b2, v, (1.0f - k.b2) * g * g);
-    x -= k.step_size * m / fmaf(sqrtf(v), k.inv_sqrt_bc2, k.eps);
-}
-
 __global__ void __launch_bounds__(256) adam_vec_kernel(float4* __restrict__ x, const float4* __restrict__ g,
                                                        float4* __restrict__ m, float4* __restrict__ v, size_t n4,
                                                        AdamK k)
@@ -224,12 +214,7 @@ __global__ void __launch_bounds__(256) adam_scalar_kernel(float* __restrict__ x,
 hipError_t adam_launch(float* x, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, int64_t step, hipStream_t st)
 {
-    AdamK k;
-    k.b1 = b1; k.b2 = b2; k.eps = eps;
-    const double bc1 = 1.0 - pow((double)b1, (double)step);
-    const double bc2 = 1.0 - pow((double)b2, (double)step);
-    k.step_size = (float)((double)lr / bc1);
-    k.inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+    const AdamK k = adam_constants(lr, b1, b2, eps, step);
     const bool aligned = ((((uintptr_t)x) | ((uintptr_t)g) | ((uintptr_t)m) | ((uintptr_t)v)) & 15) == 0;
     const size_t nn = (size_t)n;
     size_t done = 0;

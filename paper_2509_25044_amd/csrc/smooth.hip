@@ -19,6 +19,12 @@
 // Two barriers per slice (the write of step 1 and the x outputs of step 3).
 // HBM traffic is one read and one write per element plus the z halo of each
 // chunk (2R slices per chunk of at least 32).
+//
+// The ADAM variant applies the optimiser step to (x, m, v) with the smoothed
+// value as the gradient where the plain kernel would store it: the smoothed
+// gradient of the registration loop never reaches HBM (24 bytes per element
+// saved against smoothing then stepping), with bitwise the same result.
+#include "adam.hpp"
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -39,9 +45,10 @@ struct SmoothTile {
     static_assert(X2p >= SM_TX - 4 + 4 * NF4, "x runs stay inside the row");
 };
 
-template <int R>
+template <int R, bool ADAM>
 __global__ void __launch_bounds__(SM_NT) smooth_kernel(const float* __restrict__ in, float* __restrict__ out, int D,
-                                                       int H, int W, SmoothWeights wts, int zchunk, int nty)
+                                                       int H, int W, SmoothWeights wts, int zchunk, int nty,
+                                                       float* __restrict__ am, float* __restrict__ av, AdamK ak)
 {
     using T = SmoothTile<R>;
     constexpr int K = T::K, X2 = T::X2, X2p = T::X2p, PL = T::PL;
@@ -134,15 +141,26 @@ __global__ void __launch_bounds__(SM_NT) smooth_kernel(const float* __restrict__
                     // ring slot of slice zo - R + k is (j + 1 + k) % K
 #pragma unroll
                     for (int k = 0; k < K; ++k) o = fmaf(g[k], ring[e][(j + 1 + k) % K], o);
-                    dst[(size_t)zo * HW + (size_t)gy * W + gx] = o;
+                    const size_t idx = (size_t)zo * HW + (size_t)gy * W + gx;
+                    if (ADAM) {  // out is x; m, v at the same offsets
+                        const size_t ci = (size_t)c * N + idx;
+                        float xx = dst[idx], mm = am[ci], vv = av[ci];
+                        adam1(xx, o, mm, vv, ak);
+                        dst[idx] = xx;
+                        am[ci] = mm;
+                        av[ci] = vv;
+                    } else {
+                        dst[idx] = o;
+                    }
                 }
             }
         }
     }
 }
 
-hipError_t smooth_launch(const float* in, float* out, int D, int H, int W, int channels, const SmoothWeights& w,
-                         int R, hipStream_t st)
+template <bool ADAM>
+static hipError_t smooth_dispatch(const float* in, float* out, int D, int H, int W, int channels,
+                                  const SmoothWeights& w, int R, float* am, float* av, const AdamK& ak, hipStream_t st)
 {
     const int ntx = (W + SM_TX - 1) / SM_TX, nty = (H + SM_TY - 1) / SM_TY;
     const int tiles = ntx * nty;
@@ -153,16 +171,36 @@ hipError_t smooth_launch(const float* in, float* out, int D, int H, int W, int c
     const int zchunk = (D + chunks - 1) / chunks;
     chunks = (D + zchunk - 1) / zchunk;
     dim3 grid(ntx, nty * chunks, channels), block(SM_NT);
+#define FFDP_SMOOTH_CASE(RR)                                                                                    \
+    case RR:                                                                                                     \
+        hipLaunchKernelGGL((smooth_kernel<RR, ADAM>), grid, block, 0, st, in, out, D, H, W, w, zchunk, nty, am, av, \
+                           ak);                                                                                  \
+        break;
     switch (R) {
-        case 1: hipLaunchKernelGGL(smooth_kernel<1>, grid, block, 0, st, in, out, D, H, W, w, zchunk, nty); break;
-        case 2: hipLaunchKernelGGL(smooth_kernel<2>, grid, block, 0, st, in, out, D, H, W, w, zchunk, nty); break;
-        case 3: hipLaunchKernelGGL(smooth_kernel<3>, grid, block, 0, st, in, out, D, H, W, w, zchunk, nty); break;
-        case 4: hipLaunchKernelGGL(smooth_kernel<4>, grid, block, 0, st, in, out, D, H, W, w, zchunk, nty); break;
-        case 5: hipLaunchKernelGGL(smooth_kernel<5>, grid, block, 0, st, in, out, D, H, W, w, zchunk, nty); break;
-        case 6: hipLaunchKernelGGL(smooth_kernel<6>, grid, block, 0, st, in, out, D, H, W, w, zchunk, nty); break;
+        FFDP_SMOOTH_CASE(1)
+        FFDP_SMOOTH_CASE(2)
+        FFDP_SMOOTH_CASE(3)
+        FFDP_SMOOTH_CASE(4)
+        FFDP_SMOOTH_CASE(5)
+        FFDP_SMOOTH_CASE(6)
         default: return hipErrorInvalidValue;
     }
+#undef FFDP_SMOOTH_CASE
     return hipGetLastError();
+}
+
+hipError_t smooth_launch(const float* in, float* out, int D, int H, int W, int channels, const SmoothWeights& w,
+                         int R, hipStream_t st)
+{
+    return smooth_dispatch<false>(in, out, D, H, W, channels, w, R, nullptr, nullptr, AdamK{}, st);
+}
+
+hipError_t smooth_adam_launch(float* x, const float* g, float* m, float* v, int D, int H, int W, int channels,
+                              const float* taps, int R, const AdamK& k, hipStream_t st)
+{
+    SmoothWeights w{};
+    for (int t = 0; t <= 2 * R; ++t) w.w[t] = taps[t];
+    return smooth_dispatch<true>(g, x, D, H, W, channels, w, R, m, v, k, st);
 }
 
 }  // namespace ffdp

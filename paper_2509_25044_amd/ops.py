@@ -319,6 +319,24 @@ def gaussian_smooth(src: torch.Tensor, sigma: float, out=None) -> torch.Tensor:
                                                                    _stream(src)))
     return o4[0] if squeeze else o4
 
+
+def smooth_adam_step(x, g, m, v, sigma: float, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
+    """In-place Adam on x, m, v with the gradient g smoothed first, bitwise
+    gaussian_smooth then adam_step, the smoothed gradient never stored
+    (ffdp_smooth_adam_step).  All [C, D, H, W] or [D, H, W]."""
+    for t, n in ((x, "x"), (g, "g"), (m, "m"), (v, "v")):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"{n} must be a contiguous float32 device tensor")
+        if t.shape != x.shape:
+            raise ValueError("x, g, m, v must have the same shape")
+    shp = x.shape if x.dim() == 4 else (1,) + tuple(x.shape)
+    if len(shp) != 4:
+        raise ValueError("x must be [C, D, H, W] or [D, H, W]")
+    check("ffdp_smooth_adam_step", _lib.lib().ffdp_smooth_adam_step(
+        _ptr(x), _ptr(g), _ptr(m), _ptr(v), shp[1], shp[2], shp[3], shp[0], float(sigma), float(lr), float(beta1),
+        float(beta2), float(eps), int(step), _stream(x)))
+    return x
+
 # ------------------------------------------------------------ U-Net kernels --
 def _dev_t(t, name, dtype):
     if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous():

@@ -6,8 +6,8 @@ optimiser states m1, m2 per voxel of the displacement and smooths the
 gradient and the displacement; the experiments run per-scale iteration lists
 on image pyramids with sigma_grad = 1 and sigma_warp = 0.5 voxels).  Every
 iteration is library calls on the current HIP stream -- the fused
-loss+adjoint kernel, the optional Gaussian smoothing of the gradient, the
-Adam kernel, the optional smoothing of the displacement -- and the loss of
+loss+adjoint kernel, the Adam kernel (fused with the Gaussian smoothing of the
+gradient when that is on), the optional smoothing of the displacement -- and the loss of
 each iteration is written into a device buffer, so the loop never waits on
 the host.  Smoothing is off by default (sigma 0).
 
@@ -141,11 +141,12 @@ class Registration:
             _, state = ops.warp_mi_fwd(F, M, st.u, bins=c.bins, pad=c.pad, roi=self._roi(lv), loss=loss_out)
             grad = ops.warp_mi_bwd(F, M, st.u, state, bins=c.bins, pad=c.pad, roi=self._roi(lv), grad_u=grad)
         st.step += 1
-        g = grad
-        if c.sigma_grad > 0:
-            g = ops.gaussian_smooth(grad, c.sigma_grad, out=self._buffer(st.u))
-        ops.adam_step(st.u, g, st.m, st.v, lr=c.lr, beta1=c.betas[0], beta2=c.betas[1], eps=c.adam_eps,
-                      step=st.step)
+        if c.sigma_grad > 0:  # smoothed gradient and Adam in one pass (bitwise smooth, then step)
+            ops.smooth_adam_step(st.u, grad, st.m, st.v, c.sigma_grad, lr=c.lr, beta1=c.betas[0], beta2=c.betas[1],
+                                 eps=c.adam_eps, step=st.step)
+        else:
+            ops.adam_step(st.u, grad, st.m, st.v, lr=c.lr, beta1=c.betas[0], beta2=c.betas[1], eps=c.adam_eps,
+                          step=st.step)
         if c.sigma_warp > 0:
             key = tuple(st.u.shape)
             su = ops.gaussian_smooth(st.u, c.sigma_warp, out=self._buffer(st.u))

@@ -1,7 +1,8 @@
 """GPU parity of the Gaussian field smoothing (ffdp_gaussian_smooth) against
 the oracle's direct (2R+1)^3 sum: ragged shapes spanning several 64 x 16
 tiles and z chunks, arrays thinner than the kernel radius, every supported
-radius, and sampled crops of a full 512^3 three-channel field."""
+radius, and sampled crops of a full 512^3 three-channel field; and of the
+fused smoothing + Adam step (ffdp_smooth_adam_step)."""
 import numpy as np
 import pytest
 import torch
@@ -60,6 +61,43 @@ def test_rejects_overlap_and_bad_sigma():
         ops.gaussian_smooth(x, 0.0)
     with pytest.raises(FfdpError):
         ops.gaussian_smooth(x, 2.5)
+
+
+@pytest.mark.parametrize("shape,sigma,step", [
+    ((3, 37, 45, 131), 1.0, 1),
+    ((3, 33, 17, 64), 0.5, 7),
+    ((1, 70, 20, 5), 2.0, 2),
+    ((2, 2, 1, 3), 1.0, 3),
+])
+def test_smooth_adam_step_is_smooth_then_adam(shape, sigma, step):
+    """The fused step equals ffdp_gaussian_smooth followed by ffdp_adam_step
+    bitwise, and the oracle's smoothing followed by its Adam step within the
+    smoothing tolerance carried through Adam's normalisation."""
+    print(f"[smooth+adam shape={shape} sigma={sigma} step={step}]", flush=True)
+    g = _field(shape, 11).to(DEV)
+    x0 = _field(shape, 12).to(DEV)
+    m0 = 0.1 * _field(shape, 13).to(DEV)
+    v0 = (1e-4 + 0.01 * _field(shape, 14).abs()).to(DEV)  # away from 0: the step stays well conditioned
+    x1, m1, v1 = x0.clone(), m0.clone(), v0.clone()
+    ops.smooth_adam_step(x1, g, m1, v1, sigma, lr=0.05, step=step)
+    x2, m2, v2 = x0.clone(), m0.clone(), v0.clone()
+    ops.adam_step(x2, ops.gaussian_smooth(g, sigma), m2, v2, lr=0.05, step=step)
+    assert torch.equal(x1, x2) and torch.equal(m1, m2) and torch.equal(v1, v2)
+    sg = oracle.gaussian_smooth(g.cpu().numpy(), sigma)
+    xr, mr, vr = (t.cpu().numpy().astype(np.float64) for t in (x0, m0, v0))
+    oracle.adam(xr, sg.astype(np.float64), mr, vr, lr=0.05, step=step)
+    assert np.abs(m1.cpu().numpy() - mr).max() <= _tol(sg)
+    assert np.abs(x1.cpu().numpy() - xr).max() <= 1e-4 * 0.05 * max(1.0, float(np.abs(xr).max()))
+
+
+def test_smooth_adam_rejects_overlap():
+    print("[smooth+adam validation]", flush=True)
+    x, g, m, v = (torch.zeros((3, 8, 8, 8), device=DEV) for _ in range(4))
+    for args in ((x, x, m, v), (x, g, x, v), (x, g, m, m)):
+        with pytest.raises(FfdpError):
+            ops.smooth_adam_step(*args, 1.0, lr=0.1)
+    with pytest.raises(FfdpError):
+        ops.smooth_adam_step(x, g, m, v, 1.0, lr=0.1, step=0)
 
 
 @pytest.mark.parametrize("sigma", [1.0, 0.5])
