@@ -65,8 +65,9 @@ def training_pair(spec: synth.PairSpec, seed: int, device, converged: bool = Fal
 
 def train(model: UNet3D, spec: synth.PairSpec, pairs: int, batch: int = 4, lr: float = 1e-3, seed0: int = 2025,
           converged_every: int = 16, reg_cfg: Optional[RegConfig] = None, log_every: int = 25, log=print,
-          make=None):
-    """make(seed) -> (F, M, T) replaces the default pair recipe when given."""
+          make=None, lr_final: Optional[float] = None):
+    """make(seed) -> (F, M, T) replaces the default pair recipe when given;
+    lr_final: the learning rate decays linearly from lr to lr_final."""
     dev = model.device
     steps = pairs // batch
     hist = []
@@ -81,7 +82,8 @@ def train(model: UNet3D, spec: synth.PairSpec, pairs: int, batch: int = 4, lr: f
             else:
                 F, M, T = training_pair(spec, seed0 + idx, dev, conv, reg_cfg)
             Fs.append(F); Ms.append(M); Ts.append(T)
-        loss = model.train_step(torch.stack(Fs), torch.stack(Ms), torch.stack(Ts), lr=lr)
+        lr_s = lr if lr_final is None else lr + (lr_final - lr) * s / max(1, steps - 1)
+        loss = model.train_step(torch.stack(Fs), torch.stack(Ms), torch.stack(Ts), lr=lr_s)
         if s % log_every == 0 or s == steps - 1:
             l = float(loss.item())
             hist.append((s, l))
@@ -248,6 +250,11 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None, help="write the trained network's weights here")
     ap.add_argument("--load", default=None, help="skip training and load weights from here")
+    ap.add_argument("--resume", action="store_true", help="with --load: keep training the loaded weights")
+    ap.add_argument("--train-pairs", type=int, default=None,
+                    help="pairs to train on (default --pairs); with --resume drawn from --seed0 on")
+    ap.add_argument("--seed0", type=int, default=synth.BASE_SEED, help="seed of the first training pair")
+    ap.add_argument("--lr-final", type=float, default=None, help="linear decay of the learning rate to this value")
     ap.add_argument("--c5", action="store_true", help="the 1040^3 share with the network at 4x downsampling")
     args = ap.parse_args()
     if args.c5:
@@ -260,12 +267,14 @@ def main():
     plain_cfg = RegConfig(loss="lncc", window=7, levels=(0.25, 0.5, 1.0), iters=(args.plain_iters,), lr=0.1, **sm)
     conv_cfg = RegConfig(loss="lncc", window=7, levels=(0.25, 0.5, 1.0), iters=(50,), lr=0.1, **sm)
     model = UNet3D(dev, seed=0)
+    tr = {"steps": 0, "pairs": 0, "seconds": 0.0, "history": []}
     if args.load:
         model.load_state_dict(torch.load(args.load, map_location="cpu", weights_only=True))
-        tr = {"steps": 0, "pairs": 0, "seconds": 0.0, "history": []}
-    else:
-        tr = train(model, spec, args.pairs, args.batch, args.lr, converged_every=args.converged_every,
-                   reg_cfg=conv_cfg, log=lambda s: print(s, flush=True))
+    if not args.load or args.resume:
+        n_train = args.pairs if args.train_pairs is None else args.train_pairs
+        tr = train(model, spec, n_train, args.batch, args.lr, seed0=args.seed0,
+                   converged_every=args.converged_every, reg_cfg=conv_cfg, log=lambda s: print(s, flush=True),
+                   lr_final=args.lr_final)
         if args.save:
             torch.save(model.state_dict(), args.save)
     print(f"trained {tr['pairs']} pairs in {tr['seconds']:.1f} s", flush=True)
