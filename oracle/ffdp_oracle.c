@@ -20,6 +20,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 typedef int64_t i64;
 
@@ -817,3 +818,13 @@ int orc_conv3d_bwd_weight(const double* xa, const double* xb, const double* P, i
     }
     return 0;
 }
+
+/* Host threads of the OpenMP loops (timing of the oracle at a given width). */
+int orc_set_threads(int n)
+{
+    if (n < 1) return -1;
+    omp_set_num_threads(n);
+    return 0;
+}
+
+int orc_max_threads(void) { return omp_get_max_threads(); }

@@ -38,6 +38,8 @@ def load():
                                        vp, _i64, vp]
     lib.orc_mi.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
     lib.orc_parzen.argtypes = [C.c_double, C.c_int, C.c_int, vp, vp]
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_max_threads.argtypes = []
     lib.orc_adam.argtypes = [vp, vp, vp, vp, _i64, C.c_double, C.c_double, C.c_double, C.c_double, _i64]
     lib.orc_resample.argtypes = [vp, _i64, _i64, _i64, vp, _i64, _i64, _i64, C.c_int, C.c_double]
     lib.orc_gaussian_smooth.argtypes = [vp, _i64, _i64, _i64, C.c_int, C.c_double, vp]
@@ -271,3 +273,13 @@ def conv3d_bwd_weight(xa, xb, P, N, Di, Hi, Wi, Ca, Cb, Cout, stride=1, ups=Fals
     lib.orc_conv3d_bwd_weight(_ptr(xa), _ptr(xb), _ptr(P), N, Di, Hi, Wi, Ca, Cb, Cout, stride, int(ups),
                               _ptr(dw), _ptr(db))
     return dw, db
+
+
+def set_threads(n: int) -> None:
+    """Width of the oracle's OpenMP loops (for timing)."""
+    if load().orc_set_threads(int(n)) != 0:
+        raise ValueError("threads must be >= 1")
+
+
+def max_threads() -> int:
+    return int(load().orc_max_threads())
