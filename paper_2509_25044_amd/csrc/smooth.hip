@@ -142,15 +142,17 @@ __global__ void __launch_bounds__(SM_NT) smooth_kernel(const float* __restrict__
 #pragma unroll
                     for (int k = 0; k < K; ++k) o = fmaf(g[k], ring[e][(j + 1 + k) % K], o);
                     const size_t idx = (size_t)zo * HW + (size_t)gy * W + gx;
+                    // every output byte is touched once: non-temporal accesses
                     if (ADAM) {  // out is x; m, v at the same offsets
                         const size_t ci = (size_t)c * N + idx;
-                        float xx = dst[idx], mm = am[ci], vv = av[ci];
+                        float xx = __builtin_nontemporal_load(dst + idx);
+                        float mm = __builtin_nontemporal_load(am + ci), vv = __builtin_nontemporal_load(av + ci);
                         adam1(xx, o, mm, vv, ak);
-                        dst[idx] = xx;
-                        am[ci] = mm;
-                        av[ci] = vv;
+                        __builtin_nontemporal_store(xx, dst + idx);
+                        __builtin_nontemporal_store(mm, am + ci);
+                        __builtin_nontemporal_store(vv, av + ci);
                     } else {
-                        dst[idx] = o;
+                        __builtin_nontemporal_store(o, dst + idx);
                     }
                 }
             }
