@@ -119,11 +119,12 @@ __device__ __forceinline__ unsigned imul(int a, int b)
     return __umul24((unsigned)a, (unsigned)b);
 }
 
+// grad_u is written once and not read again here: non-temporal stores
 template <bool BIG>
 __device__ __forceinline__ void st(float* __restrict__ base, unsigned idx, float v)
 {
-    if (BIG) base[idx] = v;
-    else *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + idx * 4u) = v;
+    if (BIG) __builtin_nontemporal_store(v, base + idx);
+    else __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + idx * 4u));
 }
 
 // Loads of one stage-A point for one slice, issued a slice ahead of their use.

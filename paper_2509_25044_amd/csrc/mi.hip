@@ -114,7 +114,7 @@ __device__ __forceinline__ void mi_issue(const MiArgs& a, int x, int y, int z, f
                                          MiPend& g)
 {
     const int D = a.D, H = a.H, W = a.W;
-    g.f = a.F[idx];
+    g.f = __builtin_nontemporal_load(a.F + idx);  // read once per kernel
     const float fx = fminf(fmaxf(floorf(dx), -268435456.0f), 268435456.0f);
     const float fy = fminf(fmaxf(floorf(dy), -268435456.0f), 268435456.0f);
     const float fz = fminf(fmaxf(floorf(dz), -268435456.0f), 268435456.0f);
@@ -191,7 +191,11 @@ struct ColumnSampler {
     __device__ void load_u(int zz, float* o)
     {
         const int id = zz * HW + y * a.W + x;
-        if (a.u) { o[0] = a.u[id]; o[1] = a.u[N + id]; o[2] = a.u[2 * N + id]; }
+        if (a.u) {  // each element read once per kernel: non-temporal
+            o[0] = __builtin_nontemporal_load(a.u + id);
+            o[1] = __builtin_nontemporal_load(a.u + N + id);
+            o[2] = __builtin_nontemporal_load(a.u + 2 * N + id);
+        }
         else { o[0] = 0.f; o[1] = 0.f; o[2] = 0.f; }
     }
     __device__ void issue(int zz, const float* uu)
@@ -532,9 +536,9 @@ __global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* _
             if (AFF) affine_adjoint(a.aff, x, y, z, g0, g1, g2, acc, g0, g1, g2);
         }
         if (!AFF || gu) {
-            gu[idx] = g0;
-            gu[N + idx] = g1;
-            gu[2 * N + idx] = g2;
+            __builtin_nontemporal_store(g0, gu + idx);  // written once, never read here
+            __builtin_nontemporal_store(g1, gu + N + idx);
+            __builtin_nontemporal_store(g2, gu + 2 * N + idx);
         }
     }
     if (AFF) {
