@@ -20,8 +20,8 @@
 // commute, so the histogram is bitwise reproducible.  Neighbouring voxels
 // have similar intensities and so hit the same bins; to keep the lanes of a
 // wave from serialising on one address, a block keeps several LDS copies of
-// its histogram and neighbouring lanes add into different copies.  A one-block kernel
-// then forms p, the marginals, MI and the log table T.
+// its histogram and neighbouring lanes add into different copies.  A
+// one-block kernel then forms p, the marginals, MI and the log table T.
 // Backward: T in LDS, 4 x 4 weighted lookups per voxel, then the sampler's
 // derivative; grad_u written over the whole array (zero outside the ROI).
 //
