@@ -19,12 +19,13 @@ excluded and reported separately.
 
 --c5: the same study on one GPU's share of the gigavoxel problem (1040^3,
 LNCC w = 5 on the interior [8, 1032)^3, 100 full-resolution iterations for the
-plain method).  The network works at 4x downsampling: the pair is resampled to
-260^3, padded to 264^3 (edge replication; the U-Net needs sides divisible by
-8), and the prediction is cropped and resampled back to 1040^3 with each
-channel scaled by its axis's grid ratio.  Training pairs are the same
-continuous pairs evaluated directly on the 260^3 grid (synth.make_pair with
-grid=...), so no 1040^3 volume is generated for training.
+plain method).  The network works at 4x downsampling: the pair is smoothed
+(sigma 2 voxels, against aliasing of the fine texture), resampled to 260^3,
+padded to 264^3 (edge replication; the U-Net needs sides divisible by 8), and
+the prediction is cropped and resampled back to 1040^3 with each channel
+scaled by its axis's grid ratio.  Training pairs are the same continuous pairs
+without the texture evaluated directly on the 260^3 grid (synth.make_pair
+with grid=...), so no 1040^3 volume is generated for training.
 """
 from __future__ import annotations
 
@@ -183,16 +184,23 @@ def pad_edge(x: torch.Tensor, shape) -> torch.Tensor:
     return y.reshape(tuple(x.shape[:-3]) + tuple(shape)).contiguous()
 
 
+# Gaussian applied before the 4x downsampling (voxels of the full grid): the
+# 3-8 voxel texture would otherwise alias into the 260^3 images; the
+# training pairs are generated without it, as the filtered images show it.
+C5_ANTIALIAS = 2.0
+
+
 def c5_training_pair(seed: int, device):
-    p = synth.make_pair(C5.pair, seed=seed, device=device, noise_on_device=True, grid=C5_GRID)
+    spec = dataclasses.replace(C5.pair, texture_std=0.0)
+    p = synth.make_pair(spec, seed=seed, device=device, noise_on_device=True, grid=C5_GRID)
     T = inverse_target(p["d"])
     return pad_edge(p["F"], C5_NET), pad_edge(p["M"], C5_NET), pad_edge(T, C5_NET)
 
 
 def c5_predict(model: UNet3D, F: torch.Tensor, M: torch.Tensor) -> torch.Tensor:
-    """Full-resolution u0 from the network run at 4x downsampling."""
-    Fl = pad_edge(ops.resample(F, C5_GRID), C5_NET)
-    Ml = pad_edge(ops.resample(M, C5_GRID), C5_NET)
+    """Full-resolution u0 from the network run at 4x downsampling (filtered first)."""
+    Fl = pad_edge(ops.resample(ops.gaussian_smooth(F, C5_ANTIALIAS), C5_GRID), C5_NET)
+    Ml = pad_edge(ops.resample(ops.gaussian_smooth(M, C5_ANTIALIAS), C5_GRID), C5_NET)
     g = C5_GRID
     u = model.predict(Fl, Ml)[:, :g[0], :g[1], :g[2]].contiguous()
     return resample_disp(u, F.shape)
