@@ -153,3 +153,28 @@ def test_warp_and_resample_validation(L):
     assert L.ffdp_resample(FAKE, 4, 4, 4, FAKE, 8, 8, 8, 1, 2.0, None) == 3  # overlap
     assert L.ffdp_resample(FAKE, 0, 4, 4, C.c_void_p(0x900000), 8, 8, 8, 1, 2.0, None) == 2
     assert L.ffdp_resample(FAKE, 4, 4, 4, C.c_void_p(0x900000), 8, 8, 8, 0, 2.0, None) == 3
+
+
+def test_smoothing_validation(L):
+    a, b = C.c_void_p(0x100000), C.c_void_p(0x900000)
+    assert L.ffdp_gaussian_smooth(a, a, 8, 8, 8, 3, 1.0, None) == 3            # in and out overlap
+    assert L.ffdp_gaussian_smooth(a, b, 8, 8, 8, 3, 0.0, None) == 3            # sigma out of (0, 2]
+    assert L.ffdp_gaussian_smooth(a, b, 8, 8, 8, 3, 2.5, None) == 3
+    assert L.ffdp_gaussian_smooth(a, b, 8, 8, 8, 0, 1.0, None) == 3            # channels
+    assert L.ffdp_gaussian_smooth(a, b, 0, 8, 8, 3, 1.0, None) == 2            # shape
+    assert L.ffdp_gaussian_smooth(None, b, 8, 8, 8, 3, 1.0, None) == 1
+    assert L.ffdp_gaussian_smooth(FAKE_MIS, b, 8, 8, 8, 3, 1.0, None) == 4
+
+
+def test_smooth_adam_validation(L):
+    # four disjoint 3 x 8^3 float arrays (6 KiB apart)
+    x, g, m, v = (C.c_void_p(0x100000 + k * 0x2000) for k in range(4))
+    args = (8, 8, 8, 3, 1.0, 0.1, 0.9, 0.999, 1e-8)
+    assert L.ffdp_smooth_adam_step(x, g, m, v, *args, 0, None) == 3             # step 0
+    assert L.ffdp_smooth_adam_step(x, x, m, v, *args, 1, None) == 3             # g overlaps x
+    assert L.ffdp_smooth_adam_step(x, g, m, m, *args, 1, None) == 3             # m overlaps v
+    assert L.ffdp_smooth_adam_step(x, g, m, C.c_void_p(0x100000 + 0x1000), *args, 1, None) == 3  # v inside x
+    assert L.ffdp_smooth_adam_step(None, g, m, v, *args, 1, None) == 1
+    assert L.ffdp_smooth_adam_step(x, g, m, v, 8, 8, 8, 3, 3.0, 0.1, 0.9, 0.999, 1e-8, 1, None) == 3  # sigma
+    assert L.ffdp_smooth_adam_step(x, g, m, v, 8, 8, 8, 3, 1.0, 0.1, 1.0, 0.999, 1e-8, 1, None) == 3  # beta1
+    assert L.ffdp_smooth_adam_step(x, g, m, v, 8, 0, 8, 3, 1.0, 0.1, 0.9, 0.999, 1e-8, 1, None) == 2  # shape
