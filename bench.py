@@ -196,8 +196,8 @@ def main():
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build measures one GPU's share of "
-              "the volume; multi-GPU sharding is a design note, not an implemented path.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): it measures one GPU's share of the "
+              "volume; sharding across GPUs is a design, not an implemented path.", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X (HIP device); none is visible", file=sys.stderr)
