@@ -22,8 +22,9 @@
 //
 // The ADAM variant applies the optimiser step to (x, m, v) with the smoothed
 // value as the gradient where the plain kernel would store it: the smoothed
-// gradient of the registration loop never reaches HBM (24 bytes per element
-// saved against smoothing then stepping), with bitwise the same result.
+// gradient of the registration loop never reaches HBM (8 bytes per element,
+// 24 per voxel of a displacement field, saved against smoothing then
+// stepping), with bitwise the same result.
 #include "adam.hpp"
 #include "device.hpp"
 #include "internal.hpp"
