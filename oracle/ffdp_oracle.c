@@ -367,13 +367,12 @@ static double dbeta3(double t)
     return 0.0;
 }
 
-/* Hard bin of a value already clamped to [0, 1]: min(floor(v B), B-1), with
- * v B formed in fp32, the precision of the device kernels, so that both
- * sides take the same integer decision for the same fp32 value. */
+/* Hard bin of a value already clamped to [0, 1]: m* = min(floor(v B), B-1)
+ * (App. "Implicit MI implementation", approximate histogram estimator), with
+ * v B and its floor taken in double on the value as given. */
 static i64 hard_bin(double vc, int B)
 {
-    const float t = (float)vc * (float)B;
-    i64 m = (i64)floorf(t);
+    i64 m = (i64)floor(vc * (double)B);
     return m > B - 1 ? B - 1 : m;
 }
 
@@ -422,7 +421,7 @@ static int mi_core(const float* F, const double* Mw, i64 D, i64 H, i64 W, const 
                     double vf = (double)F[k], vm = Mw[k];
                     vf = vf < 0.0 ? 0.0 : (vf > 1.0 ? 1.0 : vf);
                     vm = vm < 0.0 ? 0.0 : (vm > 1.0 ? 1.0 : vm);
-                    cnt[hard_bin(vf, B) * B + hard_bin((double)(float)vm, B)] += 1.0;
+                    cnt[hard_bin(vf, B) * B + hard_bin(vm, B)] += 1.0;
                 }
         /* K[m][j] = kappa_m(b_j), then p = K (cnt / N) K^T */
         double* K = (double*)malloc(sizeof(double) * B * B);

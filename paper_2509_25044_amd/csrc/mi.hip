@@ -27,7 +27,7 @@
 //
 // Approximate forward (App. "Implicit MI implementation", the approximate
 // histogram estimator): each voxel adds one count to its hard bin pair
-// (min(floor(v B), B-1) in fp32) -- runs of equal bin pairs along a column
+// (min(floor(v B), B-1) of the exact product) -- runs of equal bin pairs along a column
 // are merged in a register before the LDS atomic -- and the one-block
 // finalize convolves the count histogram with the kernel at bin-centre
 // offsets (taps 1/6, 2/3, 1/6, folded at the edges) before forming p.  Its
@@ -37,6 +37,21 @@
 
 namespace ffdp {
 
+// Hard bin min(floor(v B), B-1) of a value v in [0, 1], taken on the exact
+// product v B rather than its fp32 rounding: p = fl(v B) and its residual
+// fma(v, B, -p) is exact, so floor(v B) = floor(p) except where p is an
+// integer reached by rounding up (residual < 0).  The decision is then the
+// same as floor in any wider precision for the same fp32 v.
+__device__ __forceinline__ int exact_bin(float vc, int B)
+{
+    const float fB = (float)B;
+    const float p = vc * fB;
+    const float e = fmaf(vc, fB, -p);
+    float f = floorf(p);
+    if (f == p && e < 0.0f) f -= 1.0f;
+    return min((int)f, B - 1);
+}
+
 // Four cubic B-spline weights of v on bins j0..j0+3 (before folding) and, with
 // DERIV, their derivatives with respect to v.  Hard mode: one unit weight.
 template <bool HARD, bool DERIV>
@@ -44,7 +59,7 @@ __device__ __forceinline__ void parzen4(float v, int B, int& j0, float w[4], flo
 {
     const float vc = fminf(fmaxf(v, 0.0f), 1.0f);  // NaN -> 0; flagged separately
     if (HARD) {
-        j0 = min((int)(vc * (float)B), B - 1);
+        j0 = exact_bin(vc, B);
         w[0] = 1.0f; w[1] = w[2] = w[3] = 0.0f;
         if (DERIV) dw[0] = dw[1] = dw[2] = dw[3] = 0.0f;
         return;
@@ -310,7 +325,6 @@ __global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long
     const int H = a.H, W = a.W, HW = H * W;
     const size_t N = (size_t)a.D * HW;
     const bool active = x < a.roi[5] && y < a.roi[3];
-    const float fB = (float)B;
     int cur = -1;
     unsigned run = 0u;
     bool bad = false;
@@ -321,8 +335,8 @@ __global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long
             const float fv = sp.f;
             const float mv = mi_interp<PAD, false>(sp).v;
             bad |= (fv != fv) || (mv != mv);
-            const int bf = min((int)floorf(fminf(fmaxf(fv, 0.0f), 1.0f) * fB), B - 1);
-            const int bm = min((int)floorf(fminf(fmaxf(mv, 0.0f), 1.0f) * fB), B - 1);
+            const int bf = exact_bin(fminf(fmaxf(fv, 0.0f), 1.0f), B);
+            const int bm = exact_bin(fminf(fmaxf(mv, 0.0f), 1.0f), B);
             const int q = bf * B + bm;
             if (q != cur) {
                 if (run) atomicAdd(&mine[cur], run);

@@ -164,14 +164,26 @@ def _mi_case(F, M, u, bins=32, hard=False, pad="border", roi=None, what=""):
     mode = 2 if hard == "approx" else int(bool(hard))
     lr, pr, gr = oracle.mi(F.numpy(), M.numpy(), None if u is None else u.numpy(), roi=_roi6(roi), bins=bins,
                            hard=mode, pad=1 if pad == "zeros" else 0)
-    assert_loss(float(loss.item()), lr, f"{what} loss")
     st = _np(state)
     B = bins
-    # approximate mode: a voxel whose fp32 warped value sits within rounding
-    # of a bin edge may count in the neighbouring bin on one side; each such
-    # voxel moves at most 2/N_roi of mass between p entries
     nroi = np.prod([b - a for a, b in roi]) if roi is not None else F.numel()
-    atol = 4.0 / nroi if (mode == 2 and u is not None) else 1e-9
+    # Hard bins (box kernel, approximate estimator): both sides take the bin
+    # of their own value exactly (floor of the exact product v B), so F's
+    # bins agree.  The warped value is fp32 on the device and float64 in the
+    # oracle; a voxel whose oracle value lies within the fp32 sampler's
+    # rounding of a bin edge may land in the neighbouring bin.  Such voxels
+    # are counted from the oracle's own values; each moves at most 2/N_roi of
+    # mass between p entries and changes MI by at most ~100/N_roi (six p log p
+    # terms with p >= 1/N_roi).  With none of them, parity is exact.
+    namb = _edge_voxels(M, u, pad, roi, B) if (mode in (1, 2) and u is not None) else 0
+    if namb:
+        print(f"  {what}: {namb} ROI voxels within fp32 rounding of a bin edge", flush=True)
+    lt = abs(float(loss.item()) - lr)
+    if namb == 0:
+        assert_loss(float(loss.item()), lr, f"{what} loss")
+    else:
+        assert lt <= 1e-5 * abs(lr) + 100.0 * namb / nroi, f"{what} loss {float(loss.item())} vs {lr}"
+    atol = 1e-9 + 2.0 * namb / nroi
     np.testing.assert_allclose(st[B * B:2 * B * B].reshape(B, B), pr, rtol=1e-5, atol=atol)
     if mode == 1:
         assert float(g.abs().max()) == 0.0
@@ -179,6 +191,20 @@ def _mi_case(F, M, u, bins=32, hard=False, pad="border", roi=None, what=""):
         _mi_approx_grad(F, M, u, pad, roi, B, st, pr, _np(g), gr, nroi, what)
     else:
         assert_grad(_np(g), gr, f"{what} grad")
+
+
+def _edge_voxels(M, u, pad, roi, B):
+    """ROI voxels whose float64 warped value (clamped to [0, 1]) lies within
+    16 fp32 ulps of 1 of an interior bin edge m / B: the fp32 trilinear
+    value (seven rounded interpolations of values in [0, 1]) can differ from
+    the float64 one by less than that."""
+    mw = np.clip(oracle.warp(M.numpy(), u.numpy(), pad=1 if pad == "zeros" else 0), 0.0, 1.0)
+    if roi is not None:
+        mw = mw[tuple(slice(a, b) for a, b in roi)]
+    t = mw * B
+    k = np.round(t)
+    near = (np.abs(t - k) <= 16 * 2.0 ** -24 * B) & (k > 0) & (k < B)
+    return int(near.sum())
 
 
 def _mi_approx_grad(F, M, u, pad, roi, B, st, pr, g, gr, nroi, what):
@@ -193,7 +219,8 @@ def _mi_approx_grad(F, M, u, pad, roi, B, st, pr, g, gr, nroi, what):
     few, those voxels few, and every gradient finite."""
     dp = np.abs(st[B * B:2 * B * B].reshape(B, B).astype(np.float64) - pr)
     moved = 0.5 * dp.sum() * nroi  # voxels whose count moved, at least
-    assert moved <= max(3.0, 1e-4 * nroi), f"{what}: {moved:.1f} voxels change bins"
+    namb = _edge_voxels(M, u, pad, roi, B)
+    assert moved <= namb + 1e-3, f"{what}: {moved:.1f} voxels change bins, {namb} lie near an edge"
     pm = pr.sum(axis=0)
     with np.errstate(divide="ignore", invalid="ignore"):
         t_orc = np.where(pr > 0, np.log(pr) - np.log(pm)[None, :], 0.0)

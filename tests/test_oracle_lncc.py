@@ -165,3 +165,85 @@ def test_gradient_vanishes_far_from_roi(orc):
     roi = np.array([0, 4, 0, 6, 0, 6])
     _, g = orc.lncc(F, M, None, roi=roi, window=3, eps=1e-5)
     assert np.all(g[:, 5:] == 0.0) and np.any(g[:, 4] != 0.0)
+
+
+# ---------------------------------------------------------------- ANTs mode --
+# App. "ANTs gradient approximation": the backward skips the window sums of
+# the gamma family, i.e. dL/dMw_k = F_k gamma_k - Mw_k gamma_AC,k + gamma_MF,k
+# with voxel k's own factors.  Written out, that is a_k (F_k - muF_k) -
+# c_k (Mw_k - muM_k) with a_k = 2 g A_k / D_k, c_k = 2 g A_k^2 B_k / D_k^2,
+# which is exactly g w^3 dn_k/dMw_k: w^3 times the derivative of voxel k's
+# own LNCC term with respect to its own warped value (the other voxels'
+# terms, which the exact gradient sums over the window, are left out).
+
+def _ants_case(seed, shape=(8, 8, 8), scale=2.0):
+    F = synth.random_volume(shape, seed).numpy()
+    M = synth.random_volume(shape, seed + 1).numpy()
+    u = synth.random_disp(shape, seed + 2, scale).numpy()
+    return F, M, u
+
+
+@pytest.mark.parametrize("w,roi", [(3, None), (5, ((1, 7), (2, 8), (0, 8))), (7, None)])
+def test_ants_gradient_is_self_term_derivative(orc, w, roi):
+    """Central differences of the single-voxel-ROI loss 1 - n_k in Mw_k
+    (the forward map, pinned above against library box means) give
+    dn_k/dMw_k; the ANTs gradient must be -w^3/N_roi times it, times the
+    sampler derivative dMw/dp."""
+    F, M, u = _ants_case(300 + w)
+    D, H, W = F.shape
+    eps = 1e-3
+    rt = _roi_tuple(roi)
+    _, g = orc.lncc(F, M, u, roi=rt, window=w, eps=eps, ants=True)
+    Mw, dMw = orc.warp(M, u, with_grad=True)
+    nroi = D * H * W if roi is None else np.prod([b - a for a, b in roi])
+    rng = np.random.default_rng(310 + w)
+    inside = 0
+    for _ in range(24):
+        z, y, x = (int(rng.integers(0, n)) for n in (D, H, W))
+        in_roi = roi is None or all(a <= c < b for c, (a, b) in zip((z, y, x), roi))
+        if not in_roi:
+            assert np.all(g[:, z, y, x] == 0.0)
+            continue
+        inside += 1
+        one = np.array([z, z + 1, y, y + 1, x, x + 1])
+        h = 1e-4
+        mp, mm = Mw.copy(), Mw.copy()
+        mp[z, y, x] += h
+        mm[z, y, x] -= h
+        dl = (orc.lncc_loss_mw(F, mp, roi=one, window=w, eps=eps) -
+              orc.lncc_loss_mw(F, mm, roi=one, window=w, eps=eps)) / (2 * h)  # = -dn_k/dMw_k
+        s = (w ** 3) * dl / nroi  # = -(1/N_roi) w^3 dn_k/dMw_k
+        ref = s * dMw[:, z, y, x]
+        np.testing.assert_allclose(g[:, z, y, x], ref, rtol=1e-6, atol=1e-9 * np.abs(g).max())
+    assert inside >= 8
+
+
+def test_ants_gradient_matches_library_box_means(orc):
+    """The same mode through avg_pool3d statistics and grid_sample's
+    derivative: a_k (F_k - muF_k) - c_k (Mw_k - muM_k) on the ROI, zero off it."""
+    F, M, u = _ants_case(320, shape=(8, 9, 10))
+    w, eps = 5, 1e-4
+    roi = ((1, 7), (0, 8), (2, 9))
+    _, g = orc.lncc(F, M, u, roi=_roi_tuple(roi), window=w, eps=eps, ants=True)
+    r = (w - 1) // 2
+
+    def box(t):
+        return tf.avg_pool3d(t[None, None], w, stride=1, padding=r, count_include_pad=True)[0, 0]
+
+    Ft = torch.from_numpy(F.astype(np.float64))
+    ut = torch.from_numpy(u.astype(np.float64)).requires_grad_(True)
+    Mw = _grid_sample(torch.from_numpy(M.astype(np.float64)), ut)
+    dMw = torch.stack(torch.autograd.grad(Mw.sum(), ut)[0].unbind(0))  # dMw/dp per channel (voxel-local)
+    Mw = Mw.detach()
+    muF, muM = box(Ft), box(Mw)
+    A = box(Ft * Mw) - muF * muM
+    B = box(Ft * Ft) - muF * muF
+    C = box(Mw * Mw) - muM * muM
+    Dn = B * C + eps
+    nroi = np.prod([b - a for a, b in roi])
+    gi = -1.0 / nroi
+    s = 2 * gi * A / Dn * (Ft - muF) - 2 * gi * A * A * B / (Dn * Dn) * (Mw - muM)
+    mask = torch.zeros_like(s)
+    mask[tuple(slice(a, b) for a, b in roi)] = 1.0
+    ref = (s * mask)[None] * dMw
+    np.testing.assert_allclose(g, ref.numpy(), rtol=0, atol=1e-10 * np.abs(g).max())
