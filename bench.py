@@ -1,11 +1,14 @@
 """Benchmark of the fused warp + dissimilarity hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5] [--no-cpu-baseline]
 
-Workload: the 512^3 pair (250 um-like scale; blobs sigma 3-8, max displacement
-8 voxels) with LNCC window 5 and MI with 32 B-spline bins.  The displacement
-starts at u = -d (the known smooth inverse field, non-integer gathers
-everywhere) and evolves under Adam.
+Workload (default): one GPU's share of the 100 um gigavoxel problem, a
+1040^3 pair (1024^3 plus an 8-voxel halo on each face; blobs sigma 10-40
+with band-passed texture, max displacement 8 voxels) with the loss region
+[8, 1032)^3, LNCC window 5 and MI with 32 B-spline bins.  `--workload c3`
+runs the 512^3 pair (250 um-like scale) instead.  The displacement starts at
+u = -d (the known smooth inverse field, non-integer gathers everywhere) and
+evolves under Adam.
 
 One step is one pass of the whole hot path: an LNCC registration iteration
 (fused warp + LNCC forward and adjoint with the loss, then Adam on its
@@ -18,7 +21,9 @@ voxels divided by the mean duration of the fused LNCC call, measured with HIP
 events on the stream it runs on, over the timed steps.  `roofline` relates
 that call's algorithmic HBM bytes (read F, M, u = 20 B/voxel, write grad_u =
 12 B/voxel) to the 8 TB/s HBM peak.  `cpu_baseline` times the FP64 oracle on
-a z-slab of the same pair.  Prints one JSON line.
+a z-slab of the same pair (1040 x 1040 x 72 by default: 64 slices plus the
+2 x 2r halo of the adjoint).  The extras time the other kernels and the fused
+LNCC call on the 512^3 pair.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -36,11 +41,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_2509_25044_amd import ops, synth  # noqa: E402
-from paper_2509_25044_amd.configs import ALL, C3  # noqa: E402
+from paper_2509_25044_amd.configs import ALL, C3, C5  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 LNCC_BYTES_PER_VOXEL = 32  # read F, M, u (4 + 4 + 12), write grad_u (12)
-COUNTERS = os.path.join(ROOT, "profiles", "lncc_bwd_c3_counters.json")
+COUNTERS = os.path.join(ROOT, "profiles", "lncc_bwd_counters.json")
 KERNEL_SOURCES = ["paper_2509_25044_amd/csrc/lncc.hip", "paper_2509_25044_amd/csrc/device.hpp",
                   "paper_2509_25044_amd/csrc/internal.hpp"]
 
@@ -59,12 +64,23 @@ def measured_traffic(workload: str):
     counters were taken on another workload."""
     try:
         with open(COUNTERS) as f:
-            c = json.load(f)
-    except (OSError, ValueError):
+            c = json.load(f).get(workload)
+    except (OSError, ValueError, AttributeError):
         return None
-    if c.get("source_hash") != kernel_source_hash() or c.get("workload") != workload:
+    if not c or c.get("source_hash") != kernel_source_hash():
         return None
     return c.get("hbm_bytes_per_launch")
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(F, M, u, window, slab, runs: int = 3, slab1: int = 8):
@@ -92,6 +108,7 @@ def cpu_baseline(F, M, u, window, slab, runs: int = 3, slab1: int = 8):
     n1, t1 = timed(min(slab1, F.shape[0]))
     oracle.set_threads(threads)
     return {"value": nvox / t / 1e9, "unit": "Gvoxel/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"z-slab {slab}x{F.shape[1]}x{F.shape[2]} of the {F.shape[0]}x{F.shape[1]}x{F.shape[2]} pair, "
                       f"FP64 LNCC w={window} loss + gradient ({nvox} voxels, median of {runs}: {t:.1f} s)",
             "single_core": {"value": n1 / t1 / 1e9, "unit": "Gvoxel/s",
@@ -181,14 +198,45 @@ def extras(F, M, u, scratch, roi, nroi, wl, reps: int = 5):
     return res
 
 
+def other_workload(wl, reps: int = 10):
+    """The fused LNCC fwd+bwd call on another workload's pair (u = -d), timed
+    like the step's call: mean over reps of HIP events on the call's stream."""
+    dev = torch.device("cuda:0")
+    pair = synth.make_pair(wl.pair, seed=synth.BASE_SEED, device=dev)
+    F, M, u = pair["F"], pair["M"], (-pair["d"]).contiguous()
+    del pair
+    roi = wl.roi
+    nroi = ops.roi_voxels(F.shape, roi)
+    g = torch.empty_like(u)
+    loss = torch.empty(1, device=dev)
+    ws = torch.empty(ops.lncc_workspace_bytes(F.shape, roi, wl.lncc_window), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def call():
+        ops.warp_lncc_bwd(F, M, u, window=wl.lncc_window, eps=wl.lncc_eps, roi=roi, grad_u=g, loss=loss, ws=ws)
+    call()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ach = LNCC_BYTES_PER_VOXEL * nroi / (ms * 1e-3) / 1e9
+    return {"workload": wl.name, "lncc_fwd_bwd_ms": round(ms, 4), "gvoxel_per_s": round(nroi / (ms * 1e-3) / 1e9, 3),
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wl.name)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default=C3.name)
+    ap.add_argument("--workload", default=C5.name)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slab", type=int, default=0, help="oracle z-slab depth (0 = whole volume)")
+    ap.add_argument("--cpu-slab", type=int, default=-1,
+                    help="oracle z-slab depth (0 = whole volume; default 72 slices, the whole volume below 600)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the timings of the kernels outside the step (smoothing, approximate MI, "
                          "composite sampler)")
@@ -291,7 +339,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "lncc_kernel<5,BWD,border> (+1-block loss finalize)",
-                     "algorithmic_bytes_per_launch": LNCC_BYTES_PER_VOXEL * nroi},
+                     "algorithmic_bytes_per_launch": LNCC_BYTES_PER_VOXEL * nroi,
+                     "limiter": "VALU issue and latency, not HBM bandwidth (about 430 VALU instructions per voxel; "
+                                "rocprofv3 SQ counters)"},
         "breakdown_ms": {"lncc_fwd_bwd": round(t_lncc, 4), "adam": round(t_adam, 4), "mi_fwd": round(t_mif, 4),
                          "mi_bwd": round(t_mib, 4)},
         "breakdown_hbm_frac": {
@@ -305,8 +355,13 @@ def main():
         "kernel_source_hash": kernel_source_hash(),
     }
     out["extras"] = None if args.no_extras else extras(F, M, u_m, g_m, roi, nroi, wl)
+    if out["extras"] is not None and wl.name != C3.name:
+        out["extras"]["c3_512cube"] = other_workload(C3)
     if not args.no_cpu_baseline:
-        slab = F.shape[0] if args.cpu_slab <= 0 else min(args.cpu_slab, F.shape[0])
+        if args.cpu_slab < 0:
+            slab = F.shape[0] if F.shape[0] < 600 else 64 + 4 * ((wl.lncc_window - 1) // 2)
+        else:
+            slab = F.shape[0] if args.cpu_slab == 0 else min(args.cpu_slab, F.shape[0])
         out["cpu_baseline"] = cpu_baseline(F, M, u_l, wl.lncc_window, slab)
     else:
         out["cpu_baseline"] = None

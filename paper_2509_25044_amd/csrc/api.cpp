@@ -128,28 +128,28 @@ void fill_roi(const ffdp_grid* g, int roi[6])
     roi[4] = (int)g->roi_lo[2]; roi[5] = (int)g->roi_hi[2];
 }
 
-size_t lncc_ws(const ffdp_grid* g)
+// one double per thread block of the largest plan over the modes of the window
+size_t lncc_ws(const ffdp_grid* g, int window)
 {
-    LnccLaunch L = lncc_plan((int)g->D, (int)g->H, (int)g->W);
-    return (size_t)L.nblocks * sizeof(double);
+    return (size_t)lncc_max_blocks((int)g->D, (int)g->H, (int)g->W, window) * sizeof(double);
 }
 
 size_t mi_ws(const ffdp_mi_params* p) { return ((size_t)p->bins * p->bins + 1) * sizeof(unsigned long long); }
 
 int lncc_common(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_lncc_params* p,
-                void* ws, size_t ws_bytes, LnccArgs& a)
+                void* ws, size_t ws_bytes, int mode, LnccArgs& a, LnccLaunch& L)
 {
     int s = check_grid(g);
     if (s) return s;
     if ((s = check_lncc(p))) return s;
     if ((s = check_ptrs("F,M", 2, (const void*)F, (const void*)M))) return s;
     if ((s = check_opt_ptr(u, "u"))) return s;
-    const size_t need = lncc_ws(g);
+    const size_t need = lncc_ws(g, p->window);
     if (!ws || ws_bytes < need)
         return fail(FFDP_ERR_WORKSPACE, "workspace of %zu bytes required (got %zu%s)", need, ws_bytes,
                     ws ? "" : ", NULL");
     if (((uintptr_t)ws) & 7u) return fail(FFDP_ERR_ALIGN, "workspace must be 8-byte aligned");
-    LnccLaunch L = lncc_plan((int)g->D, (int)g->H, (int)g->W);
+    L = lncc_plan((int)g->D, (int)g->H, (int)g->W, p->window, mode);
     a.F = F; a.M = M; a.u = u; a.gu = nullptr; a.grad_scale = nullptr;
     a.partial = (double*)ws;
     a.D = (int)g->D; a.H = (int)g->H; a.W = (int)g->W;
@@ -157,6 +157,7 @@ int lncc_common(const float* F, const float* M, const float* u, const ffdp_grid*
     a.eps = p->eps;
     a.neg_inv_nroi = (float)(-1.0 / roi_voxels(g));
     a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk; a.nblocks = L.nblocks;
+    a.zspan = L.zspan;
     return FFDP_OK;
 }
 
@@ -238,9 +239,11 @@ const char* ffdp_last_error(void) { return g_err; }
 
 size_t ffdp_lncc_workspace_bytes(const ffdp_grid* g, const ffdp_lncc_params* p)
 {
-    (void)p;
     if (!g || check_dims(g->D, g->H, g->W)) return sizeof(double);
-    return lncc_ws(g);
+    if (p && check_lncc(p) == FFDP_OK) return lncc_ws(g, p->window);
+    size_t n = 0;  // no (valid) parameters: enough for every window
+    for (int w = 3; w <= 9; w += 2) n = n > lncc_ws(g, w) ? n : lncc_ws(g, w);
+    return n;
 }
 
 size_t ffdp_mi_workspace_bytes(const ffdp_grid* g, const ffdp_mi_params* p)
@@ -293,10 +296,11 @@ int ffdp_warp_lncc_fwd(const float* F, const float* M, const float* u, const ffd
                        const ffdp_lncc_params* p, float* loss, void* ws, size_t ws_bytes, void* stream)
 {
     LnccArgs a;
-    int s = lncc_common(F, M, u, g, p, ws, ws_bytes, a);
+    LnccLaunch L;
+    int s = lncc_common(F, M, u, g, p, ws, ws_bytes, 0, a, L);
     if (s) return s;
     if ((s = check_ptrs("loss", 1, (const void*)loss))) return s;
-    return hip_status(lncc_launch(0, p->window, p->pad_mode, a, loss, roi_voxels(g), (hipStream_t)stream),
+    return hip_status(lncc_launch(0, p->window, p->pad_mode, L, a, loss, roi_voxels(g), (hipStream_t)stream),
                       "ffdp_warp_lncc_fwd");
 }
 
@@ -305,7 +309,8 @@ int ffdp_warp_lncc_bwd(const float* F, const float* M, const float* u, const ffd
                        size_t ws_bytes, void* stream)
 {
     LnccArgs a;
-    int s = lncc_common(F, M, u, g, p, ws, ws_bytes, a);
+    LnccLaunch L;
+    int s = lncc_common(F, M, u, g, p, ws, ws_bytes, (p && p->ants_approx) ? 2 : 1, a, L);
     if (s) return s;
     if ((s = check_ptrs("grad_u", 1, (const void*)grad_u))) return s;
     if ((s = check_opt_ptr(grad_scale, "grad_scale"))) return s;
@@ -313,7 +318,7 @@ int ffdp_warp_lncc_bwd(const float* F, const float* M, const float* u, const ffd
     a.gu = grad_u;
     a.grad_scale = grad_scale;
     const int mode = p->ants_approx ? 2 : 1;
-    return hip_status(lncc_launch(mode, p->window, p->pad_mode, a, loss, roi_voxels(g), (hipStream_t)stream),
+    return hip_status(lncc_launch(mode, p->window, p->pad_mode, L, a, loss, roi_voxels(g), (hipStream_t)stream),
                       "ffdp_warp_lncc_bwd");
 }
 

@@ -10,11 +10,14 @@ enum { PAD_BORDER = 0, PAD_ZEROS = 1 };
 
 // Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
 // Remap so that consecutive logical tiles (which share halo data) run on the
-// same XCD: logical = xcd * (nb/8) + (b/8).  Identity when nb % 8 != 0.
+// same XCD: XCD x = b % 8 receives the blocks b = x, x + 8, ..., and takes
+// the contiguous logical range that starts at x * (nb / 8) + min(x, nb % 8)
+// (the first nb % 8 XCDs hold one block more).  A bijection of [0, nb) for
+// every nb.
 __device__ __forceinline__ int xcd_remap(int b, int nb)
 {
-    if ((nb & 7) != 0) return b;
-    return (b & 7) * (nb >> 3) + (b >> 3);
+    const int q = nb >> 3, rem = nb & 7, x = b & 7;
+    return x * q + min(x, rem) + (b >> 3);
 }
 
 // One axis of the sample point p = x + u, split without forming x + u in

@@ -6,11 +6,8 @@
 
 namespace ffdp {
 
-// LNCC tile: 32 x 16 columns per block, 512 threads (8 waves of 64)
-constexpr int LNCC_TX = 32;
-constexpr int LNCC_TY = 16;
-constexpr int LNCC_NT = 512;
-
+// LNCC launch arguments.  Tile sizes are chosen per window and mode by
+// lncc_plan (32 x 32 columns with 1024 threads, or 32 x 16 with 512).
 struct LnccArgs {
     const float* F;
     const float* M;
@@ -23,14 +20,23 @@ struct LnccArgs {
     float eps;
     float neg_inv_nroi;   // -1 / N_roi
     int ntx, nty, zchunk, nblocks;
+    int zspan;            // slices addressable with 32-bit byte offsets from one slice (windowed addressing)
 };
+
+enum { LNCC_ADDR32 = 0, LNCC_ADDRWIN = 1, LNCC_ADDR64 = 2 };
 
 struct LnccLaunch {
+    int tx, ty, nt;       // tile columns and threads per block
     int ntx, nty, zchunk, nchunks, nblocks;
+    int addr, zspan;      // addressing mode and window (slices)
 };
 
-LnccLaunch lncc_plan(int D, int H, int W);
-hipError_t lncc_launch(int mode, int win, int pad, const LnccArgs& a, float* loss, double nroi, hipStream_t st);
+// mode: 0 forward, 1 adjoint, 2 ANTs adjoint
+LnccLaunch lncc_plan(int D, int H, int W, int win, int mode);
+// workspace blocks: the largest plan over the modes of one window
+int lncc_max_blocks(int D, int H, int W, int win);
+hipError_t lncc_launch(int mode, int win, int pad, const LnccLaunch& L, const LnccArgs& a, float* loss, double nroi,
+                       hipStream_t st);
 
 // Composite sampler, affine part: the sample point of voxel X = (x, y, z) is
 // X + d with d = Am X + t + S u(X) and Am = A - I formed on the host in
