@@ -534,6 +534,127 @@ int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, 
     return 0;
 }
 
+/* The same joint PMF for volumes too large to warp whole: each ROI voxel is
+ * sampled (O1) and binned (O4) on the fly, with per-thread histograms added
+ * at the end (the sums of mi_core in another order).  hard = 2 counts the
+ * hard bins first and convolves with K as mi_core does. */
+int orc_mi_pmf(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, const i64* roi, int B,
+               int hard, int pad, double* p_out)
+{
+    const i64 N = D * H * W;
+    i64 R[6];
+    roi_or_full(roi, D, H, W, R);
+    const double nroi = (double)((R[1] - R[0]) * (R[3] - R[2]) * (R[5] - R[4]));
+    const int approx = hard == 2;
+    double* acc = (double*)calloc((size_t)B * B, sizeof(double));
+#pragma omp parallel
+    {
+        double* pl = (double*)calloc((size_t)B * B, sizeof(double));
+        double* kf = (double*)malloc(sizeof(double) * B);
+        double* km = (double*)malloc(sizeof(double) * B);
+        double* of = (double*)malloc(sizeof(double) * B);
+        double* om = (double*)malloc(sizeof(double) * B);
+#pragma omp for schedule(static)
+        for (i64 z = R[0]; z < R[1]; ++z)
+            for (i64 y = R[2]; y < R[3]; ++y)
+                for (i64 x = R[4]; x < R[5]; ++x) {
+                    const i64 k = AT(z, y, x);
+                    double pt[3] = {(double)x, (double)y, (double)z};
+                    if (u) { pt[0] += (double)u[k]; pt[1] += (double)u[N + k]; pt[2] += (double)u[2 * N + k]; }
+                    const double mw = sample_point(M, D, H, W, pt, pad, NULL);
+                    if (approx) {
+                        double vf = (double)F[k], vm = mw;
+                        vf = vf < 0.0 ? 0.0 : (vf > 1.0 ? 1.0 : vf);
+                        vm = vm < 0.0 ? 0.0 : (vm > 1.0 ? 1.0 : vm);
+                        pl[hard_bin(vf, B) * B + hard_bin(vm, B)] += 1.0;
+                        continue;
+                    }
+                    parzen_all((double)F[k], B, hard, kf, of);
+                    parzen_all(mw, B, hard, km, om);
+                    for (int m = 0; m < B; ++m) {
+                        if (kf[m] == 0.0) continue;
+                        for (int nn = 0; nn < B; ++nn) pl[m * B + nn] += kf[m] * km[nn];
+                    }
+                }
+#pragma omp critical
+        for (int q = 0; q < B * B; ++q) acc[q] += pl[q];
+        free(pl); free(kf); free(km); free(of); free(om);
+    }
+    if (approx) {
+        double* K = (double*)malloc(sizeof(double) * B * B);
+        double* kc = (double*)malloc(sizeof(double) * B);
+        double* oc = (double*)malloc(sizeof(double) * B);
+        for (int j = 0; j < B; ++j) {
+            parzen_all(((double)j + 0.5) / (double)B, B, 0, kc, oc);
+            for (int m = 0; m < B; ++m) K[m * B + j] = kc[m];
+        }
+        for (int m = 0; m < B; ++m)
+            for (int nn = 0; nn < B; ++nn) {
+                double a = 0.0;
+                for (int i = 0; i < B; ++i)
+                    for (int j = 0; j < B; ++j) a += K[m * B + i] * K[nn * B + j] * acc[i * B + j];
+                p_out[m * B + nn] = a / nroi;
+            }
+        free(K); free(kc); free(oc);
+    } else {
+        for (int q = 0; q < B * B; ++q) p_out[q] = acc[q] / nroi;
+    }
+    free(acc);
+    return 0;
+}
+
+/* dloss/du (loss = -MI) at the listed voxels pts [npts][3] (z, y, x), given
+ * the joint PMF p of the same inputs (orc_mi_pmf): eq. gradientmi-threadn
+ * with the full double sum of reading G7, times dMw/dp (O1):
+ *   dloss/dMw_k = -(1/N_roi) sum_{m,n} kappa_m(F_k) omega_n(Mw_k)
+ *                 (ln p[m][n] - ln pF[m] - ln pM[n] - 1)
+ * (the last three terms sum to zero over n; ln p - ln pM is taken as 0 where
+ * p = 0), zero outside the ROI.  hard = 2 uses the smooth kernel, as mi_core
+ * does; hard = 1 gives zero. */
+int orc_mi_grad_u_at(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, const i64* roi, int B,
+                     int hard, int pad, const double* p, i64 npts, const i64* pts, double* out)
+{
+    const i64 N = D * H * W;
+    i64 R[6];
+    roi_or_full(roi, D, H, W, R);
+    const double nroi = (double)((R[1] - R[0]) * (R[3] - R[2]) * (R[5] - R[4]));
+    if (hard == 2) hard = 0;
+    double* pF = (double*)calloc(B, sizeof(double));
+    double* pM = (double*)calloc(B, sizeof(double));
+    for (int m = 0; m < B; ++m)
+        for (int nn = 0; nn < B; ++nn) { pF[m] += p[m * B + nn]; pM[nn] += p[m * B + nn]; }
+    double* kf = (double*)malloc(sizeof(double) * B);
+    double* km = (double*)malloc(sizeof(double) * B);
+    double* of = (double*)malloc(sizeof(double) * B);
+    double* om = (double*)malloc(sizeof(double) * B);
+    for (i64 i = 0; i < npts; ++i) {
+        const i64 z = pts[3 * i], y = pts[3 * i + 1], x = pts[3 * i + 2];
+        out[3 * i] = out[3 * i + 1] = out[3 * i + 2] = 0.0;
+        if (!in_roi(R, z, y, x)) continue;
+        const i64 k = AT(z, y, x);
+        double pt[3] = {(double)x, (double)y, (double)z};
+        if (u) { pt[0] += (double)u[k]; pt[1] += (double)u[N + k]; pt[2] += (double)u[2 * N + k]; }
+        double dv[3];
+        const double mw = sample_point(M, D, H, W, pt, pad, dv);
+        parzen_all((double)F[k], B, hard, kf, of);
+        parzen_all(mw, B, hard, km, om);
+        double sdl = 0.0;
+        for (int m = 0; m < B; ++m)
+            for (int nn = 0; nn < B; ++nn) {
+                const double wgt = kf[m] * om[nn];
+                if (wgt == 0.0) continue;
+                const double q = p[m * B + nn];
+                const double t = q > 0.0 ? log(q) - log(pM[nn]) : 0.0;
+                sdl += -wgt / nroi * (t - log(pF[m]) - 1.0);
+            }
+        out[3 * i] = sdl * dv[0];
+        out[3 * i + 1] = sdl * dv[1];
+        out[3 * i + 2] = sdl * dv[2];
+    }
+    free(pF); free(pM); free(kf); free(km); free(of); free(om);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* O7. Composite implicit grid sampler (Sec. "Composite Implicit Grid        */
 /* Sampler", the affine form of Alg. gridsampler): the sample point of the   */

@@ -38,6 +38,8 @@ def load():
                                        vp, _i64, vp]
     lib.orc_mi.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
     lib.orc_parzen.argtypes = [C.c_double, C.c_int, C.c_int, vp, vp]
+    lib.orc_mi_pmf.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_int, C.c_int, vp]
+    lib.orc_mi_grad_u_at.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_int, C.c_int, vp, _i64, vp, vp]
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_max_threads.argtypes = []
     lib.orc_adam.argtypes = [vp, vp, vp, vp, _i64, C.c_double, C.c_double, C.c_double, C.c_double, _i64]
@@ -50,7 +52,7 @@ def load():
     lib.orc_conv3d_fwd.argtypes = [vp, vp, vp, vp] + [_i64] * 9 + [C.c_int, C.c_double, vp]
     lib.orc_conv3d_bwd_data.argtypes = [vp, vp] + [_i64] * 8 + [vp]
     lib.orc_conv3d_bwd_weight.argtypes = [vp, vp, vp] + [_i64] * 9 + [vp, vp]
-    for f in ("orc_warp", "orc_lncc", "orc_lncc_grad_u_at", "orc_mi", "orc_parzen", "orc_adam", "orc_resample",
+    for f in ("orc_warp", "orc_lncc", "orc_lncc_grad_u_at", "orc_mi", "orc_mi_pmf", "orc_mi_grad_u_at", "orc_parzen", "orc_adam", "orc_resample",
               "orc_gaussian_smooth", "orc_warp_affine", "orc_warp_affine_bwd", "orc_mi_affine", "orc_conv3d_fwd", "orc_conv3d_bwd_data", "orc_conv3d_bwd_weight"):
         getattr(lib, f).restype = C.c_int
     _LIB = lib
@@ -138,6 +140,31 @@ def mi(F, M, u=None, roi=None, bins: int = 32, hard: int = 0, pad: int = 0, with
     g = np.empty((3, D, H, W), np.float64) if with_grad else None
     lib.orc_mi(_ptr(F), _ptr(M), _ptr(u), D, H, W, _ptr(r), bins, int(hard), pad, _ptr(loss), _ptr(p), _ptr(g))
     return float(loss[0]), p, g
+
+
+def mi_pmf(F, M, u=None, roi=None, bins: int = 32, hard: int = 0, pad: int = 0):
+    """Joint PMF p[B][B] of (F, M(x+u)) over the ROI, sampled on the fly (for
+    volumes too large for mi()); the same estimator as mi()."""
+    lib = load()
+    F, M, u = _f32(F), _f32(M), _f32(u)
+    D, H, W = F.shape
+    p = np.empty((bins, bins), np.float64)
+    lib.orc_mi_pmf(_ptr(F), _ptr(M), _ptr(u), D, H, W, _ptr(_roi(roi)), bins, int(hard), pad, _ptr(p))
+    return p
+
+
+def mi_grad_u_at(F, M, u, points, p, roi=None, bins: int = 32, hard: int = 0, pad: int = 0):
+    """dloss/du [npts][3] at voxels points [npts][3] (z, y, x) for the PMF p
+    of the same inputs (from mi_pmf or mi)."""
+    lib = load()
+    F, M, u = _f32(F), _f32(M), _f32(u)
+    D, H, W = F.shape
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.int64).reshape(-1, 3))
+    p = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(bins, bins))
+    out = np.empty((pts.shape[0], 3), np.float64)
+    lib.orc_mi_grad_u_at(_ptr(F), _ptr(M), _ptr(u), D, H, W, _ptr(_roi(roi)), bins, int(hard), pad, _ptr(p),
+                         pts.shape[0], _ptr(pts), _ptr(out))
+    return out
 
 
 def parzen(v: float, bins: int, hard: bool = False):

@@ -233,3 +233,46 @@ def test_approx_estimator_swap_symmetry_and_closeness(orc):
     assert abs(la - lb) < 1e-12
     le, _, _ = orc.mi(F, M, None, bins=B, hard=0, with_grad=False)
     assert abs(la - le) < 0.05 * abs(le), (la, le)
+
+
+@pytest.mark.parametrize("hard", [0, 2])
+def test_streamed_pmf_and_pointwise_gradient_match_whole_volume_mi(orc, hard):
+    """mi_pmf (sampling on the fly, per-thread histograms) equals the PMF of
+    mi() (pinned above to brute force and closed forms), and mi_grad_u_at
+    given that PMF equals mi()'s gradient at the listed voxels, inside and
+    outside an ROI."""
+    rng = np.random.default_rng(31)
+    D, H, W = 9, 11, 13
+    F = rng.random((D, H, W)).astype(np.float32)
+    M = rng.random((D, H, W)).astype(np.float32)
+    u = (1.7 * rng.standard_normal((3, D, H, W))).astype(np.float32)
+    roi = [1, 8, 2, 10, 0, 12]
+    loss, p, g = orc.mi(F, M, u, roi=roi, bins=12, hard=hard)
+    ps = orc.mi_pmf(F, M, u, roi=roi, bins=12, hard=hard)
+    np.testing.assert_allclose(ps, p, rtol=1e-12, atol=1e-15)
+    pts = np.array([[z, y, x] for z in (0, 1, 4, 7, 8) for y in (0, 2, 9, 10) for x in (0, 5, 11, 12)])
+    gp = orc.mi_grad_u_at(F, M, u, pts, ps, roi=roi, bins=12, hard=hard)
+    ref = g[:, pts[:, 0], pts[:, 1], pts[:, 2]].T
+    np.testing.assert_allclose(gp, ref, rtol=1e-10, atol=1e-14)
+    assert np.abs(ref).max() > 0
+
+
+def test_pointwise_gradient_is_the_finite_difference_of_the_loss(orc):
+    """mi_grad_u_at against central differences of mi()'s loss in one voxel's
+    displacement (fractional parts kept away from the trilinear kinks)."""
+    rng = np.random.default_rng(32)
+    D, H, W = 8, 9, 10
+    F = rng.random((D, H, W)).astype(np.float32)
+    M = rng.random((D, H, W)).astype(np.float32)
+    u = (0.3 + 0.4 * rng.random((3, D, H, W))).astype(np.float32)
+    p = orc.mi_pmf(F, M, u, bins=8)
+    k = (4, 5, 3)
+    g = orc.mi_grad_u_at(F, M, u, [k], p, bins=8)[0]
+    h = 1e-3
+    for c in range(3):
+        up, um = u.copy(), u.copy()
+        up[c][k] += h
+        um[c][k] -= h
+        fd = (orc.mi(F, M, up, bins=8, with_grad=False)[0] - orc.mi(F, M, um, bins=8, with_grad=False)[0]) / (
+            float(up[c][k]) - float(um[c][k]))
+        assert abs(fd - g[c]) <= 2e-3 * abs(g[c]) + 1e-9, (c, fd, g[c])
