@@ -47,6 +47,7 @@ extern "C" {
 #define FFDP_ERR_ALIGN 4     /* a pointer is not 4-byte aligned */
 #define FFDP_ERR_WORKSPACE 5 /* workspace NULL or smaller than the query */
 #define FFDP_ERR_HIP 6       /* the HIP runtime refused a launch */
+#define FFDP_ERR_NONFINITE 7 /* checked mode: a NaN or infinite input, or a non-finite loss */
 
 #define FFDP_PAD_BORDER 0 /* samples clamp to the array (default) */
 #define FFDP_PAD_ZEROS 1  /* lattice points outside the array read as 0 */
@@ -61,22 +62,34 @@ typedef struct ffdp_grid {
     int64_t roi_hi[3];
 } ffdp_grid;
 
+/* Checked mode (check_finite = 1 in the parameters of ffdp_warp_lncc_fwd,
+ * ffdp_warp_lncc_bwd, ffdp_warp_mi_fwd and ffdp_warp_mi_bwd): before the
+ * computation a pass over F, M, u (when given) and grad_scale (when given)
+ * flags NaN and infinite values; after it the call WAITS for the stream
+ * (the only calls that do) and returns FFDP_ERR_NONFINITE if an input was
+ * flagged or the loss it wrote is not finite (finite inputs can still give a
+ * NaN loss, e.g. eps = 0 with a constant window).  The outputs are written
+ * either way.  The flag lives in the caller's workspace.  0: no checks, no
+ * wait (the default). */
+
 /* LNCC settings (App. "Definition of LNCC loss", Alg. fusedlncc):
- *  window      odd box edge w in {3, 5, 7, 9}; the filter is the uniform
- *              w^3 box with weights 1/w^3, zero padding at the array border.
- *  eps         the stabiliser in n_i = A_i^2 / (B_i C_i + eps); >= 0.
- *  ants_approx 1: skip the window sum of the adjoint (App. "ANTs gradient
- *              approximation"); 0: exact gradient.
- *  pad_mode    FFDP_PAD_BORDER or FFDP_PAD_ZEROS for the sampler. */
+ *  window       odd box edge w in {3, 5, 7, 9}; the filter is the uniform
+ *               w^3 box with weights 1/w^3, zero padding at the array border.
+ *  eps          the stabiliser in n_i = A_i^2 / (B_i C_i + eps); >= 0.
+ *  ants_approx  1: skip the window sum of the adjoint (App. "ANTs gradient
+ *               approximation"); 0: exact gradient.
+ *  pad_mode     FFDP_PAD_BORDER or FFDP_PAD_ZEROS for the sampler.
+ *  check_finite 0 or 1 (checked mode, above). */
 typedef struct ffdp_lncc_params {
     int32_t window;
     float eps;
     int32_t ants_approx;
     int32_t pad_mode;
+    int32_t check_finite;
 } ffdp_lncc_params;
 
 /* MI settings (eq. mi, App. "Vanilla MI implementation"):
- *  bins      B in [8, 64]; bin centres (m + 1/2)/B on [0, 1]; intensities
+ *  bins      B in [8, 256]; bin centres (m + 1/2)/B on [0, 1]; intensities
  *            are clamped to [0, 1].  The kernel is the cubic B-spline of one
  *            bin width; support beyond the first/last bin folds onto it.
  *  hard_bins 0: the Parzen estimate above.
@@ -87,12 +100,14 @@ typedef struct ffdp_lncc_params {
  *               ROI is normalised and convolved with the kernel at bin-centre
  *               offsets (taps 1/6, 2/3, 1/6, folded like the kernel).  The
  *               backward pass is the hard_bins = 0 one evaluated with this p.
- *  pad_mode  as for LNCC. */
+ *  pad_mode  as for LNCC.
+ *  check_finite 0 or 1 (checked mode, above; ffdp_warp_mi_fwd and
+ *            ffdp_warp_mi_bwd only, 0 for the composite-sampler calls). */
 typedef struct ffdp_mi_params {
     int32_t bins;
     int32_t hard_bins;
     int32_t pad_mode;
-    int32_t reserved; /* must be 0 */
+    int32_t check_finite;
 } ffdp_mi_params;
 
 /* Library version (major*10000 + minor*100 + patch). */
@@ -102,7 +117,9 @@ const char* ffdp_status_string(int status);
 /* Text of the last error on this thread ("" if none). */
 const char* ffdp_last_error(void);
 
-/* Workspace bytes for the LNCC / MI calls on this geometry (0 never occurs). */
+/* Workspace bytes for the LNCC / MI calls on this geometry (0 never occurs):
+ * LNCC 8 per thread block of the launch plus 16 (checked-mode flag); MI
+ * 8 * (B^2 + 2).  With p NULL or invalid: enough for any valid p. */
 size_t ffdp_lncc_workspace_bytes(const ffdp_grid* g, const ffdp_lncc_params* p);
 size_t ffdp_mi_workspace_bytes(const ffdp_grid* g, const ffdp_mi_params* p);
 /* Number of floats in the caller-owned MI state: 2*B*B + 2*B + 16. */

@@ -13,8 +13,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libffdp.so")
 
 FFDP_OK = 0
+FFDP_ERR_NONFINITE = 7
 STATUS = {0: "ok", 1: "null pointer", 2: "bad shape or ROI", 3: "bad parameter", 4: "misaligned pointer",
-          5: "workspace missing or too small", 6: "HIP runtime error"}
+          5: "workspace missing or too small", 6: "HIP runtime error", 7: "non-finite input or loss"}
 
 
 class Grid(C.Structure):
@@ -23,11 +24,12 @@ class Grid(C.Structure):
 
 
 class LnccParams(C.Structure):
-    _fields_ = [("window", C.c_int32), ("eps", C.c_float), ("ants_approx", C.c_int32), ("pad_mode", C.c_int32)]
+    _fields_ = [("window", C.c_int32), ("eps", C.c_float), ("ants_approx", C.c_int32), ("pad_mode", C.c_int32),
+                ("check_finite", C.c_int32)]
 
 
 class MiParams(C.Structure):
-    _fields_ = [("bins", C.c_int32), ("hard_bins", C.c_int32), ("pad_mode", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("bins", C.c_int32), ("hard_bins", C.c_int32), ("pad_mode", C.c_int32), ("check_finite", C.c_int32)]
 
 
 class Affine(C.Structure):

@@ -67,17 +67,48 @@ int check_lncc(const ffdp_lncc_params* p)
     if (p->ants_approx != 0 && p->ants_approx != 1) return fail(FFDP_ERR_PARAM, "ants_approx must be 0 or 1");
     if (p->pad_mode != FFDP_PAD_BORDER && p->pad_mode != FFDP_PAD_ZEROS)
         return fail(FFDP_ERR_PARAM, "pad_mode must be 0 (border) or 1 (zeros)");
+    if (p->check_finite != 0 && p->check_finite != 1) return fail(FFDP_ERR_PARAM, "check_finite must be 0 or 1");
     return FFDP_OK;
 }
 
 int check_mi(const ffdp_mi_params* p)
 {
     if (!p) return fail(FFDP_ERR_NULL, "mi params are NULL");
-    if (p->bins < 8 || p->bins > 64) return fail(FFDP_ERR_PARAM, "bins must be in [8, 64] (got %d)", p->bins);
+    if (p->bins < 8 || p->bins > MI_MAX_BINS)
+        return fail(FFDP_ERR_PARAM, "bins must be in [8, %d] (got %d)", MI_MAX_BINS, p->bins);
     if (p->hard_bins < 0 || p->hard_bins > 2) return fail(FFDP_ERR_PARAM, "hard_bins must be 0, 1 or 2");
     if (p->pad_mode != FFDP_PAD_BORDER && p->pad_mode != FFDP_PAD_ZEROS)
         return fail(FFDP_ERR_PARAM, "pad_mode must be 0 (border) or 1 (zeros)");
-    if (p->reserved != 0) return fail(FFDP_ERR_PARAM, "reserved must be 0");
+    if (p->check_finite != 0 && p->check_finite != 1) return fail(FFDP_ERR_PARAM, "check_finite must be 0 or 1");
+    return FFDP_OK;
+}
+
+// Checked mode (check_finite = 1): the flag word is cleared and set by a pass
+// over the inputs before the computation; finish_checked waits for the stream
+// and reports a flagged input or a non-finite loss.
+int start_checked(const float* F, const float* M, const float* u, const ffdp_grid* g, const float* grad_scale,
+                  unsigned* flag, hipStream_t st)
+{
+    const long long N = (long long)g->D * g->H * g->W;
+    hipError_t e = finite_clear_launch(flag, st);
+    if (e == hipSuccess) e = finite_check_launch(F, N, flag, st);
+    if (e == hipSuccess) e = finite_check_launch(M, N, flag, st);
+    if (e == hipSuccess && u) e = finite_check_launch(u, 3 * N, flag, st);
+    if (e == hipSuccess && grad_scale) e = finite_check_launch(grad_scale, 1, flag, st);
+    return hip_status(e, "checked mode (input scan)");
+}
+
+int finish_checked(int status, const unsigned* flag, const float* loss, hipStream_t st)
+{
+    if (status != FFDP_OK) return status;
+    unsigned hf = 0;
+    float hl = 0.0f;
+    hipError_t e = hipMemcpyAsync(&hf, flag, sizeof(hf), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && loss) e = hipMemcpyAsync(&hl, loss, sizeof(hl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_status(e, "checked mode (read-back)");
+    if (hf) return fail(FFDP_ERR_NONFINITE, "an input (F, M, u or grad_scale) holds a NaN or infinite value");
+    if (loss && !isfinite(hl)) return fail(FFDP_ERR_NONFINITE, "the loss is not finite (%g)", (double)hl);
     return FFDP_OK;
 }
 
@@ -128,13 +159,23 @@ void fill_roi(const ffdp_grid* g, int roi[6])
     roi[4] = (int)g->roi_lo[2]; roi[5] = (int)g->roi_hi[2];
 }
 
-// one double per thread block of the largest plan over the modes of the window
+// one double per thread block of the largest plan over the modes of the
+// window, then 16 bytes for the checked-mode flag
 size_t lncc_ws(const ffdp_grid* g, int window)
 {
-    return (size_t)lncc_max_blocks((int)g->D, (int)g->H, (int)g->W, window) * sizeof(double);
+    return (size_t)lncc_max_blocks((int)g->D, (int)g->H, (int)g->W, window) * sizeof(double) + 16;
+}
+unsigned* lncc_flag(void* ws, const ffdp_grid* g, int window)
+{
+    return reinterpret_cast<unsigned*>(static_cast<char*>(ws) + lncc_ws(g, window) - 16);
 }
 
-size_t mi_ws(const ffdp_mi_params* p) { return ((size_t)p->bins * p->bins + 1) * sizeof(unsigned long long); }
+// the B^2 histogram, its NaN flag, the checked-mode flag
+size_t mi_ws(const ffdp_mi_params* p) { return ((size_t)p->bins * p->bins + 2) * sizeof(unsigned long long); }
+unsigned* mi_flag(void* ws, const ffdp_mi_params* p)
+{
+    return reinterpret_cast<unsigned*>(static_cast<unsigned long long*>(ws) + (size_t)p->bins * p->bins + 1);
+}
 
 int lncc_common(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_lncc_params* p,
                 void* ws, size_t ws_bytes, int mode, LnccArgs& a, LnccLaunch& L)
@@ -171,6 +212,8 @@ int mi_common(const float* F, const float* M, const float* u, const ffdp_grid* g
     int s = check_grid(g);
     if (s) return s;
     if ((s = check_mi(p))) return s;
+    if (ws_kind && p->check_finite)
+        return fail(FFDP_ERR_PARAM, "check_finite is not available for the composite-sampler calls");
     if ((s = check_ptrs("F,M", 2, (const void*)F, (const void*)M))) return s;
     if ((s = check_opt_ptr(u, "u"))) return s;
     const size_t need = ws_kind ? affine_ws(g) : mi_ws(p);
@@ -231,6 +274,7 @@ const char* ffdp_status_string(int s)
         case FFDP_ERR_ALIGN: return "misaligned pointer";
         case FFDP_ERR_WORKSPACE: return "workspace missing or too small";
         case FFDP_ERR_HIP: return "HIP runtime error";
+        case FFDP_ERR_NONFINITE: return "non-finite input or loss";
         default: return "unknown status";
     }
 }
@@ -249,7 +293,7 @@ size_t ffdp_lncc_workspace_bytes(const ffdp_grid* g, const ffdp_lncc_params* p)
 size_t ffdp_mi_workspace_bytes(const ffdp_grid* g, const ffdp_mi_params* p)
 {
     (void)g;
-    if (!p || p->bins < 8 || p->bins > 64) return sizeof(unsigned long long) * (64 * 64 + 1);
+    if (!p || p->bins < 8 || p->bins > MI_MAX_BINS) return sizeof(unsigned long long) * (MI_MAX_BINS * MI_MAX_BINS + 2);
     return mi_ws(p);
 }
 
@@ -300,8 +344,11 @@ int ffdp_warp_lncc_fwd(const float* F, const float* M, const float* u, const ffd
     int s = lncc_common(F, M, u, g, p, ws, ws_bytes, 0, a, L);
     if (s) return s;
     if ((s = check_ptrs("loss", 1, (const void*)loss))) return s;
-    return hip_status(lncc_launch(0, p->window, p->pad_mode, L, a, loss, roi_voxels(g), (hipStream_t)stream),
-                      "ffdp_warp_lncc_fwd");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned* flag = lncc_flag(ws, g, p->window);
+    if (p->check_finite && (s = start_checked(F, M, u, g, nullptr, flag, st))) return s;
+    s = hip_status(lncc_launch(0, p->window, p->pad_mode, L, a, loss, roi_voxels(g), st), "ffdp_warp_lncc_fwd");
+    return p->check_finite ? finish_checked(s, flag, loss, st) : s;
 }
 
 int ffdp_warp_lncc_bwd(const float* F, const float* M, const float* u, const ffdp_grid* g,
@@ -318,8 +365,11 @@ int ffdp_warp_lncc_bwd(const float* F, const float* M, const float* u, const ffd
     a.gu = grad_u;
     a.grad_scale = grad_scale;
     const int mode = p->ants_approx ? 2 : 1;
-    return hip_status(lncc_launch(mode, p->window, p->pad_mode, L, a, loss, roi_voxels(g), (hipStream_t)stream),
-                      "ffdp_warp_lncc_bwd");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned* flag = lncc_flag(ws, g, p->window);
+    if (p->check_finite && (s = start_checked(F, M, u, g, grad_scale, flag, st))) return s;
+    s = hip_status(lncc_launch(mode, p->window, p->pad_mode, L, a, loss, roi_voxels(g), st), "ffdp_warp_lncc_bwd");
+    return p->check_finite ? finish_checked(s, flag, loss, st) : s;
 }
 
 int ffdp_warp_mi_fwd(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_mi_params* p,
@@ -331,9 +381,13 @@ int ffdp_warp_mi_fwd(const float* F, const float* M, const float* u, const ffdp_
     if ((s = check_ptrs("loss,mi_state", 2, (const void*)loss, (const void*)mi_state))) return s;
     MiLaunch L = mi_plan(a.roi[1] - a.roi[0], a.roi[3] - a.roi[2], a.roi[5] - a.roi[4]);
     a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk; a.nblocks = L.nblocks;
-    return hip_status(mi_fwd_launch(a, p->hard_bins, p->pad_mode, (unsigned long long*)ws, mi_state, loss,
-                                    roi_voxels(g), (hipStream_t)stream),
-                      "ffdp_warp_mi_fwd");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned* flag = mi_flag(ws, p);
+    if (p->check_finite && (s = start_checked(F, M, u, g, nullptr, flag, st))) return s;
+    s = hip_status(mi_fwd_launch(a, p->hard_bins, p->pad_mode, (unsigned long long*)ws, mi_state, loss,
+                                 roi_voxels(g), st),
+                   "ffdp_warp_mi_fwd");
+    return p->check_finite ? finish_checked(s, flag, loss, st) : s;
 }
 
 int ffdp_warp_mi_bwd(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_mi_params* p,
@@ -347,9 +401,12 @@ int ffdp_warp_mi_bwd(const float* F, const float* M, const float* u, const ffdp_
     if ((s = check_opt_ptr(grad_scale, "grad_scale"))) return s;
     MiLaunch L = mi_plan(a.D, a.H, a.W);
     a.ntx = L.ntx; a.nty = L.nty; a.zchunk = L.zchunk; a.nblocks = L.nblocks;
-    return hip_status(mi_bwd_launch(a, p->hard_bins, p->pad_mode, mi_state, grad_scale, grad_u, roi_voxels(g),
-                                    (hipStream_t)stream),
-                      "ffdp_warp_mi_bwd");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned* flag = mi_flag(ws, p);
+    if (p->check_finite && (s = start_checked(F, M, u, g, grad_scale, flag, st))) return s;
+    s = hip_status(mi_bwd_launch(a, p->hard_bins, p->pad_mode, mi_state, grad_scale, grad_u, roi_voxels(g), st),
+                   "ffdp_warp_mi_bwd");
+    return p->check_finite ? finish_checked(s, flag, nullptr, st) : s;
 }
 
 size_t ffdp_affine_workspace_bytes(const ffdp_grid* g)
@@ -405,6 +462,7 @@ int ffdp_warp_mi_affine_fwd(const float* F, const float* M, const float* u, cons
     MiArgs a;
     int s = mi_common(F, M, u, g, p, ws, ws_bytes, a);
     if (s) return s;
+    if (p->check_finite) return fail(FFDP_ERR_PARAM, "check_finite is not available for the composite-sampler calls");
     if ((s = check_ptrs("loss,mi_state", 2, (const void*)loss, (const void*)mi_state))) return s;
     if ((s = affine_from(aff, a.aff))) return s;
     a.affine = 1;

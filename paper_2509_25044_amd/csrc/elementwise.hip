@@ -249,4 +249,36 @@ hipError_t adam_launch(float* x, const float* g, float* m, float* v, int64_t n, 
     return hipSuccess;
 }
 
+// Checked mode: one flag word set when any value of an input is NaN or
+// infinite (exponent bits all ones).  Cleared by a kernel rather than a
+// memset, so a captured call records no memset node.
+__global__ void __launch_bounds__(64) finite_flag_clear(unsigned* flag)
+{
+    if (threadIdx.x == 0) *flag = 0u;
+}
+
+__global__ void __launch_bounds__(256) finite_check_kernel(const float* __restrict__ p, long long n,
+                                                           unsigned* __restrict__ flag)
+{
+    bool bad = false;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        bad |= (__float_as_uint(p[i]) & 0x7f800000u) == 0x7f800000u;
+    if (__builtin_amdgcn_ballot_w64(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+hipError_t finite_clear_launch(unsigned* flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(finite_flag_clear, dim3(1), dim3(64), 0, st, flag);
+    return hipGetLastError();
+}
+
+hipError_t finite_check_launch(const float* p, long long n, unsigned* flag, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(finite_check_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, flag);
+    return hipGetLastError();
+}
+
 }  // namespace ffdp

@@ -80,6 +80,8 @@ __device__ __forceinline__ void affine_adjoint(const Affine& f, int x, int y, in
 hipError_t affine_reduce_launch(const double* part, int nblocks, double* out, hipStream_t st);
 
 // MI
+constexpr int MI_MAX_BINS = 256;
+constexpr int MI_LDS_TABLE_BINS = 128;  // log tables up to 128^2 floats (64 KB) are staged in LDS
 constexpr int MI_TX = 64;
 constexpr int MI_TY = 4;
 constexpr int MI_NT = MI_TX * MI_TY;
@@ -107,6 +109,10 @@ hipError_t mi_fwd_launch(const MiArgs& a, int hard, int pad, unsigned long long*
                          double nroi, hipStream_t st);
 hipError_t mi_bwd_launch(const MiArgs& a, int hard, int pad, const float* state, const float* grad_scale,
                          float* gu, double nroi, hipStream_t st);
+
+// checked mode: flag = 0, then flag |= any non-finite value of p[0..n)
+hipError_t finite_clear_launch(unsigned* flag, hipStream_t st);
+hipError_t finite_check_launch(const float* p, long long n, unsigned* flag, hipStream_t st);
 
 // elementwise
 hipError_t warp_launch(const float* M, const float* u, int D, int H, int W, int pad, float* out, hipStream_t st);

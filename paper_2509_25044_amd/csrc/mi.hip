@@ -239,7 +239,8 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
     extern __shared__ unsigned long long hist[];  // a.ncopy copies of [B*B], stride B*B+1
     const int B = a.bins, BB = B * B, CS = BB + 1;
     for (int q = threadIdx.x; q < a.ncopy * CS; q += MI_NT) hist[q] = 0ull;
-    unsigned long long* const mine = hist + (threadIdx.x & (a.ncopy - 1)) * CS;
+    // ncopy == 0 (histograms too large for LDS): add straight into the global one
+    unsigned long long* const mine = a.ncopy ? hist + (threadIdx.x & (a.ncopy - 1)) * CS : ghist;
     __shared__ int nanflag;
     if (threadIdx.x == 0) nanflag = 0;
     __syncthreads();
@@ -296,7 +297,7 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
     }
     if (bad) nanflag = 1;
     __syncthreads();
-    for (int q = threadIdx.x; q < BB; q += MI_NT) {
+    for (int q = threadIdx.x; a.ncopy && q < BB; q += MI_NT) {
         unsigned long long v = 0ull;
         for (int c = 0; c < a.ncopy; ++c) v += hist[c * CS + q];
         if (v) atomicAdd(&ghist[q], v);
@@ -311,7 +312,8 @@ __global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long
     extern __shared__ unsigned int cnt[];  // a.ncopy copies of [B*B], stride B*B+1
     const int B = a.bins, BB = B * B, CS = BB + 1;
     for (int q = threadIdx.x; q < a.ncopy * CS; q += MI_NT) cnt[q] = 0u;
-    unsigned int* const mine = cnt + (threadIdx.x & (a.ncopy - 1)) * CS;
+    unsigned int* const mine = cnt + (threadIdx.x & (a.ncopy > 0 ? a.ncopy - 1 : 0)) * CS;
+    const bool glob = a.ncopy == 0;  // counts too large for LDS: add straight into the global histogram
     __shared__ int nanflag;
     if (threadIdx.x == 0) nanflag = 0;
     __syncthreads();
@@ -339,17 +341,23 @@ __global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long
             const int bm = exact_bin(fminf(fmaxf(mv, 0.0f), 1.0f), B);
             const int q = bf * B + bm;
             if (q != cur) {
-                if (run) atomicAdd(&mine[cur], run);
+                if (run) {
+                    if (glob) atomicAdd(&ghist[cur], (unsigned long long)run);
+                    else atomicAdd(&mine[cur], run);
+                }
                 cur = q;
                 run = 0u;
             }
             ++run;
         }
-        if (run) atomicAdd(&mine[cur], run);
+        if (run) {
+            if (glob) atomicAdd(&ghist[cur], (unsigned long long)run);
+            else atomicAdd(&mine[cur], run);
+        }
     }
     if (bad) nanflag = 1;
     __syncthreads();
-    for (int q = threadIdx.x; q < BB; q += MI_NT) {
+    for (int q = threadIdx.x; !glob && q < BB; q += MI_NT) {
         unsigned long long v = 0ull;
         for (int c = 0; c < a.ncopy; ++c) v += cnt[c * CS + q];
         if (v) atomicAdd(&ghist[q], v);
@@ -369,15 +377,31 @@ __device__ __forceinline__ double centre_tap(int m, int j, int B)
     return w;
 }
 
+// Entry (m, n) of the approximate PMF p = K (counts / total) K^T.
+__device__ __forceinline__ double approx_p(const unsigned long long* __restrict__ hist, int B, int m, int n,
+                                          double sc)
+{
+    double acc = 0.0;
+    for (int i = max(m - 1, 0); i <= min(m + 1, B - 1); ++i) {
+        const double wi = centre_tap(m, i, B);
+        if (wi == 0.0) continue;
+        double row = 0.0;
+        for (int j = max(n - 1, 0); j <= min(n + 1, B - 1); ++j) row += centre_tap(n, j, B) * (double)hist[i * B + j];
+        acc += wi * row;
+    }
+    return acc * sc;
+}
+
 // One block: the approximate PMF p = K (counts / total) K^T, marginals, MI and
-// the log table, with the same state layout as mi_finalize.
+// the log table, with the same state layout as mi_finalize.  Entries of p
+// are recomputed where needed (nine taps each) instead of held, so any
+// B <= 256 fits.
 __global__ void __launch_bounds__(1024) mi_finalize_approx(const unsigned long long* __restrict__ hist,
                                                            const unsigned long long* __restrict__ flag, int B,
                                                            float* __restrict__ state, float* __restrict__ loss)
 {
-    __shared__ double P[64 * 64];
-    __shared__ double pF[64], pM[64];
-    __shared__ unsigned long long rowsum[64];
+    __shared__ double pF[MI_MAX_BINS], pM[MI_MAX_BINS];
+    __shared__ unsigned long long rowsum[MI_MAX_BINS];
     __shared__ double red[1024];
     const int BB = B * B;
     for (int t = threadIdx.x; t < B; t += 1024) {
@@ -389,23 +413,9 @@ __global__ void __launch_bounds__(1024) mi_finalize_approx(const unsigned long l
     unsigned long long total = 0;
     for (int t = 0; t < B; ++t) total += rowsum[t];
     const double sc = total ? 1.0 / (double)total : 0.0;
-    for (int q = threadIdx.x; q < BB; q += 1024) {
-        const int m = q / B, n = q - m * B;
-        double acc = 0.0;
-        for (int i = max(m - 1, 0); i <= min(m + 1, B - 1); ++i) {
-            const double wi = centre_tap(m, i, B);
-            if (wi == 0.0) continue;
-            double row = 0.0;
-            for (int j = max(n - 1, 0); j <= min(n + 1, B - 1); ++j)
-                row += centre_tap(n, j, B) * (double)hist[i * B + j];
-            acc += wi * row;
-        }
-        P[q] = acc * sc;
-    }
-    __syncthreads();
     for (int t = threadIdx.x; t < B; t += 1024) {
         double rf = 0.0, cm = 0.0;
-        for (int n = 0; n < B; ++n) { rf += P[t * B + n]; cm += P[n * B + t]; }
+        for (int n = 0; n < B; ++n) { rf += approx_p(hist, B, t, n, sc); cm += approx_p(hist, B, n, t, sc); }
         pF[t] = rf;
         pM[t] = cm;
     }
@@ -413,7 +423,7 @@ __global__ void __launch_bounds__(1024) mi_finalize_approx(const unsigned long l
     double part = 0.0;
     for (int q = threadIdx.x; q < BB; q += 1024) {
         const int m = q / B, n = q - m * B;
-        const double p = P[q];
+        const double p = approx_p(hist, B, m, n, sc);
         float tv = 0.0f;
         if (p > 0.0) {
             part += p * log(p / (pF[m] * pM[n]));
@@ -452,8 +462,8 @@ __global__ void __launch_bounds__(1024) mi_finalize(const unsigned long long* __
                                                     const unsigned long long* __restrict__ flag, int B,
                                                     float* __restrict__ state, float* __restrict__ loss)
 {
-    __shared__ double pF[64], pM[64];
-    __shared__ unsigned long long rowsum[64];
+    __shared__ double pF[MI_MAX_BINS], pM[MI_MAX_BINS];
+    __shared__ unsigned long long rowsum[MI_MAX_BINS];
     __shared__ double red[1024];
     const int BB = B * B;
     for (int t = threadIdx.x; t < B; t += 1024) {
@@ -505,10 +515,12 @@ __global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* _
                                                         const float* __restrict__ grad_scale, float neg_inv_nroi,
                                                         float* __restrict__ gu)
 {
-    extern __shared__ float T[];  // [B*B]
+    extern __shared__ float Ts[];  // [B*B] for B <= MI_LDS_TABLE_BINS
     const int B = a.bins, BB = B * B;
-    for (int q = threadIdx.x; q < BB; q += MI_NT) T[q] = state[q];
+    const bool lds_table = B <= MI_LDS_TABLE_BINS;
+    for (int q = threadIdx.x; lds_table && q < BB; q += MI_NT) Ts[q] = state[q];
     __syncthreads();
+    const float* __restrict__ T = lds_table ? Ts : state;  // larger tables are read through the caches
     const float g = neg_inv_nroi * (grad_scale ? *grad_scale : 1.0f);
 
     const int bid = xcd_remap(blockIdx.x, a.nblocks);
@@ -615,10 +627,14 @@ hipError_t mi_fwd_launch(const MiArgs& a0, int hard, int pad, unsigned long long
 {
     (void)nroi;
     MiArgs a = a0;
-    // LDS histogram copies: at most 4, and at most 66 KB of u64 bins (4
-    // copies up to 45 bins, 2 copies up to 64)
-    a.ncopy = 1;
-    while (a.ncopy < 4 && (size_t)2 * a.ncopy * (a.bins * a.bins + 1) * sizeof(unsigned long long) <= 67584) a.ncopy *= 2;
+    // LDS histogram copies: at most 4, and at most 66 KB of bins (u64 for the
+    // Parzen histogram: 4 copies up to 45 bins, 2 up to 64, 1 up to 90; u32
+    // counts of the approximate estimator: 1 copy up to 128 bins).  Larger
+    // histograms are added straight into the global one (ncopy = 0).
+    const size_t cell = hard == 2 ? sizeof(unsigned int) : sizeof(unsigned long long);
+    const size_t one = (size_t)(a.bins * a.bins + 1) * cell;
+    a.ncopy = one <= 67584 ? 1 : 0;
+    while (a.ncopy && a.ncopy < 4 && 2 * a.ncopy * one <= 67584) a.ncopy *= 2;
     const int BB = a.bins * a.bins;
     unsigned long long* flag = hist + BB;
     hipLaunchKernelGGL(mi_zero, dim3((BB + 1 + 255) / 256), dim3(256), 0, st, hist, BB + 1);
@@ -632,7 +648,7 @@ template <bool AFF>
 static hipError_t mi_bwd_dispatch(const MiArgs& a, int hard, int pad, const float* state, const float* grad_scale,
                                   float nin, float* gu, hipStream_t st)
 {
-    const size_t lds = sizeof(float) * a.bins * a.bins;
+    const size_t lds = a.bins <= MI_LDS_TABLE_BINS ? sizeof(float) * a.bins * a.bins : 0;
     dim3 grid(a.nblocks), block(MI_NT);
     if (hard == 1) {
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<true, PAD_BORDER, AFF>), grid, block, lds, st, a, state, grad_scale, nin, gu);

@@ -118,22 +118,25 @@ def _check_pair(F, M, u):
             raise ValueError(f"u must be [3, D, H, W] on F's device (got {tuple(u.shape)})")
 
 
-def lncc_params(window=5, eps=1e-5, ants=False, pad="border") -> LnccParams:
+def lncc_params(window=5, eps=1e-5, ants=False, pad="border", check=False) -> LnccParams:
+    """check: checked mode (the call scans its inputs, waits for the stream and raises FfdpError with code
+    FFDP_ERR_NONFINITE on a NaN or infinite input or loss)."""
     p = LnccParams()
     p.window, p.eps, p.ants_approx, p.pad_mode = int(window), float(eps), int(bool(ants)), PAD[pad]
+    p.check_finite = int(bool(check))
     return p
 
 
 MI_ESTIMATORS = {"parzen": 0, "box": 1, "approx": 2}
 
 
-def mi_params(bins=32, hard=False, pad="border") -> MiParams:
+def mi_params(bins=32, hard=False, pad="border", check=False) -> MiParams:
     """hard: False/"parzen" exact Parzen window, True/"box" box kernel (test
     mode), "approx" the approximate estimator (hard-bin counts convolved
     with the kernel; exact-kernel backward)."""
     p = MiParams()
     mode = MI_ESTIMATORS[hard] if isinstance(hard, str) else int(bool(hard))
-    p.bins, p.hard_bins, p.pad_mode, p.reserved = int(bins), mode, PAD[pad], 0
+    p.bins, p.hard_bins, p.pad_mode, p.check_finite = int(bins), mode, PAD[pad], int(bool(check))
     return p
 
 
@@ -180,11 +183,12 @@ def resample(src: torch.Tensor, size: Sequence[int], value_scale: float = 1.0, o
     return o4[0] if squeeze else o4
 
 
-def warp_lncc_fwd(F, M, u=None, window=5, eps=1e-5, pad="border", roi=None, loss=None, ws=None) -> torch.Tensor:
+def warp_lncc_fwd(F, M, u=None, window=5, eps=1e-5, pad="border", roi=None, loss=None, ws=None,
+                  check_finite=False) -> torch.Tensor:
     """LNCC loss 1 - mean n_i of (F, M(x+u)) over the ROI -> float32 tensor [1] (ffdp_warp_lncc_fwd)."""
     _check_pair(F, M, u)
     g = make_grid(F.shape, roi)
-    p = lncc_params(window, eps, False, pad)
+    p = lncc_params(window, eps, False, pad, check_finite)
     L = _lib.lib()
     ws = _workspace(int(L.ffdp_lncc_workspace_bytes(C.byref(g), C.byref(p))), F.device, ws)
     loss = torch.empty(1, dtype=torch.float32, device=F.device) if loss is None else _dev_scalar(loss, "loss", F.device)
@@ -194,11 +198,12 @@ def warp_lncc_fwd(F, M, u=None, window=5, eps=1e-5, pad="border", roi=None, loss
 
 
 def warp_lncc_bwd(F, M, u=None, window=5, eps=1e-5, ants=False, pad="border", roi=None, grad_scale=None,
-                  grad_u=None, loss=None, want_loss=True, ws=None) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+                  grad_u=None, loss=None, want_loss=True, ws=None,
+                  check_finite=False) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
     """Fused LNCC forward + adjoint: (grad_u [3,D,H,W], loss [1] or None) (ffdp_warp_lncc_bwd)."""
     _check_pair(F, M, u)
     g = make_grid(F.shape, roi)
-    p = lncc_params(window, eps, ants, pad)
+    p = lncc_params(window, eps, ants, pad, check_finite)
     L = _lib.lib()
     ws = _workspace(int(L.ffdp_lncc_workspace_bytes(C.byref(g), C.byref(p))), F.device, ws)
     if grad_u is None:
@@ -215,11 +220,12 @@ def warp_lncc_bwd(F, M, u=None, window=5, eps=1e-5, ants=False, pad="border", ro
     return grad_u, loss
 
 
-def warp_mi_fwd(F, M, u=None, bins=32, hard=False, pad="border", roi=None, state=None, loss=None, ws=None):
+def warp_mi_fwd(F, M, u=None, bins=32, hard=False, pad="border", roi=None, state=None, loss=None, ws=None,
+                check_finite=False):
     """Parzen MI: (loss = -MI [1], mi_state) (ffdp_warp_mi_fwd)."""
     _check_pair(F, M, u)
     g = make_grid(F.shape, roi)
-    p = mi_params(bins, hard, pad)
+    p = mi_params(bins, hard, pad, check_finite)
     L = _lib.lib()
     ws = _workspace(int(L.ffdp_mi_workspace_bytes(C.byref(g), C.byref(p))), F.device, ws)
     if state is None:
@@ -231,11 +237,12 @@ def warp_mi_fwd(F, M, u=None, bins=32, hard=False, pad="border", roi=None, state
     return loss, state
 
 
-def warp_mi_bwd(F, M, u, state, bins=32, hard=False, pad="border", roi=None, grad_scale=None, grad_u=None, ws=None):
+def warp_mi_bwd(F, M, u, state, bins=32, hard=False, pad="border", roi=None, grad_scale=None, grad_u=None, ws=None,
+                check_finite=False):
     """MI adjoint -> grad_u [3,D,H,W] (ffdp_warp_mi_bwd)."""
     _check_pair(F, M, u)
     g = make_grid(F.shape, roi)
-    p = mi_params(bins, hard, pad)
+    p = mi_params(bins, hard, pad, check_finite)
     L = _lib.lib()
     ws = _workspace(int(L.ffdp_mi_workspace_bytes(C.byref(g), C.byref(p))), F.device, ws)
     if grad_u is None:

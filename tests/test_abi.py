@@ -44,15 +44,15 @@ def _grid(D=8, H=8, W=8, roi=None):
     return g
 
 
-def _lp(window=5, eps=1e-5, ants=0, pad=0):
+def _lp(window=5, eps=1e-5, ants=0, pad=0, check=0):
     p = LnccParams()
-    p.window, p.eps, p.ants_approx, p.pad_mode = window, eps, ants, pad
+    p.window, p.eps, p.ants_approx, p.pad_mode, p.check_finite = window, eps, ants, pad, check
     return p
 
 
-def _mp(bins=32, hard=0, pad=0, reserved=0):
+def _mp(bins=32, hard=0, pad=0, check=0):
     p = MiParams()
-    p.bins, p.hard_bins, p.pad_mode, p.reserved = bins, hard, pad, reserved
+    p.bins, p.hard_bins, p.pad_mode, p.check_finite = bins, hard, pad, check
     return p
 
 
@@ -64,6 +64,7 @@ def test_status_strings_and_version(L):
     assert L.ffdp_version() >= 100
     assert L.ffdp_status_string(0) == b"ok"
     assert L.ffdp_status_string(5).startswith(b"workspace")
+    assert L.ffdp_status_string(7).startswith(b"non-finite")
     assert L.ffdp_status_string(99) == b"unknown status"
 
 
@@ -72,7 +73,13 @@ def test_workspace_queries_grow_with_blocks_not_voxels(L):
     small = L.ffdp_lncc_workspace_bytes(C.byref(_grid(64, 64, 64)), C.byref(lp))
     big = L.ffdp_lncc_workspace_bytes(C.byref(_grid(512, 512, 512)), C.byref(lp))
     assert 0 < small <= big <= 64 * 1024      # O(#blocks) doubles, far below N
-    assert L.ffdp_mi_workspace_bytes(C.byref(_grid()), C.byref(_mp(32))) == (32 * 32 + 1) * 8
+    assert (small - 16) % 8 == 0 and (big - 16) % 8 == 0  # block partials, then the checked-mode flag
+    assert L.ffdp_mi_workspace_bytes(C.byref(_grid()), C.byref(_mp(32))) == (32 * 32 + 2) * 8
+    assert L.ffdp_mi_workspace_bytes(C.byref(_grid()), C.byref(_mp(256))) == (256 * 256 + 2) * 8
+    assert L.ffdp_mi_workspace_bytes(C.byref(_grid()), None) == (256 * 256 + 2) * 8  # any valid bins
+    # no (valid) parameters: enough for every window
+    n = [L.ffdp_lncc_workspace_bytes(C.byref(_grid(100, 200, 300)), C.byref(_lp(window=w))) for w in (3, 5, 7, 9)]
+    assert L.ffdp_lncc_workspace_bytes(C.byref(_grid(100, 200, 300)), None) == max(n)
     assert L.ffdp_mi_state_floats(32) == 2 * 32 * 32 + 2 * 32 + 16
 
 
@@ -95,6 +102,7 @@ def test_workspace_queries_grow_with_blocks_not_voxels(L):
     (dict(params=_lp(eps=float("nan"))), 3),
     (dict(params=_lp(pad=2)), 3),
     (dict(params=_lp(ants=3)), 3),
+    (dict(params=_lp(check=2)), 3),
     (dict(ws=None), 5),
     (dict(ws_bytes=1), 5),
     (dict(loss=None), 1),
@@ -118,14 +126,35 @@ def test_lncc_bwd_validation(L):
                                 1 << 20, None) == 3
 
 
-@pytest.mark.parametrize("mp,code", [(_mp(bins=7), 3), (_mp(bins=65), 3), (_mp(hard=3), 3), (_mp(hard=-1), 3), (_mp(pad=5), 3),
-                                     (_mp(reserved=1), 3)])
+@pytest.mark.parametrize("mp,code", [(_mp(bins=7), 3), (_mp(bins=257), 3), (_mp(hard=3), 3), (_mp(hard=-1), 3),
+                                     (_mp(pad=5), 3), (_mp(check=2), 3), (_mp(check=-1), 3)])
 def test_mi_validation(L, mp, code):
     g = _grid()
     s = L.ffdp_warp_mi_fwd(FAKE, FAKE, None, C.byref(g), C.byref(mp), FAKE, FAKE, FAKE, 1 << 20, None)
     assert s == code
     s = L.ffdp_warp_mi_bwd(FAKE, FAKE, None, C.byref(g), C.byref(mp), FAKE, None, FAKE, FAKE, 1 << 20, None)
     assert s == code
+
+
+def test_mi_bins_beyond_64_pass_validation_to_the_workspace_check(L):
+    g = _grid()
+    for b in (65, 128, 200, 256):
+        need = L.ffdp_mi_workspace_bytes(C.byref(g), C.byref(_mp(b)))
+        assert L.ffdp_warp_mi_fwd(FAKE, FAKE, None, C.byref(g), C.byref(_mp(b)), FAKE, FAKE, FAKE, need - 8,
+                                  None) == 5
+        assert b"workspace" in L.ffdp_last_error()
+
+
+def test_checked_mode_is_refused_by_the_composite_sampler_calls(L):
+    from paper_2509_25044_amd._lib import Affine
+    g, aff = _grid(), Affine()
+    for i in range(3):
+        aff.A[4 * i] = 1.0
+        aff.S[4 * i] = 1.0
+    mp = _mp(check=1)
+    assert L.ffdp_warp_mi_affine_fwd(FAKE, FAKE, None, C.byref(g), C.byref(aff), C.byref(mp), FAKE, FAKE, FAKE,
+                                     1 << 20, None) == 3
+    assert b"check_finite" in L.ffdp_last_error()
 
 
 def test_mi_workspace_and_null_checks(L):

@@ -87,13 +87,22 @@ def _lncc_case(F, M, u, window=5, eps=1e-5, ants=False, pad="border", roi=None, 
     print(f"[lncc {what} shape={tuple(F.shape)} w={window} ants={ants} pad={pad} roi={roi}]", flush=True)
     Fd, Md = _dev(F), _dev(M)
     ud = None if u is None else _dev(u)
-    lf = float(ops.warp_lncc_fwd(Fd, Md, ud, window=window, eps=eps, pad=pad, roi=roi).item())
-    g, lb = ops.warp_lncc_bwd(Fd, Md, ud, window=window, eps=eps, ants=ants, pad=pad, roi=roi)
+    nws = ops.lncc_workspace_bytes(F.shape, roi, window)
+    wsf = torch.zeros(nws, dtype=torch.uint8, device=DEV)
+    wsb = torch.zeros(nws, dtype=torch.uint8, device=DEV)
+    lf = float(ops.warp_lncc_fwd(Fd, Md, ud, window=window, eps=eps, pad=pad, roi=roi, ws=wsf).item())
+    g, lb = ops.warp_lncc_bwd(Fd, Md, ud, window=window, eps=eps, ants=ants, pad=pad, roi=roi, ws=wsb)
     lb = float(lb.item())
     lr, gr = oracle.lncc(F.numpy(), M.numpy(), None if u is None else u.numpy(), roi=_roi6(roi), window=window,
                          eps=eps, ants=ants, pad=1 if pad == "zeros" else 0)
     assert_loss(lf, lr, f"{what} fwd")
     assert_loss(lb, lr, f"{what} bwd")
+    # the FP64 block partials hold sum n_i: the mean similarity 1 - L without
+    # the fp32 rounding of L (the strong form of the check where L is near 1)
+    nroi = np.prod([b - a for a, b in roi]) if roi is not None else F.numel()
+    for name, ws in (("fwd", wsf), ("bwd", wsb)):
+        sim = float(ws.view(torch.float64).sum().item()) / nroi
+        assert abs(sim - (1.0 - lr)) <= 1e-5 * abs(1.0 - lr) + 1e-9, f"{what} {name} similarity {sim} vs {1.0 - lr}"
     assert_grad(_np(g), gr, f"{what} grad")
 
 
@@ -131,6 +140,8 @@ def test_lncc_c2_clinical_window7(c2):
 def test_lncc_ragged_shapes(shape):
     F, M, u = _rand_case(shape, 130)
     _lncc_case(F, M, u, window=5, eps=1e-3, what="ragged")
+    _lncc_case(F, M, u, window=5, eps=1e-5, what="ragged eps 1e-5")
+    _lncc_case(F, M, u, window=7, eps=1e-5, what="ragged w7")
     _lncc_case(F, M, u, window=3, eps=1e-3, ants=True, what="ragged ants")
 
 
@@ -300,6 +311,55 @@ def test_mi_bin_counts_and_histogram_copies(c1, bins):
     _mi_case(F, M, u, bins=bins, what=f"c1 b{bins}")
     if bins in (45, 64):
         _mi_case(F, M, u, bins=bins, hard="approx", what=f"c1 approx b{bins}")
+
+
+@pytest.mark.parametrize("bins", [90, 91, 128, 129, 200, 256])
+def test_mi_wide_histograms(bins):
+    """Bin counts beyond the LDS-resident layouts: one u64 LDS histogram up to
+    90 bins, global u64 atomics above; the approximate estimator's u32
+    counts in LDS up to 128 bins, global above; the adjoint's log table in
+    LDS up to 128 bins, read through the caches above."""
+    F, M, u = _rand_case((24, 28, 36), 160 + bins)
+    _mi_case(F, M, u, bins=bins, what=f"wide b{bins}")
+    if bins in (90, 129, 200):  # the oracle's approximate p is a B^4 sum
+        _mi_case(F, M, u, bins=bins, hard="approx", what=f"wide approx b{bins}")
+
+
+def test_checked_mode(c1):
+    """check_finite = 1: the same results on finite inputs; FFDP_ERR_NONFINITE
+    for a NaN or infinite value in F, M, u or grad_scale, and for a NaN loss
+    from finite inputs (eps = 0 on a constant image)."""
+    from paper_2509_25044_amd._lib import FfdpError
+    F, M, u = (_dev(t) for t in c1)
+    g0, l0 = ops.warp_lncc_bwd(F, M, u)
+    g1, l1 = ops.warp_lncc_bwd(F, M, u, check_finite=True)
+    assert torch.equal(g0, g1) and torch.equal(l0, l1)
+    assert torch.equal(ops.warp_lncc_fwd(F, M, u, check_finite=True), l0)
+    m0, s0 = ops.warp_mi_fwd(F, M, u)
+    m1, s1 = ops.warp_mi_fwd(F, M, u, check_finite=True)
+    assert torch.equal(m0, m1) and torch.equal(s0, s1)
+    assert torch.equal(ops.warp_mi_bwd(F, M, u, s1, check_finite=True), ops.warp_mi_bwd(F, M, u, s1))
+
+    def refused(fn):
+        with pytest.raises(FfdpError) as e:
+            fn()
+        assert e.value.code == 7, e.value
+    Fn = F.clone()
+    Fn[3, 4, 5] = float("nan")
+    un = u.clone()
+    un[1, 10, 11, 12] = float("inf")
+    Mn = M.clone()
+    Mn[60, 1, 2] = -float("inf")
+    refused(lambda: ops.warp_lncc_fwd(Fn, M, u, check_finite=True))
+    refused(lambda: ops.warp_lncc_bwd(F, M, un, check_finite=True))
+    refused(lambda: ops.warp_lncc_bwd(F, M, u, grad_scale=torch.tensor([float("nan")], device=DEV),
+                                      check_finite=True))
+    refused(lambda: ops.warp_mi_fwd(F, Mn, u, check_finite=True))
+    refused(lambda: ops.warp_mi_bwd(F, M, un, s1, check_finite=True))
+    C = torch.full_like(F, 0.5)
+    l_nan = ops.warp_lncc_fwd(C, C, None, eps=0.0)  # unchecked: a NaN loss, no error
+    assert torch.isnan(l_nan).all()
+    refused(lambda: ops.warp_lncc_fwd(C, C, None, eps=0.0, check_finite=True))
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (37, 45, 70)])
