@@ -537,9 +537,13 @@ int orc_mi(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, 
 /* The same joint PMF for volumes too large to warp whole: each ROI voxel is
  * sampled (O1) and binned (O4) on the fly, with per-thread histograms added
  * at the end (the sums of mi_core in another order).  hard = 2 counts the
- * hard bins first and convolves with K as mi_core does. */
+ * hard bins first and convolves with K as mi_core does.  n_edge (nullable)
+ * receives the number of ROI voxels whose warped value, clamped to [0, 1],
+ * lies within edge_tol of an interior bin edge m / B (0 < m < B), the
+ * voxels whose hard bin a less precise evaluation of the same value could
+ * change. */
 int orc_mi_pmf(const float* F, const float* M, const float* u, i64 D, i64 H, i64 W, const i64* roi, int B,
-               int hard, int pad, double* p_out)
+               int hard, int pad, double* p_out, double edge_tol, i64* n_edge)
 {
     const i64 N = D * H * W;
     i64 R[6];
@@ -547,7 +551,8 @@ int orc_mi_pmf(const float* F, const float* M, const float* u, i64 D, i64 H, i64
     const double nroi = (double)((R[1] - R[0]) * (R[3] - R[2]) * (R[5] - R[4]));
     const int approx = hard == 2;
     double* acc = (double*)calloc((size_t)B * B, sizeof(double));
-#pragma omp parallel
+    i64 nedge = 0;
+#pragma omp parallel reduction(+ : nedge)
     {
         double* pl = (double*)calloc((size_t)B * B, sizeof(double));
         double* kf = (double*)malloc(sizeof(double) * B);
@@ -562,6 +567,11 @@ int orc_mi_pmf(const float* F, const float* M, const float* u, i64 D, i64 H, i64
                     double pt[3] = {(double)x, (double)y, (double)z};
                     if (u) { pt[0] += (double)u[k]; pt[1] += (double)u[N + k]; pt[2] += (double)u[2 * N + k]; }
                     const double mw = sample_point(M, D, H, W, pt, pad, NULL);
+                    {
+                        const double t = (mw < 0.0 ? 0.0 : (mw > 1.0 ? 1.0 : mw)) * (double)B;
+                        const double e = floor(t + 0.5);
+                        if (e > 0.0 && e < (double)B && fabs(t - e) <= edge_tol * (double)B) ++nedge;
+                    }
                     if (approx) {
                         double vf = (double)F[k], vm = mw;
                         vf = vf < 0.0 ? 0.0 : (vf > 1.0 ? 1.0 : vf);
@@ -600,6 +610,7 @@ int orc_mi_pmf(const float* F, const float* M, const float* u, i64 D, i64 H, i64
         for (int q = 0; q < B * B; ++q) p_out[q] = acc[q] / nroi;
     }
     free(acc);
+    if (n_edge) *n_edge = nedge;
     return 0;
 }
 

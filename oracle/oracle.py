@@ -38,7 +38,7 @@ def load():
                                        vp, _i64, vp]
     lib.orc_mi.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_int, C.c_int, vp, vp, vp]
     lib.orc_parzen.argtypes = [C.c_double, C.c_int, C.c_int, vp, vp]
-    lib.orc_mi_pmf.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_int, C.c_int, vp]
+    lib.orc_mi_pmf.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_int, C.c_int, vp, C.c_double, vp]
     lib.orc_mi_grad_u_at.argtypes = [vp, vp, vp, _i64, _i64, _i64, vp, C.c_int, C.c_int, C.c_int, vp, _i64, vp, vp]
     lib.orc_set_threads.argtypes = [C.c_int]
     lib.orc_max_threads.argtypes = []
@@ -142,15 +142,20 @@ def mi(F, M, u=None, roi=None, bins: int = 32, hard: int = 0, pad: int = 0, with
     return float(loss[0]), p, g
 
 
-def mi_pmf(F, M, u=None, roi=None, bins: int = 32, hard: int = 0, pad: int = 0):
+def mi_pmf(F, M, u=None, roi=None, bins: int = 32, hard: int = 0, pad: int = 0, edge_tol: float = 0.0,
+           with_edges: bool = False):
     """Joint PMF p[B][B] of (F, M(x+u)) over the ROI, sampled on the fly (for
-    volumes too large for mi()); the same estimator as mi()."""
+    volumes too large for mi()); the same estimator as mi().  with_edges:
+    also return the number of ROI voxels whose clamped warped value lies
+    within edge_tol of an interior bin edge."""
     lib = load()
     F, M, u = _f32(F), _f32(M), _f32(u)
     D, H, W = F.shape
     p = np.empty((bins, bins), np.float64)
-    lib.orc_mi_pmf(_ptr(F), _ptr(M), _ptr(u), D, H, W, _ptr(_roi(roi)), bins, int(hard), pad, _ptr(p))
-    return p
+    ne = np.zeros(1, np.int64)
+    lib.orc_mi_pmf(_ptr(F), _ptr(M), _ptr(u), D, H, W, _ptr(_roi(roi)), bins, int(hard), pad, _ptr(p),
+                   float(edge_tol), _ptr(ne))
+    return (p, int(ne[0])) if with_edges else p
 
 
 def mi_grad_u_at(F, M, u, points, p, roi=None, bins: int = 32, hard: int = 0, pad: int = 0):

@@ -32,7 +32,7 @@ def _db3(t):
     return np.nan_to_num(v, nan=0.0)
 
 
-@pytest.mark.parametrize("B", [8, 32])
+@pytest.mark.parametrize("B", [8, 32, 256])
 def test_parzen_weights_match_scipy_bspline_in_the_interior(orc, B):
     rng = np.random.default_rng(30)
     for v in rng.uniform(2.0 / B, 1.0 - 2.0 / B, 50):
@@ -43,7 +43,7 @@ def test_parzen_weights_match_scipy_bspline_in_the_interior(orc, B):
         np.testing.assert_allclose(o, B * _db3(s - m), rtol=0, atol=1e-12)
 
 
-@pytest.mark.parametrize("B", [8, 32, 64])
+@pytest.mark.parametrize("B", [8, 32, 64, 200, 256])
 def test_parzen_partition_of_unity_and_zero_derivative_sum(orc, B):
     for v in np.concatenate([np.linspace(-0.1, 1.1, 241), [0.0, 1.0, 0.5 / B, 1 - 0.5 / B]]):
         k, o = orc.parzen(v, B)
@@ -82,7 +82,7 @@ def _entropy(p):
     return float(-(p * np.log(p)).sum())
 
 
-@pytest.mark.parametrize("B", [8, 32])
+@pytest.mark.parametrize("B", [8, 32, 256])
 def test_self_information_identity_and_bounds(orc, B):
     F = synth.random_volume((10, 9, 8), 33).numpy()
     loss, p, _ = orc.mi(F, F, None, bins=B, with_grad=False)
@@ -127,7 +127,7 @@ def _grid_sample(M, u):
                                            padding_mode="border", align_corners=True)[0, 0]
 
 
-@pytest.mark.parametrize("B,roi", [(8, None), (16, ((1, 6), (0, 7), (2, 8)))])
+@pytest.mark.parametrize("B,roi", [(8, None), (16, ((1, 6), (0, 7), (2, 8))), (256, None)])
 def test_loss_and_gradient_match_autograd_of_parzen_block_route(orc, B, roi):
     D, H, W = 7, 8, 9
     F = synth.random_volume((D, H, W), 36, lo=0.05, hi=0.95).numpy()
@@ -276,3 +276,21 @@ def test_pointwise_gradient_is_the_finite_difference_of_the_loss(orc):
         fd = (orc.mi(F, M, up, bins=8, with_grad=False)[0] - orc.mi(F, M, um, bins=8, with_grad=False)[0]) / (
             float(up[c][k]) - float(um[c][k]))
         assert abs(fd - g[c]) <= 2e-3 * abs(g[c]) + 1e-9, (c, fd, g[c])
+
+
+def test_streamed_pmf_counts_values_near_bin_edges(orc):
+    """The edge count of mi_pmf is the number of ROI voxels whose clamped
+    warped value lies within the tolerance of an interior bin edge (counted
+    here from the oracle's warp)."""
+    rng = np.random.default_rng(33)
+    D, H, W = 8, 9, 10
+    F = rng.random((D, H, W)).astype(np.float32)
+    M = (np.round(rng.random((D, H, W)) * 16) / 16).astype(np.float32)  # many values on edges of 8 or 16 bins
+    u = np.zeros((3, D, H, W), np.float32)
+    u[0, ::2] = 0.5
+    for B, tol in ((8, 1e-6), (16, 1e-6), (16, 0.02)):
+        _, ne = orc.mi_pmf(F, M, u, roi=[1, 7, 0, 9, 2, 10], bins=B, edge_tol=tol, with_edges=True)
+        mw = np.clip(orc.warp(M, u), 0.0, 1.0)[1:7, 0:9, 2:10] * B
+        e = np.floor(mw + 0.5)
+        ref = int(((np.abs(mw - e) <= tol * B) & (e > 0) & (e < B)).sum())
+        assert ne == ref and (tol < 0.01 or ne > 0), (B, tol, ne, ref)
