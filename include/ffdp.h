@@ -26,7 +26,9 @@
  *  - Return value: FFDP_OK or one of the FFDP_ERR_* codes below.  The text
  *    of the last error on the calling thread is in ffdp_last_error().
  *  - Calls on different streams with disjoint outputs and workspaces may run
- *    concurrently; the library keeps no mutable global state.
+ *    concurrently; the library keeps no mutable global state, except for
+ *    the one entry point for callers that cannot allocate
+ *    (ffdp_warp_lncc_bwd_noalloc), whose scratch array is shared per GPU.
  *  - Reductions are two-stage and in a fixed order (LNCC) or in exact
  *    integer arithmetic (MI histogram), so results are bitwise reproducible.
  */
@@ -156,6 +158,22 @@ int ffdp_warp_lncc_fwd(const float* F, const float* M, const float* u, const ffd
 int ffdp_warp_lncc_bwd(const float* F, const float* M, const float* u, const ffdp_grid* g,
                        const ffdp_lncc_params* p, const float* grad_scale, float* grad_u, float* loss, void* ws,
                        size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): ffdp_warp_lncc_bwd with its block partials in a library-owned
+ * device array of FFDP_NOALLOC_MAX_BLOCKS doubles (512 KB, one per GPU, held
+ * until the process ends) instead of a caller workspace.  Same arguments and
+ * results otherwise (bitwise the same outputs; checked mode included).  Grids
+ * whose launch needs more than FFDP_NOALLOC_MAX_BLOCKS partials are rejected
+ * with FFDP_ERR_WORKSPACE before anything runs.  All calls on one
+ * GPU share its array: calls that overlap in time on one GPU (different
+ * streams or threads) race and must be serialised by the caller.  The array
+ * belongs to the device that runs `stream`. */
+#define FFDP_NOALLOC_MAX_BLOCKS 65536
+int ffdp_warp_lncc_bwd_noalloc(const float* F, const float* M, const float* u, const ffdp_grid* g,
+                               const ffdp_lncc_params* p, const float* grad_scale, float* grad_u, float* loss,
+                               void* stream);
 
 /* Fused warp + Parzen MI forward (eq. mi; App. "Implicit MI implementation",
  * Forward Pass): the joint histogram of (F, M(x+u)) over the ROI, then

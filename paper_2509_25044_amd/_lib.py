@@ -74,6 +74,7 @@ def lib():
         "ffdp_resample": ([vp, i64, i64, i64, vp, i64, i64, i64, i32, f32, vp], C.c_int),
         "ffdp_warp_lncc_fwd": ([vp, vp, vp, gp, lp, vp, vp, sz, vp], C.c_int),
         "ffdp_warp_lncc_bwd": ([vp, vp, vp, gp, lp, vp, vp, vp, vp, sz, vp], C.c_int),
+        "ffdp_warp_lncc_bwd_noalloc": ([vp, vp, vp, gp, lp, vp, vp, vp, vp], C.c_int),
         "ffdp_warp_mi_fwd": ([vp, vp, vp, gp, mp, vp, vp, vp, sz, vp], C.c_int),
         "ffdp_warp_mi_bwd": ([vp, vp, vp, gp, mp, vp, vp, vp, vp, sz, vp], C.c_int),
         "ffdp_affine_workspace_bytes": ([gp], sz),

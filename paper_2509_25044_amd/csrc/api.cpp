@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/ffdp.h"
 #include "adam.hpp"
 #include "internal.hpp"
@@ -370,6 +372,70 @@ int ffdp_warp_lncc_bwd(const float* F, const float* M, const float* u, const ffd
     if (p->check_finite && (s = start_checked(F, M, u, g, grad_scale, flag, st))) return s;
     s = hip_status(lncc_launch(mode, p->window, p->pad_mode, L, a, loss, roi_voxels(g), st), "ffdp_warp_lncc_bwd");
     return p->check_finite ? finish_checked(s, flag, loss, st) : s;
+}
+
+// Library-owned LNCC block partials for ffdp_warp_lncc_bwd_noalloc: one
+// array per GPU, held until the process ends.  In host code `scratch` only
+// names the symbol; its device address comes from hipGetSymbolAddress, once
+// per device, and only that address is ever passed to a kernel.
+static __device__ __align__(256) double scratch[FFDP_NOALLOC_MAX_BLOCKS + 2];  // + the checked-mode flag
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the device that runs `stream`, looked up
+// with that device current the first time the device is seen.
+int scratch_address(void* stream, double** out)
+{
+    int dev = 0;
+    hipError_t e = hipStreamGetDevice((hipStream_t)stream, &dev);
+    if (e != hipSuccess) return hip_status(e, "hipStreamGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FFDP_ERR_PARAM, "device %d beyond the %d supported", dev,
+                                                   kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = 0;
+        if ((e = hipGetDevice(&cur)) != hipSuccess) return hip_status(e, "hipGetDevice");
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return hip_status(e, "hipSetDevice");
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) {
+            hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return hip_status(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return FFDP_OK;
+}
+
+}  // namespace
+
+int ffdp_warp_lncc_bwd_noalloc(const float* F, const float* M, const float* u, const ffdp_grid* g,
+                               const ffdp_lncc_params* p, const float* grad_scale, float* grad_u, float* loss,
+                               void* stream)
+{
+    // everything that can be checked without the device first
+    int s = check_grid(g);
+    if (s) return s;
+    if ((s = check_lncc(p))) return s;
+    const size_t need = lncc_ws(g, p->window);
+    if (need > sizeof(scratch))
+        return fail(FFDP_ERR_WORKSPACE, "this grid needs %zu block partials; the library-owned scratch holds %d",
+                    (need - 16) / sizeof(double), FFDP_NOALLOC_MAX_BLOCKS);
+    if ((s = check_ptrs("F,M,grad_u", 3, (const void*)F, (const void*)M, (const void*)grad_u))) return s;
+    if ((s = check_opt_ptr(u, "u"))) return s;
+    if ((s = check_opt_ptr(grad_scale, "grad_scale"))) return s;
+    if ((s = check_opt_ptr(loss, "loss"))) return s;
+    double* part = nullptr;
+    if ((s = scratch_address(stream, &part))) return s;
+    // every block writes its own partial before the finalize reads them, so
+    // nothing has to be cleared between calls
+    return ffdp_warp_lncc_bwd(F, M, u, g, p, grad_scale, grad_u, loss, part, sizeof(scratch), stream);
 }
 
 int ffdp_warp_mi_fwd(const float* F, const float* M, const float* u, const ffdp_grid* g, const ffdp_mi_params* p,

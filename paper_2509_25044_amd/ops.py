@@ -220,6 +220,23 @@ def warp_lncc_bwd(F, M, u=None, window=5, eps=1e-5, ants=False, pad="border", ro
     return grad_u, loss
 
 
+def warp_lncc_bwd_noalloc(F, M, u, grad_u, loss=None, window=5, eps=1e-5, ants=False, pad="border", roi=None,
+                          grad_scale=None):
+    """ffdp_warp_lncc_bwd with the library-owned scratch (ffdp_warp_lncc_bwd_noalloc): the caller passes every
+    output (grad_u [3,D,H,W], loss [1] or None); nothing is allocated."""
+    _check_pair(F, M, u)
+    g = make_grid(F.shape, roi)
+    p = lncc_params(window, eps, ants, pad)
+    L = _lib.lib()
+    _out(grad_u, "grad_u", (3,) + tuple(F.shape), F.device)
+    _dev_scalar(loss, "loss", F.device)
+    _dev_scalar(grad_scale, "grad_scale", F.device)
+    check("ffdp_warp_lncc_bwd_noalloc",
+          L.ffdp_warp_lncc_bwd_noalloc(_ptr(F), _ptr(M), _ptr(u), C.byref(g), C.byref(p), _ptr(grad_scale),
+                                       _ptr(grad_u), _ptr(loss), _stream(F)))
+    return grad_u, loss
+
+
 def warp_mi_fwd(F, M, u=None, bins=32, hard=False, pad="border", roi=None, state=None, loss=None, ws=None,
                 check_finite=False):
     """Parzen MI: (loss = -MI [1], mi_state) (ffdp_warp_mi_fwd)."""
