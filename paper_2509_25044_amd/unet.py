@@ -107,6 +107,22 @@ class UNet3D:
     def state_dict(self):
         return {"master": self.master.cpu(), "m": self.m.cpu(), "v": self.v.cpu(), "step": self.step_count}
 
+    def save_weights(self, path: str):
+        """The fp32 master weights alone (no optimiser state), as safetensors."""
+        from safetensors.torch import save_file
+        save_file({"master": self.master.detach().cpu().contiguous()}, path,
+                  metadata={"layers": ",".join(L.name for L in LAYERS), "nparams": str(self.nparams),
+                            "step": str(self.step_count)})
+
+    def load_weights(self, path: str):
+        """Master weights written by save_weights (safetensors: no code runs on load)."""
+        from safetensors.torch import load_file
+        w = load_file(path)["master"]
+        if w.numel() != self.nparams:
+            raise ValueError(f"{path}: {w.numel()} parameters, this network has {self.nparams}")
+        self.master.copy_(w.to(self.device))
+        self.refresh_bf16()
+
     def load_state_dict(self, d):
         self.master.copy_(d["master"].to(self.device))
         self.m.copy_(d["m"].to(self.device))

@@ -220,6 +220,8 @@ def c5_main(args):
                    log=lambda s: print(s, flush=True), make=lambda seed: c5_training_pair(seed, dev))
         if args.save:
             torch.save(model.state_dict(), args.save)
+        if args.save_weights:
+            model.save_weights(args.save_weights)
     print(f"trained {tr['pairs']} pairs in {tr['seconds']:.1f} s", flush=True)
     res = []
     for k in range(args.eval_pairs):
@@ -258,6 +260,8 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None, help="write the trained network's weights here")
     ap.add_argument("--load", default=None, help="skip training and load weights from here")
+    ap.add_argument("--save-weights", default=None, help="also write the trained weights alone (safetensors)")
+    ap.add_argument("--load-weights", default=None, help="skip training and load weights alone (safetensors)")
     ap.add_argument("--resume", action="store_true", help="with --load: keep training the loaded weights")
     ap.add_argument("--train-pairs", type=int, default=None,
                     help="pairs to train on (default --pairs); with --resume drawn from --seed0 on")
@@ -278,13 +282,17 @@ def main():
     tr = {"steps": 0, "pairs": 0, "seconds": 0.0, "history": []}
     if args.load:
         model.load_state_dict(torch.load(args.load, map_location="cpu", weights_only=True))
-    if not args.load or args.resume:
+    if args.load_weights:
+        model.load_weights(args.load_weights)
+    if not (args.load or args.load_weights) or args.resume:
         n_train = args.pairs if args.train_pairs is None else args.train_pairs
         tr = train(model, spec, n_train, args.batch, args.lr, seed0=args.seed0,
                    converged_every=args.converged_every, reg_cfg=conv_cfg, log=lambda s: print(s, flush=True),
                    lr_final=args.lr_final)
         if args.save:
             torch.save(model.state_dict(), args.save)
+        if args.save_weights:
+            model.save_weights(args.save_weights)
     print(f"trained {tr['pairs']} pairs in {tr['seconds']:.1f} s", flush=True)
     res = []
     for k in range(args.eval_pairs):
@@ -305,6 +313,8 @@ def _report(args, shape, tr, res, table):
     if args.out:
         with open(args.out, "w") as f:
             json.dump(out, f, indent=1)
+    if not res:
+        return
     summ = {"plain_seconds_mean": sum(r["plain_seconds"] for r in res) / len(res), "plain_iters": res[0]["plain_iters"]}
     for name in table:
         for init in ("warm", "zero"):

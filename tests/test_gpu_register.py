@@ -194,3 +194,29 @@ def test_affine_mi_stage_recovers_a_known_affine():
         print(hard, "corner error", err, "loss", l0, "->", l1, flush=True)
         assert err < 1.0, (hard, err)
         assert l1 < l0
+
+
+def test_registration_recovers_the_inverse_field_on_a_textured_pair():
+    """On a 64^3 pair whose images carry the band-passed texture (reading W1:
+    on the plain blob images a 5^3 window sees little of the motion), a
+    two-level LNCC registration with the paper's smoothing moves u toward the
+    true inverse displacement: the rms error in the interior falls below
+    three quarters of that of u = 0 (0.48 against 0.73 voxels when this test
+    was written) and u points the same way as the true field (correlation
+    0.82; asserted above 0.75)."""
+    print("[register textured pair, inverse recovery]", flush=True)
+    from paper_2509_25044_amd.warmstart import inverse_target
+    spec = synth.PairSpec((64, 64, 64), (3.0, 8.0), 3.0, texture_std=0.05)
+    p = synth.make_pair(spec, seed=synth.BASE_SEED + 7, device=DEV)
+    F, M = p["F"], p["M"]
+    tgt = inverse_target(p["d"])
+    inner = (slice(None), slice(6, -6), slice(6, -6), slice(6, -6))
+    st = register(F, M, RegConfig(loss="lncc", window=5, levels=(0.5, 1.0), iters=(100,), lr=0.1, sigma_grad=1.0,
+                                  sigma_warp=0.5))
+    e0 = float(torch.sqrt((tgt[inner] ** 2).mean()))
+    e = float(torch.sqrt(((st.u - tgt)[inner] ** 2).mean()))
+    a, b = st.u[inner].reshape(-1).double(), tgt[inner].reshape(-1).double()
+    corr = float((a * b).sum() / (a.norm() * b.norm()))
+    print("rms error: u = 0", e0, "registered", e, "correlation", corr, flush=True)
+    assert e < 0.75 * e0, (e0, e)
+    assert corr > 0.75, corr
