@@ -232,15 +232,17 @@ struct ColumnSampler {
     }
 };
 
-template <bool HARD, int PAD, bool AFF>
+// GLOB: the histogram is too large for LDS (a.ncopy == 0) and the taps are
+// added straight into the global one; otherwise into a.ncopy LDS copies.
+// (Compile-time, so that each atomic is an LDS or a global one, never flat.)
+template <bool HARD, int PAD, bool AFF, bool GLOB>
 __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long long* __restrict__ ghist,
                                                         unsigned long long* __restrict__ gflag)
 {
     extern __shared__ unsigned long long hist[];  // a.ncopy copies of [B*B], stride B*B+1
     const int B = a.bins, BB = B * B, CS = BB + 1;
-    for (int q = threadIdx.x; q < a.ncopy * CS; q += MI_NT) hist[q] = 0ull;
-    // ncopy == 0 (histograms too large for LDS): add straight into the global one
-    unsigned long long* const mine = a.ncopy ? hist + (threadIdx.x & (a.ncopy - 1)) * CS : ghist;
+    for (int q = threadIdx.x; !GLOB && q < a.ncopy * CS; q += MI_NT) hist[q] = 0ull;
+    unsigned long long* const mine = GLOB ? ghist : hist + (threadIdx.x & (a.ncopy - 1)) * CS;
     __shared__ int nanflag;
     if (threadIdx.x == 0) nanflag = 0;
     __syncthreads();
@@ -297,7 +299,7 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
     }
     if (bad) nanflag = 1;
     __syncthreads();
-    for (int q = threadIdx.x; a.ncopy && q < BB; q += MI_NT) {
+    for (int q = threadIdx.x; !GLOB && q < BB; q += MI_NT) {
         unsigned long long v = 0ull;
         for (int c = 0; c < a.ncopy; ++c) v += hist[c * CS + q];
         if (v) atomicAdd(&ghist[q], v);
@@ -510,17 +512,19 @@ __global__ void __launch_bounds__(1024) mi_finalize(const unsigned long long* __
     }
 }
 
-template <bool HARD, int PAD, bool AFF>
+// LDST: the log table is staged in LDS (B <= MI_LDS_TABLE_BINS); larger
+// tables are read from the state through the caches.  (Compile-time, so the
+// table reads are LDS or global loads, never flat.)
+template <bool HARD, int PAD, bool AFF, bool LDST>
 __global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* __restrict__ state,
                                                         const float* __restrict__ grad_scale, float neg_inv_nroi,
                                                         float* __restrict__ gu)
 {
-    extern __shared__ float Ts[];  // [B*B] for B <= MI_LDS_TABLE_BINS
+    extern __shared__ float Ts[];  // [B*B] when LDST
     const int B = a.bins, BB = B * B;
-    const bool lds_table = B <= MI_LDS_TABLE_BINS;
-    for (int q = threadIdx.x; lds_table && q < BB; q += MI_NT) Ts[q] = state[q];
+    for (int q = threadIdx.x; LDST && q < BB; q += MI_NT) Ts[q] = state[q];
     __syncthreads();
-    const float* __restrict__ T = lds_table ? Ts : state;  // larger tables are read through the caches
+    const float* __restrict__ T = LDST ? Ts : state;
     const float g = neg_inv_nroi * (grad_scale ? *grad_scale : 1.0f);
 
     const int bid = xcd_remap(blockIdx.x, a.nblocks);
@@ -609,12 +613,20 @@ static hipError_t mi_fwd_dispatch(const MiArgs& a, int hard, int pad, unsigned l
         return hipGetLastError();
     }
     const size_t lds = sizeof(unsigned long long) * a.ncopy * (BB + 1);
-    if (hard) {
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER, AFF>), grid, block, lds, st, a, hist, flag);
-        else hipLaunchKernelGGL((mi_hist_kernel<true, PAD_ZEROS, AFF>), grid, block, lds, st, a, hist, flag);
+    if (a.ncopy == 0) {
+        if (hard) {
+            if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER, AFF, true>), grid, block, 0, st, a, hist, flag);
+            else hipLaunchKernelGGL((mi_hist_kernel<true, PAD_ZEROS, AFF, true>), grid, block, 0, st, a, hist, flag);
+        } else {
+            if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<false, PAD_BORDER, AFF, true>), grid, block, 0, st, a, hist, flag);
+            else hipLaunchKernelGGL((mi_hist_kernel<false, PAD_ZEROS, AFF, true>), grid, block, 0, st, a, hist, flag);
+        }
+    } else if (hard) {
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER, AFF, false>), grid, block, lds, st, a, hist, flag);
+        else hipLaunchKernelGGL((mi_hist_kernel<true, PAD_ZEROS, AFF, false>), grid, block, lds, st, a, hist, flag);
     } else {
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<false, PAD_BORDER, AFF>), grid, block, lds, st, a, hist, flag);
-        else hipLaunchKernelGGL((mi_hist_kernel<false, PAD_ZEROS, AFF>), grid, block, lds, st, a, hist, flag);
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<false, PAD_BORDER, AFF, false>), grid, block, lds, st, a, hist, flag);
+        else hipLaunchKernelGGL((mi_hist_kernel<false, PAD_ZEROS, AFF, false>), grid, block, lds, st, a, hist, flag);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -648,14 +660,18 @@ template <bool AFF>
 static hipError_t mi_bwd_dispatch(const MiArgs& a, int hard, int pad, const float* state, const float* grad_scale,
                                   float nin, float* gu, hipStream_t st)
 {
-    const size_t lds = a.bins <= MI_LDS_TABLE_BINS ? sizeof(float) * a.bins * a.bins : 0;
+    const bool ldst = a.bins <= MI_LDS_TABLE_BINS;
+    const size_t lds = ldst ? sizeof(float) * a.bins * a.bins : 0;
     dim3 grid(a.nblocks), block(MI_NT);
-    if (hard == 1) {
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<true, PAD_BORDER, AFF>), grid, block, lds, st, a, state, grad_scale, nin, gu);
-        else hipLaunchKernelGGL((mi_grad_kernel<true, PAD_ZEROS, AFF>), grid, block, lds, st, a, state, grad_scale, nin, gu);
+    if (hard == 1) {  // box kernel: zero gradient, the table is not read
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<true, PAD_BORDER, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
+        else hipLaunchKernelGGL((mi_grad_kernel<true, PAD_ZEROS, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
+    } else if (ldst) {
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<false, PAD_BORDER, AFF, true>), grid, block, lds, st, a, state, grad_scale, nin, gu);
+        else hipLaunchKernelGGL((mi_grad_kernel<false, PAD_ZEROS, AFF, true>), grid, block, lds, st, a, state, grad_scale, nin, gu);
     } else {
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<false, PAD_BORDER, AFF>), grid, block, lds, st, a, state, grad_scale, nin, gu);
-        else hipLaunchKernelGGL((mi_grad_kernel<false, PAD_ZEROS, AFF>), grid, block, lds, st, a, state, grad_scale, nin, gu);
+        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<false, PAD_BORDER, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
+        else hipLaunchKernelGGL((mi_grad_kernel<false, PAD_ZEROS, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
     }
     return hipGetLastError();
 }
