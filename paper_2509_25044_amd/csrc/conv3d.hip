@@ -13,13 +13,20 @@
 // with P = dL/dy * act'(y) (LeakyReLU: slope where y <= 0), formed in the
 // gather and rounded to bf16 as the MFMA operand.
 //
-// Each 64-lane wave owns one 16-row slab of the GEMM and issues
-// v_mfma_f32_16x16x16_bf16 over 16-wide K chunks.  Operand layout of that
-// instruction (lane l, element e = 0..3):
-//   A[i][k]: i = l % 16, k = 4 (l / 16) + e      B[k][j]: k = 4 (l / 16) + e, j = l % 16
-//   D[i][j]: i = 4 (l / 16) + e, j = l % 16
-// K is ordered (tap, channel) with 4 consecutive channels per lane, so every
-// operand fetch is one 8-byte load of 4 bf16 (channel counts are multiples of 4).
+// Forward and backward-data: each 64-lane wave owns one 16-row slab of the
+// GEMM (a block of four waves 64 rows) and issues gfx950's
+// v_mfma_f32_16x16x32_bf16 over 32-wide K steps.  Operand layout of that
+// instruction (lane l, element e):
+//   A[i][k]: i = l % 16, k = 8 (l / 16) + e (e < 8)   B[k][j]: k = 8 (l / 16) + e, j = l % 16
+//   D[i][j]: i = 4 (l / 16) + e (e < 4), j = l % 16
+// K is ordered (tap, channel); a lane's 8 K elements are two groups of 4
+// consecutive channels (channel counts are multiples of 4), each one 8-byte
+// load of 4 bf16 (or 16 bytes of fp32 for the backward-data operand).  The
+// weight operand of 128 K columns for every output column of the block is
+// staged in LDS once per block and read by all four waves (rows padded by 8
+// bf16 so that the 16 rows a wave reads fall in different banks).
+// Backward-weight uses the same instruction with K = output voxels (8
+// consecutive voxels per lane).
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -72,6 +79,44 @@ __device__ __forceinline__ s4v load_x4(const ConvGeom& g, const unsigned short* 
     return ld4bf(xb + v * g.Cb + (c - g.Ca));
 }
 
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+
+// eight bf16 (bit patterns in shorts) as the MFMA operand type
+__device__ __forceinline__ bf8v cat8(s4v lo, s4v hi)
+{
+    const s8v r = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(bf8v, r);
+}
+
+constexpr int CONV_KC = 128;            // K columns of the weight tile staged per round
+constexpr int CONV_KCP = CONV_KC + 8;   // LDS row pitch (bf16)
+
+// Stage rows [0, 16 NT) x columns [k0, k0 + KC) of a row-major bf16 weight
+// matrix wsrc [rows][K] into LDS (zeros outside rows < nrows, k < K).  Rows
+// start 8-byte aligned (K is a multiple of 4), so each thread moves 4 bf16
+// per load.
+template <int NT>
+__device__ __forceinline__ void stage_weights(unsigned short* __restrict__ ws, const unsigned short* __restrict__ wsrc,
+                                              int nrows, int K, int k0)
+{
+    constexpr int Q = NT * 16 * (CONV_KC / 4);  // 4-element groups
+    for (int q = threadIdx.x; q < Q; q += 256) {
+        const int r = q / (CONV_KC / 4), c = (q - r * (CONV_KC / 4)) * 4;
+        uint2 v = make_uint2(0u, 0u);
+        if (r < nrows && k0 + c < K) v = *reinterpret_cast<const uint2*>(wsrc + (size_t)r * K + k0 + c);
+        *reinterpret_cast<uint2*>(ws + r * CONV_KCP + c) = v;
+    }
+}
+
+// B operand of one K step from the staged tile: column j of tile jt, K rows
+// kk + 8 (l / 16) .. + 8
+__device__ __forceinline__ bf8v b_from_lds(const unsigned short* __restrict__ ws, int jt, int lane, int kk)
+{
+    const uint4 v = *reinterpret_cast<const uint4*>(ws + (jt * 16 + (lane & 15)) * CONV_KCP + kk + (lane >> 4) * 8);
+    return __builtin_bit_cast(bf8v, v);
+}
+
 // ---------------------------------------------------------------- forward --
 template <int NT>
 __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
@@ -80,6 +125,7 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
                                                        const float* __restrict__ bias, int act, float slope,
                                                        unsigned short* __restrict__ ybf, float* __restrict__ yf)
 {
+    __shared__ __attribute__((aligned(16))) unsigned short ws[NT * 16 * CONV_KCP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int Cin = g.Ca + g.Cb;
     const int K = 27 * Cin;
@@ -94,12 +140,7 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
         yo = (int)(q % g.Ho); q /= g.Ho;
         zo = (int)(q % g.Do); n = (int)(q / g.Do);
     }
-    const int kg = (lane >> 4) * 4;
-    f4v acc[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        const int k = k0 + kg;
+    auto load_a4 = [&](int k) {  // channels k..k+3 of (tap, channel) index k
         s4v a = s4v{0, 0, 0, 0};
         if (mvalid && k < K) {
             const int t = k / Cin, c = k - t * Cin;
@@ -108,12 +149,23 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
             if ((unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi && (unsigned)xi < (unsigned)g.Wi)
                 a = load_x4(g, xa, xb, n, zi, yi, xi, c);
         }
+        return a;
+    };
+    const int kg = (lane >> 4) * 8;
+    f4v acc[NT];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int co = j * 16 + (lane & 15);
-            s4v b = s4v{0, 0, 0, 0};
-            if (co < g.Cout && k < K) b = ld4bf(w + (size_t)co * K + k);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+    for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += CONV_KC) {
+        __syncthreads();
+        stage_weights<NT>(ws, w, g.Cout, K, k0);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < CONV_KC; kk += 32) {
+            const int k = k0 + kk + kg;
+            const bf8v a = cat8(load_a4(k), load_a4(k + 4));
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b_from_lds(ws, j, lane, kk), acc[j], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -141,6 +193,7 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
                                                             const unsigned short* __restrict__ wt,
                                                             float* __restrict__ dx, int accumulate)
 {
+    __shared__ __attribute__((aligned(16))) unsigned short ws[NT * 16 * CONV_KCP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int Cin = g.Ca + g.Cb;
     const int K = 27 * g.Cout;
@@ -155,12 +208,7 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
         yi = (int)(q % g.Hi); q /= g.Hi;
         zi = (int)(q % g.Di); n = (int)(q / g.Di);
     }
-    const int kg = (lane >> 4) * 4;
-    f4v acc[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        const int k = k0 + kg;
+    auto load_p4 = [&](int k) {  // P = dL/dy * act'(y) at output channels k..k+3 of (tap, channel) index k
         s4v a = s4v{0, 0, 0, 0};
         if (mvalid && k < K) {
             const int t = k / g.Cout, co = k - t * g.Cout;
@@ -183,12 +231,23 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
                 a = pack4(d4.x * s0, d4.y * s1, d4.z * s2, d4.w * s3);
             }
         }
+        return a;
+    };
+    const int kg = (lane >> 4) * 8;
+    f4v acc[NT];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const int ci = j * 16 + (lane & 15);
-            s4v b = s4v{0, 0, 0, 0};
-            if (ci < Cin && k < K) b = ld4bf(wt + (size_t)ci * K + k);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+    for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += CONV_KC) {
+        __syncthreads();
+        stage_weights<NT>(ws, wt, Cin, K, k0);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < CONV_KC; kk += 32) {
+            const int k = k0 + kk + kg;
+            const bf8v a = cat8(load_p4(k), load_p4(k + 4));
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b_from_lds(ws, j, lane, kk), acc[j], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -208,7 +267,9 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
 // --------------------------------------------------------- backward weight --
 // Block (chunk, tap t): partial dW[co][t][ci] over output voxels
 // [chunk*VC, chunk*VC + VC), written to part[chunk][co][t][ci].  Wave w owns
-// the ci-tiles w, w+4, ... and all co-tiles.
+// the ci-tiles w, w+4, ... and all co-tiles.  GEMM rows co, columns ci, K =
+// output voxels: each lane takes 8 consecutive output voxels per 32-wide K
+// step of v_mfma_f32_16x16x32_bf16.
 template <int TM, int TNW>
 __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
                                                               const unsigned short* __restrict__ xb,
@@ -229,14 +290,14 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const 
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TNW; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
-    const int kg = (lane >> 4) * 4;
-    for (long long o0 = ob; o0 < oe; o0 += 16) {
-        // this lane's 4 output voxels o0 + kg + e and their shifted input voxels
-        long long iv[4];
-        bool ov[4], iok[4];
-        size_t ooff[4];
+    const int kg = (lane >> 4) * 8;
+    for (long long o0 = ob; o0 < oe; o0 += 32) {
+        // this lane's 8 output voxels o0 + kg + e and their shifted input voxels
+        long long iv[8];
+        bool ov[8], iok[8];
+        size_t ooff[8];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < 8; ++e) {
             const long long o = o0 + kg + e;
             ov[e] = o < oe;
             iok[e] = false;
@@ -255,29 +316,29 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const 
             }
         }
         // A operands: P[o][co] for the co-tiles
-        s4v a[TM];
+        bf8v a[TM];
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
             const int co = i * 16 + (lane & 15);
-            float pv[4];
+            float pv[8];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int e = 0; e < 8; ++e) {
                 pv[e] = 0.f;
                 if (ov[e] && co < g.Cout) {
                     pv[e] = dy[ooff[e] + co];
                     if (y) pv[e] *= lrelu_d(y[ooff[e] + co], slope);
                 }
             }
-            a[i] = pack4(pv[0], pv[1], pv[2], pv[3]);
+            a[i] = cat8(pack4(pv[0], pv[1], pv[2], pv[3]), pack4(pv[4], pv[5], pv[6], pv[7]));
         }
 #pragma unroll
         for (int jj = 0; jj < TNW; ++jj) {
             const int jt = wave + 4 * jj;
             if (jt >= TN) break;
             const int ci = jt * 16 + (lane & 15);
-            s4v b;
+            s8v bs;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int e = 0; e < 8; ++e) {
                 unsigned short h = 0;
                 if (iok[e] && ci < Cin) {
                     const long long v = iv[e];
@@ -298,10 +359,11 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const 
                         h = xb[(size_t)v * g.Cb + (ci - g.Ca)];
                     }
                 }
-                b[e] = (short)h;
+                bs[e] = (short)h;
             }
+            const bf8v b = __builtin_bit_cast(bf8v, bs);
 #pragma unroll
-            for (int i = 0; i < TM; ++i) acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b, acc[i][jj], 0, 0, 0);
+            for (int i = 0; i < TM; ++i) acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][jj], 0, 0, 0);
         }
     }
     // D[i = co][j = ci]: lane holds co = 16 i_t + 4 (l/16) + e, ci = 16 jt + l % 16
@@ -318,6 +380,122 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const 
                 const int co = i * 16 + (lane >> 4) * 4 + e;
                 if (co < g.Cout && ci < Cin) P[((size_t)co * 27 + t) * Cin + ci] = acc[i][jj][e];
             }
+    }
+}
+
+// Backward-weight for layers with few channels (TM * TN <= 3 tiles: the
+// full-resolution layers): a block takes a chunk of output voxels for all 27
+// taps, and wave w accumulates taps w, w + 4, ... (7 or 6 of them), so P =
+// dL/dy act'(y) of a K step is loaded once per wave for all of its taps
+// (the tap-per-block kernel reads it once per tap, which dominates when the
+// channel counts are small).  part[chunk][co][t][ci] as conv_bwd_weight_kernel.
+template <int TM, int TN>
+__global__ void __launch_bounds__(256) conv_bwd_weight_taps_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
+                                                                   const unsigned short* __restrict__ xb,
+                                                                   const float* __restrict__ dy,
+                                                                   const unsigned short* __restrict__ y, float slope,
+                                                                   long long VC, float* __restrict__ part)
+{
+    constexpr int QT = 7;  // taps per wave: 27 = 4 * 7 - 1
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Cin = g.Ca + g.Cb;
+    const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
+    const long long ob = (long long)blockIdx.x * VC;
+    const long long oe = min(M, ob + VC);
+    const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
+    f4v acc[QT][TM][TN];
+#pragma unroll
+    for (int q = 0; q < QT; ++q)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[q][i][j] = f4v{0.f, 0.f, 0.f, 0.f};
+    const int kg = (lane >> 4) * 8;
+    for (long long o0 = ob; o0 < oe; o0 += 32) {
+        // the lane's 8 output voxels o0 + kg + e: batch index and the input
+        // corner (tap 0, 0, 0) of each
+        int vn[8], vz[8], vy[8], vx[8];
+        bool ov[8];
+        size_t ooff[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const long long o = o0 + kg + e;
+            ov[e] = o < oe;
+            long long q = ov[e] ? o : 0;
+            const int xo = (int)(q % g.Wo); q /= g.Wo;
+            const int yo = (int)(q % g.Ho); q /= g.Ho;
+            const int zo = (int)(q % g.Do);
+            vn[e] = (int)(q / g.Do);
+            vz[e] = zo * g.stride - 1; vy[e] = yo * g.stride - 1; vx[e] = xo * g.stride - 1;
+            ooff[e] = (size_t)(ov[e] ? o : 0) * g.Cout;
+        }
+        bf8v a[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int co = i * 16 + (lane & 15);
+            float pv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                pv[e] = 0.f;
+                if (ov[e] && co < g.Cout) {
+                    pv[e] = dy[ooff[e] + co];
+                    if (y) pv[e] *= lrelu_d(y[ooff[e] + co], slope);
+                }
+            }
+            a[i] = cat8(pack4(pv[0], pv[1], pv[2], pv[3]), pack4(pv[4], pv[5], pv[6], pv[7]));
+        }
+#pragma unroll
+        for (int q = 0; q < QT; ++q) {
+            const int t = wave + 4 * q;
+            if (t >= 27) break;
+            const int dz = t / 9, dyy = (t / 3) % 3, dx_ = t % 3;
+            bf8v b[TN];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int ci = j * 16 + (lane & 15);
+                s8v bs;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int zi = vz[e] + dz, yi = vy[e] + dyy, xi = vx[e] + dx_;
+                    unsigned short h = 0;
+                    if (ov[e] && ci < Cin && (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi &&
+                        (unsigned)xi < (unsigned)g.Wi) {
+                        if (ci < g.Ca) {
+                            const size_t va = g.ups ? (((size_t)vn[e] * Da + (zi >> 1)) * Ha + (yi >> 1)) * Wa + (xi >> 1)
+                                                    : (((size_t)vn[e] * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                            h = xa[va * g.Ca + ci];
+                        } else {
+                            const size_t vb = (((size_t)vn[e] * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                            h = xb[vb * g.Cb + (ci - g.Ca)];
+                        }
+                    }
+                    bs[e] = (short)h;
+                }
+                b[j] = __builtin_bit_cast(bf8v, bs);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[q][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[q][i][j], 0, 0, 0);
+        }
+    }
+    float* P = part + (size_t)blockIdx.x * g.Cout * 27 * Cin;
+#pragma unroll
+    for (int q = 0; q < QT; ++q) {
+        const int t = wave + 4 * q;
+        if (t >= 27) break;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int ci = j * 16 + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int co = i * 16 + (lane >> 4) * 4 + e;
+                    if (co < g.Cout && ci < Cin) P[((size_t)co * 27 + t) * Cin + ci] = acc[q][i][j][e];
+                }
+        }
     }
 }
 
@@ -515,12 +693,21 @@ hipError_t conv_bwd_data_launch(const ConvGeom& g, const float* dy, const unsign
     return hipGetLastError();
 }
 
+// The all-taps kernel for layers with at most 3 tiles of 16 x 16 (co, ci).
+static bool wgrad_all_taps(const ConvGeom& g)
+{
+    const int tm = (g.Cout + 15) / 16, tn = (g.Ca + g.Cb + 15) / 16;
+    return tm * tn <= 3;
+}
+
 ConvWgradPlan conv_wgrad_plan(const ConvGeom& g)
 {
     ConvWgradPlan p;
     const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
-    long long vc = (M + 255) / 256;
-    vc = ((vc + 15) / 16) * 16;
+    // all-taps kernel: about 1024 chunks (each block covers every tap);
+    // tap-per-block kernel: about 256 chunks x 27 taps
+    long long vc = (M + (wgrad_all_taps(g) ? 1023 : 255)) / (wgrad_all_taps(g) ? 1024 : 256);
+    vc = ((vc + 31) / 32) * 32;
     if (vc < 256) vc = 256;
     p.VC = vc;
     p.nchunks = (int)((M + vc - 1) / vc);
@@ -547,12 +734,21 @@ hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, c
     const int Cin = g.Ca + g.Cb;
     const int tm = (g.Cout + 15) / 16, tn = (Cin + 15) / 16, tnw = (tn + 3) / 4;
     if (tnw > 3 || tm > 8) return hipErrorInvalidValue;
-    dim3 grid(p.nchunks, 27);
-    switch (tm) {
-        case 1: launch_wg_tm<1>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
-        case 2: launch_wg_tm<2>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
-        case 3: case 4: launch_wg_tm<4>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
-        default: launch_wg_tm<8>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
+    if (wgrad_all_taps(g)) {
+        dim3 grid1(p.nchunks);
+        if (tm == 1 && tn == 1) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 1>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
+        else if (tm == 1 && tn == 2) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 2>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
+        else if (tm == 1) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 3>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
+        else if (tm == 2) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<2, 1>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
+        else hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<3, 1>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
+    } else {
+        dim3 grid(p.nchunks, 27);
+        switch (tm) {
+            case 1: launch_wg_tm<1>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
+            case 2: launch_wg_tm<2>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
+            case 3: case 4: launch_wg_tm<4>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
+            default: launch_wg_tm<8>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
