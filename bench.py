@@ -228,6 +228,121 @@ def other_workload(wl, reps: int = 10):
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wl.name)}
 
 
+WEIGHTS_C4 = os.path.join(ROOT, "paper_2509_25044_amd", "weights", "unet_c4.safetensors")
+
+
+def time_to_target_c4(pairs: int = 2, first_pair: int = 2000):
+    """The metric's second half on the clinical shape (160x192x224, textured
+    pairs of the warm-start recipe, held out from the network's training
+    seeds): the plain method (3-level pyramid 0.25/0.5/1.0, 200 LNCC w = 7
+    Adam iterations per level, the paper's smoothing) runs from u = 0 and its
+    final loss is the target; the warm-started method runs the trained U-Net
+    (forward pass timed) and Adam at full resolution until the loss reaches
+    the target; the same full-resolution schedule from u = 0 is the control.
+    Wall-clock seconds with device synchronisation."""
+    if not os.path.exists(WEIGHTS_C4):
+        return None
+    from paper_2509_25044_amd import warmstart
+    from paper_2509_25044_amd.register import RegConfig
+    from paper_2509_25044_amd.unet import UNet3D
+    dev = torch.device("cuda:0")
+    model = UNet3D(dev, seed=0)
+    model.load_weights(WEIGHTS_C4)
+    spec = synth.PairSpec((160, 192, 224), (4.0, 12.0), 3.0, texture_std=0.05)
+    plain = RegConfig(loss="lncc", window=7, levels=(0.25, 0.5, 1.0), iters=(200,), lr=0.1, sigma_grad=1.0,
+                      sigma_warp=0.5)
+    table = {"fine": ((1.0,), (600,))}
+    res = []
+    for k in range(pairs):
+        p = synth.make_pair(spec, seed=synth.BASE_SEED + first_pair + k, device=dev)
+        if k == 0:  # first use of each kernel and of torch's allocator is not timed
+            warmstart.time_to_target(model, p["F"], p["M"], plain, table=table, controls=True)
+        r = warmstart.time_to_target(model, p["F"], p["M"], plain, table=table, controls=True)
+        res.append({"pair": synth.BASE_SEED + first_pair + k, "target_loss": round(r["target_loss"], 6),
+                    "plain_s": round(r["plain_seconds"], 4), "plain_iters": r["plain_iters"],
+                    "warm_s": round(r["warm"]["fine"]["seconds"], 4), "warm_iters": r["warm"]["fine"]["iters"],
+                    "warm_reached": bool(r["warm"]["fine"]["reached"]),
+                    "zero_s": round(r["zero"]["fine"]["seconds"], 4), "zero_iters": r["zero"]["fine"]["iters"],
+                    "zero_reached": bool(r["zero"]["fine"]["reached"])})
+    ok = [x for x in res if x["warm_reached"]]
+    return {"workload": "c4 clinical 160x192x224, LNCC w=7, U-Net warm start", "pairs": res,
+            "speedup_vs_plain": round(sum(x["plain_s"] for x in ok) / sum(x["warm_s"] for x in ok), 3) if ok else None,
+            "weights": os.path.relpath(WEIGHTS_C4, ROOT)}
+
+
+def unet_step_timing(steps: int = 3, batch: int = 4, shape=(160, 192, 224)):
+    """Per-layer times of U-Net training steps (forward, backward-data and
+    backward-weight convolutions) on a batch of the clinical-shape input,
+    from HIP events around each convolution call on the current stream, with
+    the MFMA work of each call (2 x output voxels x 27 x Cin x Cout flop;
+    the same for the two backward products) against the 2.5 PFLOP/s dense
+    bf16 peak."""
+    from paper_2509_25044_amd import unet
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    spec = synth.PairSpec(tuple(shape), (4.0, 12.0), 3.0, texture_std=0.05)
+    Fs, Ms, Ts = [], [], []
+    for i in range(batch):
+        p = synth.make_pair(spec, seed=synth.BASE_SEED + i, device=dev)
+        Fs.append(p["F"]); Ms.append(p["M"]); Ts.append((-p["d"]).contiguous())
+    F, M, T = torch.stack(Fs), torch.stack(Ms), torch.stack(Ts)
+    model = unet.UNet3D(dev, seed=0)
+    rec = []
+    orig = {k: getattr(ops, k) for k in ("conv3d_fwd", "conv3d_bwd_data", "conv3d_bwd_weight")}
+
+    def wrap(kind):
+        fn = orig[kind]
+
+        def timed(*a, **kw):
+            g = a[4] if kind == "conv3d_fwd" else (a[3] if kind == "conv3d_bwd_data" else a[4])
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out = fn(*a, **kw)
+            e1.record(stream)
+            rec.append((kind, g, e0, e1))
+            return out
+        return timed
+    model.train_step(F, M, T, lr=1e-4)  # warm-up
+    torch.cuda.synchronize()
+    for k in orig:
+        setattr(ops, k, wrap(k))
+    try:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            model.train_step(F, M, T, lr=1e-4)
+        e1.record(stream)
+        torch.cuda.synchronize()
+    finally:
+        for k, fn in orig.items():
+            setattr(ops, k, fn)
+    step_ms = e0.elapsed_time(e1) / steps
+    per = {}
+    conv_ms = 0.0
+    for kind, g, a0, a1 in rec:
+        cin = g.Ca + g.Cb
+        Do, Ho, Wo = ops.conv_out_shape(g)
+        flop = 2.0 * g.N * Do * Ho * Wo * 27 * cin * g.Cout
+        key = f"{kind.replace('conv3d_', '')} {cin}->{g.Cout} s{g.stride}{' up' if g.ups else ''} {Do}x{Ho}x{Wo}"
+        d = per.setdefault(key, {"ms": 0.0, "flop": flop, "calls": 0})
+        ms = a0.elapsed_time(a1)
+        d["ms"] += ms
+        d["calls"] += 1
+        conv_ms += ms
+    layers = {k: {"ms": round(v["ms"] / v["calls"], 4),
+                  "tflops": round(v["flop"] / (v["ms"] / v["calls"] * 1e-3) / 1e12, 2),
+                  "frac_of_bf16_peak": round(v["flop"] / (v["ms"] / v["calls"] * 1e-3) / 2.5e15, 4)}
+              for k, v in per.items()}
+    total_flop = sum(v["flop"] * v["calls"] for v in per.values()) / steps
+    return {"metric": "U-Net training step (batch 4, 2x160x192x224 input)", "value": round(step_ms, 3), "unit": "ms",
+            "steps": steps, "higher_is_better": False, "conv_ms_per_step": round(conv_ms / steps, 3),
+            "conv_tflops": round(total_flop / (conv_ms / steps * 1e-3) / 1e12, 2),
+            "conv_frac_of_bf16_peak": round(total_flop / (conv_ms / steps * 1e-3) / 2.5e15, 4),
+            "conv_flop_per_step": total_flop, "layers": layers}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +355,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the timings of the kernels outside the step (smoothing, approximate MI, "
                          "composite sampler)")
+    ap.add_argument("--no-time-to-target", action="store_true",
+                    help="skip the warm-start time-to-target measurement (the metric's second half)")
+    ap.add_argument("--unet", action="store_true",
+                    help="only time U-Net training steps at the clinical shape, per convolution layer")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -252,6 +371,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.unet:
+        print(json.dumps(unet_step_timing(steps=args.steps if args.steps < 30 else 3)), flush=True)
         return
     wl = ALL.get(args.workload) or next(w for w in ALL.values() if w.name.startswith(args.workload))
     dev = torch.device("cuda:0")
@@ -357,6 +479,10 @@ def main():
     out["extras"] = None if args.no_extras else extras(F, M, u_m, g_m, roi, nroi, wl)
     if out["extras"] is not None and wl.name != C3.name:
         out["extras"]["c3_512cube"] = other_workload(C3)
+    if not args.no_time_to_target:
+        del F, M, u_l, u_m, g_l, g_m, m_l, v_l, m_m, v_m  # the registrations below need little memory
+        torch.cuda.empty_cache()
+        out["time_to_target"] = time_to_target_c4()
     if not args.no_cpu_baseline:
         if args.cpu_slab < 0:
             slab = F.shape[0] if F.shape[0] < 600 else 64 + 4 * ((wl.lncc_window - 1) // 2)

@@ -1,6 +1,9 @@
 """GPU: the U-Net built on the library's conv kernels trains (overfits a fixed
-batch), its backward agrees with a finite difference of its own forward, and a
-small trained network gives registration a head start over zero init."""
+batch), its backward predicts finite differences of its own forward, and the
+committed trained network reaches the plain method's final LNCC sooner than
+the method without it."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -60,25 +63,65 @@ def test_weight_gradient_direction():
     assert lm < l0 < lp, (lm, l0, lp)
 
 
-def test_trained_network_gives_a_head_start():
-    """Train briefly on 32^3 pairs; on held-out pairs the prediction is closer
-    to the true inverse field than zero (the gain over starting from u = 0);
-    the time-to-target of warm-started versus plain registration is printed."""
-    print("[unet warm start small]", flush=True)
-    spec = synth.PairSpec((32, 32, 32), (3.0, 6.0), 2.0)
-    model = UNet3D(DEV, seed=3)
-    train(model, spec, pairs=800, batch=4, lr=1e-3, converged_every=0, log_every=50)
-    gains, res = [], []
+def test_network_gradient_predicts_finite_differences():
+    """Network-level check of the backward (all 8 layers, bf16 operands): for
+    perturbations of every weight along the computed gradient, rounded to the
+    bf16 values the forward actually uses (w+ and w-), the change of the MSE
+    loss L(w+) - L(w-) agrees with g . (w+ - w-) within 15%."""
+    print("[unet finite differences]", flush=True)
+    model = UNet3D(DEV, seed=4)
+    F, M, T = _batch(2, (16, 16, 16), 210)
+    pred, acts = model.forward(F, M)
+    _, dpred = ops.mse_disp(pred, T)
+    g = model.backward(dpred, acts).clone().double()
+    bf = lambda t: t.to(torch.bfloat16).to(torch.float32)
+    w0 = bf(model.master.clone())
+    d = (g / g.norm()).float()
+    for rel in (0.02, 0.05):
+        h = rel * float(w0.abs().max())
+        wp, wm = bf(w0 + h * d), bf(w0 - h * d)
+        losses = []
+        for w in (wp, wm):
+            model.master.copy_(w)
+            model.refresh_bf16()
+            losses.append(float(ops.mse_disp(model.forward(F, M)[0], T)[0]))
+        predicted = float((g * (wp - wm).double()).sum())
+        print("step", rel, "dL", losses[0] - losses[1], "g.dw", predicted, flush=True)
+        assert predicted > 0
+        assert abs((losses[0] - losses[1]) - predicted) <= 0.15 * abs(predicted), (rel, losses, predicted)
+
+
+WEIGHTS_C4 = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2509_25044_amd",
+                          "weights", "unet_c4.safetensors")
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS_C4), reason="no trained warm-start weights in the tree")
+def test_committed_network_reaches_the_plain_target_sooner():
+    """The network trained with the library's own conv, MSE and Adam kernels
+    (2500 steps of batch 4 on 10,000 seeded clinical-shape pairs; the
+    commands are in the design notes), on three held-out 160x192x224 pairs:
+    the plain method (3-level pyramid, 200 LNCC w = 7 iterations per level,
+    the paper's smoothing) sets the target loss; Adam at full resolution from
+    the network's prediction reaches it in fewer iterations than the same
+    schedule from u = 0 (which may not reach it at all within 600), and the
+    warm-started run, forward pass included, takes fewer wall-clock seconds
+    than the plain pyramid."""
+    print("[unet warm start, committed weights]", flush=True)
+    model = UNet3D(DEV, seed=0)
+    model.load_weights(WEIGHTS_C4)
+    spec = synth.PairSpec((160, 192, 224), (4.0, 12.0), 3.0, texture_std=0.05)
+    plain = RegConfig(loss="lncc", window=7, levels=(0.25, 0.5, 1.0), iters=(200,), lr=0.1, sigma_grad=1.0,
+                      sigma_warp=0.5)
+    table = {"fine": ((1.0,), (600,))}
     for k in range(3):
-        p = synth.make_pair(spec, seed=9000 + k, device=DEV)
-        tgt = inverse_target(p["d"])
-        u0 = model.predict(p["F"], p["M"])
-        e_net = float(torch.sqrt(((u0 - tgt) ** 2).mean()))
-        e_zero = float(torch.sqrt((tgt ** 2).mean()))
-        gains.append(e_zero - e_net)
-        r = time_to_target(model, p["F"], p["M"], RegConfig(loss="lncc", window=5, levels=(0.5, 1.0), iters=(60,),
-                                                             lr=0.1))
-        print(k, e_net, e_zero, r, flush=True)
-        res.append(r)
-    assert sum(gains) > 0, gains
-    assert all(np.isfinite(r["warm_u0_loss"]) for r in res)
+        p = synth.make_pair(spec, seed=synth.BASE_SEED + 2000 + k, device=DEV)
+        if k == 0:  # first use of the kernels and the allocator, untimed
+            time_to_target(model, p["F"], p["M"], plain, table=table, controls=True, check_every=1)
+        r = time_to_target(model, p["F"], p["M"], plain, table=table, controls=True, check_every=1)
+        w, z = r["warm"]["fine"], r["zero"]["fine"]
+        print(k, "plain", r["plain_iters"], "it", round(r["plain_seconds"], 4), "s | warm", w["iters"], "it",
+              round(w["seconds"], 4), "s", w["reached"], "| zero", z["iters"], "it", round(z["seconds"], 4), "s",
+              z["reached"], flush=True)
+        assert w["reached"], (k, r)
+        assert (not z["reached"]) or w["iters"] < z["iters"], (k, w, z)
+        assert w["seconds"] < r["plain_seconds"], (k, w["seconds"], r["plain_seconds"])
