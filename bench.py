@@ -198,9 +198,11 @@ def extras(F, M, u, scratch, roi, nroi, wl, reps: int = 5):
     return res
 
 
-def other_workload(wl, reps: int = 10):
+def other_workload(wl, reps: int = 10, windows=(3, 7, 9, 11, 13, 15)):
     """The fused LNCC fwd+bwd call on another workload's pair (u = -d), timed
-    like the step's call: mean over reps of HIP events on the call's stream."""
+    like the step's call: mean over reps of HIP events on the call's stream;
+    then the same call at the other window sizes (w <= 9 the fused kernel,
+    w >= 11 the separable FP64 passes)."""
     dev = torch.device("cuda:0")
     pair = synth.make_pair(wl.pair, seed=synth.BASE_SEED, device=dev)
     F, M, u = pair["F"], pair["M"], (-pair["d"]).contiguous()
@@ -224,8 +226,22 @@ def other_workload(wl, reps: int = 10):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     ach = LNCC_BYTES_PER_VOXEL * nroi / (ms * 1e-3) / 1e9
-    return {"workload": wl.name, "lncc_fwd_bwd_ms": round(ms, 4), "gvoxel_per_s": round(nroi / (ms * 1e-3) / 1e9, 3),
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wl.name)}
+    out = {"workload": wl.name, "lncc_fwd_bwd_ms": round(ms, 4), "gvoxel_per_s": round(nroi / (ms * 1e-3) / 1e9, 3),
+           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(wl.name)}
+    by_window = {}
+    for w in windows:
+        wsw = torch.empty(ops.lncc_workspace_bytes(F.shape, roi, w), dtype=torch.uint8, device=dev)
+        ops.warp_lncc_bwd(F, M, u, window=w, eps=wl.lncc_eps, roi=roi, grad_u=g, loss=loss, ws=wsw)
+        e0.record(stream)
+        for _ in range(reps):
+            ops.warp_lncc_bwd(F, M, u, window=w, eps=wl.lncc_eps, roi=roi, grad_u=g, loss=loss, ws=wsw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        msw = e0.elapsed_time(e1) / reps
+        by_window[str(w)] = {"ms": round(msw, 4), "gvoxel_per_s": round(nroi / (msw * 1e-3) / 1e9, 3)}
+        del wsw
+    out["lncc_fwd_bwd_by_window"] = by_window
+    return out
 
 
 WEIGHTS_C4 = os.path.join(ROOT, "paper_2509_25044_amd", "weights", "unet_c4.safetensors")

@@ -75,8 +75,11 @@ typedef struct ffdp_grid {
  * wait (the default). */
 
 /* LNCC settings (App. "Definition of LNCC loss", Alg. fusedlncc):
- *  window       odd box edge w in {3, 5, 7, 9}; the filter is the uniform
- *               w^3 box with weights 1/w^3, zero padding at the array border.
+ *  window       odd box edge w in [3, 15]; the filter is the uniform w^3 box
+ *               with weights 1/w^3, zero padding at the array border.
+ *               w <= 9 runs one fused kernel per call; w = 11, 13, 15 run
+ *               separable passes through an FP64 workspace of 64 bytes per
+ *               voxel (the fused kernel's register rings do not fit there).
  *  eps          the stabiliser in n_i = A_i^2 / (B_i C_i + eps); >= 0.
  *  ants_approx  1: skip the window sum of the adjoint (App. "ANTs gradient
  *               approximation"); 0: exact gradient.
@@ -120,8 +123,10 @@ const char* ffdp_status_string(int status);
 const char* ffdp_last_error(void);
 
 /* Workspace bytes for the LNCC / MI calls on this geometry (0 never occurs):
- * LNCC 8 per thread block of the launch plus 16 (checked-mode flag); MI
- * 8 * (B^2 + 2).  With p NULL or invalid: enough for any valid p. */
+ * LNCC w <= 9: 8 per thread block of the launch plus 16 (checked-mode flag);
+ * LNCC w >= 11: 64 per voxel (FP64 window sums and adjoint fields) plus 8
+ * per block of its column passes plus 16; MI 8 * (B^2 + 2).  With p NULL or
+ * invalid: enough for any valid p (the wide-window size for LNCC). */
 size_t ffdp_lncc_workspace_bytes(const ffdp_grid* g, const ffdp_lncc_params* p);
 size_t ffdp_mi_workspace_bytes(const ffdp_grid* g, const ffdp_mi_params* p);
 /* Number of floats in the caller-owned MI state: 2*B*B + 2*B + 16. */
@@ -164,9 +169,11 @@ int ffdp_warp_lncc_bwd(const float* F, const float* M, const float* u, const ffd
  * allocation): ffdp_warp_lncc_bwd with its block partials in a library-owned
  * device array of FFDP_NOALLOC_MAX_BLOCKS doubles (512 KB, one per GPU, held
  * until the process ends) instead of a caller workspace.  Same arguments and
- * results otherwise (bitwise the same outputs; checked mode included).  Grids
- * whose launch needs more than FFDP_NOALLOC_MAX_BLOCKS partials are rejected
- * with FFDP_ERR_WORKSPACE before anything runs.  All calls on one
+ * results otherwise (bitwise the same outputs; checked mode included).  Calls
+ * whose workspace (ffdp_lncc_workspace_bytes) exceeds the array are rejected
+ * with FFDP_ERR_WORKSPACE before anything runs: grids needing more than
+ * FFDP_NOALLOC_MAX_BLOCKS block partials, and wide windows (w >= 11) beyond
+ * about 8,000 voxels.  All calls on one
  * GPU share its array: calls that overlap in time on one GPU (different
  * streams or threads) race and must be serialised by the caller.  The array
  * belongs to the device that runs `stream`. */

@@ -20,7 +20,7 @@ OUT = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libffdp.so")
 ARCH = "gfx950"
 
-SOURCES = ["lncc.hip", "mi.hip", "elementwise.hip", "smooth.hip", "conv3d.hip", "api.cpp"]
+SOURCES = ["lncc.hip", "lncc_wide.hip", "mi.hip", "elementwise.hip", "smooth.hip", "conv3d.hip", "api.cpp"]
 
 # Packed fp32 instructions are switched off (ordinary float code only).
 HIPFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",

@@ -11,6 +11,7 @@
 #include "../../include/ffdp.h"
 #include "adam.hpp"
 #include "internal.hpp"
+#include "wide.hpp"
 
 using namespace ffdp;
 
@@ -63,8 +64,8 @@ int check_grid(const ffdp_grid* g)
 int check_lncc(const ffdp_lncc_params* p)
 {
     if (!p) return fail(FFDP_ERR_NULL, "lncc params are NULL");
-    if (p->window != 3 && p->window != 5 && p->window != 7 && p->window != 9)
-        return fail(FFDP_ERR_PARAM, "window must be 3, 5, 7 or 9 (got %d)", p->window);
+    if (p->window < 3 || p->window > LNCC_MAX_WINDOW || !(p->window & 1))
+        return fail(FFDP_ERR_PARAM, "window must be odd in [3, %d] (got %d)", LNCC_MAX_WINDOW, p->window);
     if (!(p->eps >= 0.0f) || isinf(p->eps)) return fail(FFDP_ERR_PARAM, "eps must be finite and >= 0");
     if (p->ants_approx != 0 && p->ants_approx != 1) return fail(FFDP_ERR_PARAM, "ants_approx must be 0 or 1");
     if (p->pad_mode != FFDP_PAD_BORDER && p->pad_mode != FFDP_PAD_ZEROS)
@@ -161,10 +162,12 @@ void fill_roi(const ffdp_grid* g, int roi[6])
     roi[4] = (int)g->roi_lo[2]; roi[5] = (int)g->roi_hi[2];
 }
 
-// one double per thread block of the largest plan over the modes of the
-// window, then 16 bytes for the checked-mode flag
+// fused windows: one double per thread block of the largest plan over the
+// modes of the window; wide windows: the FP64 fields and block partials of
+// the separable passes; then 16 bytes for the checked-mode flag
 size_t lncc_ws(const ffdp_grid* g, int window)
 {
+    if (window > LNCC_FUSED_MAX_WINDOW) return wide_ws_bytes((int)g->D, (int)g->H, (int)g->W) + 16;
     return (size_t)lncc_max_blocks((int)g->D, (int)g->H, (int)g->W, window) * sizeof(double) + 16;
 }
 unsigned* lncc_flag(void* ws, const ffdp_grid* g, int window)
@@ -288,7 +291,7 @@ size_t ffdp_lncc_workspace_bytes(const ffdp_grid* g, const ffdp_lncc_params* p)
     if (!g || check_dims(g->D, g->H, g->W)) return sizeof(double);
     if (p && check_lncc(p) == FFDP_OK) return lncc_ws(g, p->window);
     size_t n = 0;  // no (valid) parameters: enough for every window
-    for (int w = 3; w <= 9; w += 2) n = n > lncc_ws(g, w) ? n : lncc_ws(g, w);
+    for (int w = 3; w <= LNCC_MAX_WINDOW; w += 2) n = n > lncc_ws(g, w) ? n : lncc_ws(g, w);
     return n;
 }
 
@@ -349,7 +352,11 @@ int ffdp_warp_lncc_fwd(const float* F, const float* M, const float* u, const ffd
     hipStream_t st = (hipStream_t)stream;
     unsigned* flag = lncc_flag(ws, g, p->window);
     if (p->check_finite && (s = start_checked(F, M, u, g, nullptr, flag, st))) return s;
-    s = hip_status(lncc_launch(0, p->window, p->pad_mode, L, a, loss, roi_voxels(g), st), "ffdp_warp_lncc_fwd");
+    if (p->window > LNCC_FUSED_MAX_WINDOW)
+        s = hip_status(lncc_wide_launch(0, p->window, p->pad_mode, a, ws, loss, roi_voxels(g), st),
+                       "ffdp_warp_lncc_fwd");
+    else
+        s = hip_status(lncc_launch(0, p->window, p->pad_mode, L, a, loss, roi_voxels(g), st), "ffdp_warp_lncc_fwd");
     return p->check_finite ? finish_checked(s, flag, loss, st) : s;
 }
 
@@ -370,7 +377,12 @@ int ffdp_warp_lncc_bwd(const float* F, const float* M, const float* u, const ffd
     hipStream_t st = (hipStream_t)stream;
     unsigned* flag = lncc_flag(ws, g, p->window);
     if (p->check_finite && (s = start_checked(F, M, u, g, grad_scale, flag, st))) return s;
-    s = hip_status(lncc_launch(mode, p->window, p->pad_mode, L, a, loss, roi_voxels(g), st), "ffdp_warp_lncc_bwd");
+    if (p->window > LNCC_FUSED_MAX_WINDOW)
+        s = hip_status(lncc_wide_launch(mode, p->window, p->pad_mode, a, ws, loss, roi_voxels(g), st),
+                       "ffdp_warp_lncc_bwd");
+    else
+        s = hip_status(lncc_launch(mode, p->window, p->pad_mode, L, a, loss, roi_voxels(g), st),
+                       "ffdp_warp_lncc_bwd");
     return p->check_finite ? finish_checked(s, flag, loss, st) : s;
 }
 
@@ -425,8 +437,9 @@ int ffdp_warp_lncc_bwd_noalloc(const float* F, const float* M, const float* u, c
     if ((s = check_lncc(p))) return s;
     const size_t need = lncc_ws(g, p->window);
     if (need > sizeof(scratch))
-        return fail(FFDP_ERR_WORKSPACE, "this grid needs %zu block partials; the library-owned scratch holds %d",
-                    (need - 16) / sizeof(double), FFDP_NOALLOC_MAX_BLOCKS);
+        return fail(FFDP_ERR_WORKSPACE,
+                    "this grid and window need %zu bytes of workspace; the library-owned scratch holds %zu", need,
+                    sizeof(scratch));
     if ((s = check_ptrs("F,M,grad_u", 3, (const void*)F, (const void*)M, (const void*)grad_u))) return s;
     if ((s = check_opt_ptr(u, "u"))) return s;
     if ((s = check_opt_ptr(grad_scale, "grad_scale"))) return s;

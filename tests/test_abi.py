@@ -78,8 +78,23 @@ def test_workspace_queries_grow_with_blocks_not_voxels(L):
     assert L.ffdp_mi_workspace_bytes(C.byref(_grid()), C.byref(_mp(256))) == (256 * 256 + 2) * 8
     assert L.ffdp_mi_workspace_bytes(C.byref(_grid()), None) == (256 * 256 + 2) * 8  # any valid bins
     # no (valid) parameters: enough for every window
-    n = [L.ffdp_lncc_workspace_bytes(C.byref(_grid(100, 200, 300)), C.byref(_lp(window=w))) for w in (3, 5, 7, 9)]
+    n = [L.ffdp_lncc_workspace_bytes(C.byref(_grid(100, 200, 300)), C.byref(_lp(window=w))) for w in range(3, 16, 2)]
     assert L.ffdp_lncc_workspace_bytes(C.byref(_grid(100, 200, 300)), None) == max(n)
+    assert L.ffdp_lncc_workspace_bytes(C.byref(_grid(100, 200, 300)), C.byref(_lp(window=18))) == max(n)
+
+
+@pytest.mark.parametrize("w", [11, 13, 15])
+def test_wide_window_workspace_holds_fp64_fields(L, w):
+    """Windows past 9 run separable passes: 8 doubles per voxel (window sums
+    of the five products, then of a, c, e; the fields a, c, e), the block
+    partials of the 64 x 4-column passes, and the checked-mode flag."""
+    for shape in ((100, 200, 300), (7, 9, 11), (1, 1, 1)):
+        D, H, W = shape
+        n = L.ffdp_lncc_workspace_bytes(C.byref(_grid(*shape)), C.byref(_lp(window=w)))
+        blocks = (n - 16 - 64 * D * H * W) // 8
+        cols = -(-W // 64) * -(-H // 4)
+        assert (n - 16) % 8 == 0 and blocks >= cols and blocks % cols == 0, (shape, n, blocks, cols)
+        assert blocks <= max(cols, 4096 + cols)
     assert L.ffdp_mi_state_floats(32) == 2 * 32 * 32 + 2 * 32 + 16
 
 
@@ -96,7 +111,8 @@ def test_workspace_queries_grow_with_blocks_not_voxels(L):
     (dict(grid=_grid(2048, 2048, 1024)), 2),
     (dict(grid=_grid(8, 70000, 8)), 2),
     (dict(params=_lp(window=4)), 3),
-    (dict(params=_lp(window=11)), 3),
+    (dict(params=_lp(window=17)), 3),
+    (dict(params=_lp(window=12)), 3),
     (dict(params=_lp(window=1)), 3),
     (dict(params=_lp(eps=-1.0)), 3),
     (dict(params=_lp(eps=float("nan"))), 3),

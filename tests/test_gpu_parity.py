@@ -100,8 +100,11 @@ def _lncc_case(F, M, u, window=5, eps=1e-5, ants=False, pad="border", roi=None, 
     # the FP64 block partials hold sum n_i: the mean similarity 1 - L without
     # the fp32 rounding of L (the strong form of the check where L is near 1)
     nroi = np.prod([b - a for a, b in roi]) if roi is not None else F.numel()
+    # fused windows: the workspace is the block partials (and a zero flag);
+    # wide windows: 8 N doubles of window sums and fields come first
+    first = 8 * F.numel() if window > 9 else 0
     for name, ws in (("fwd", wsf), ("bwd", wsb)):
-        sim = float(ws.view(torch.float64).sum().item()) / nroi
+        sim = float(ws.view(torch.float64)[first:(nws - 16) // 8].sum().item()) / nroi
         assert abs(sim - (1.0 - lr)) <= 1e-5 * abs(1.0 - lr) + 1e-9, f"{what} {name} similarity {sim} vs {1.0 - lr}"
     assert_grad(_np(g), gr, f"{what} grad")
 
@@ -134,6 +137,77 @@ def test_lncc_c1_zeros_pad_and_roi(c1):
 def test_lncc_c2_clinical_window7(c2):
     F, M, u = c2
     _lncc_case(F, M, u, window=7, what="c2")
+
+
+@pytest.mark.parametrize("window", [11, 13, 15])
+def test_lncc_wide_windows_c1(c1, window):
+    """Windows past the fused kernel's register rings: the separable FP64
+    passes, forward and exact adjoint."""
+    F, M, u = c1
+    _lncc_case(F, M, u, window=window, what="c1 wide")
+
+
+def test_lncc_wide_window_modes(c1):
+    F, M, u = c1
+    _lncc_case(F, M, u, window=13, ants=True, what="c1 wide ants")
+    _lncc_case(F, M, u * 3.0, window=11, pad="zeros", what="c1 wide zeros")
+    _lncc_case(F, M, u, window=15, roi=((8, 56), (3, 61), (10, 50)), what="c1 wide roi")
+    _lncc_case(F, M, None, window=15, what="c1 wide u=None")
+    l = float(ops.warp_lncc_fwd(_dev(F), _dev(F), None, window=15, eps=0.0).item())
+    assert abs(l) < 1e-6
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (37, 45, 70), (20, 17, 130)])
+def test_lncc_wide_ragged_shapes(shape):
+    F, M, u = _rand_case(shape, 130)
+    _lncc_case(F, M, u, window=15, eps=1e-5, what="ragged w15")
+    _lncc_case(F, M, u, window=11, eps=1e-3, ants=True, what="ragged w11 ants")
+
+
+def _wide_zchunk(shape):
+    """z-chunk of the wide-window column passes (64 x 4 columns per block,
+    about 4096 blocks, chunks of at least 32 slices): the library's planner,
+    restated only to put sampled voxels on the chunk seams."""
+    D, H, W = shape
+    cols = -(-W // 64) * -(-H // 4)
+    want = max(1, min(-(-4096 // cols), max(1, D // 32)))
+    return -(-D // want)
+
+
+def test_lncc_wide_window_clinical_samples(c2):
+    """w = 15 on the clinical pair: dloss/du at voxels on the 32 x 8 slice-tile
+    seams, the column passes' z-chunk seams, the faces and random voxels
+    against the oracle's per-voxel adjoint on the whole arrays; the loss of a
+    sub-ROI box against the oracle on the warped volume."""
+    F, M, u = c2
+    D, H, W = F.shape
+    zc = _wide_zchunk(F.shape)
+    rng = np.random.default_rng(77)
+    pts = set()
+    xs = [0, 31, 32, 63, 64, 127, 128, W - 1]
+    ys = [0, 7, 8, 15, 16, 95, 96, H - 1]
+    zs = sorted({0, D - 1, D // 2} | {v for k in (1, 2) for v in (k * zc - 1, k * zc) if 0 <= v < D})
+    for i, z in enumerate(zs):
+        for j, x in enumerate(xs):
+            pts.add((z, ys[(i + j) % len(ys)], x))
+    for _ in range(16):
+        pts.add((int(rng.integers(D)), int(rng.integers(H)), int(rng.integers(W))))
+    pts = sorted(pts)
+    print(f"[lncc wide clinical: {len(pts)} samples, z-chunk {zc}]", flush=True)
+    Fd, Md, ud = _dev(F), _dev(M), _dev(u)
+    g, _ = ops.warp_lncc_bwd(Fd, Md, ud, window=15)
+    got = g[:, [p[0] for p in pts], [p[1] for p in pts], [p[2] for p in pts]].double().cpu().numpy().T
+    ref = oracle.lncc_grad_u_at(F.numpy(), M.numpy(), u.numpy(), pts, window=15)
+    sc = np.abs(ref).max()
+    assert sc > 0
+    err = np.abs(got - ref).max(axis=1)
+    bad = [(pts[i], got[i], ref[i]) for i in np.nonzero(err > 1e-4 * sc)[0]]
+    assert not bad, bad[:5]
+    box = ((60, 84), (90, 114), (100, 124))
+    l_gpu = float(ops.warp_lncc_fwd(Fd, Md, ud, window=15, roi=box).item())
+    mw = oracle.warp(M.numpy(), u.numpy())
+    l_ref = oracle.lncc_loss_mw(F.numpy(), mw, roi=_roi6(box), window=15)
+    assert_loss(l_gpu, l_ref, "clinical w15 sub-ROI")
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (2, 40, 3), (37, 45, 70), (20, 17, 130)])

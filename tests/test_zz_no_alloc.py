@@ -3,7 +3,8 @@ called through the C ABI: its outputs equal those of ffdp_warp_lncc_bwd with a
 caller workspace, bit for bit, on two calls in a row (the second on a smaller
 grid, which reuses the library-owned scratch the first call left behind);
 grids that need more block partials than the scratch holds are rejected
-before anything runs."""
+before anything runs.  A wide window (w = 15) on a small grid keeps its FP64
+fields in the same scratch."""
 import ctypes as C
 
 import pytest
@@ -28,6 +29,13 @@ def test_noalloc_rejects_grids_beyond_its_scratch():
     rc = L.ffdp_warp_lncc_bwd_noalloc(fake, fake, fake, C.byref(g), C.byref(p), None, fake, fake, None)
     assert rc == 5, rc
     assert b"scratch" in L.ffdp_last_error()
+    # wide windows keep 64 bytes per voxel in the workspace: 64^3 does not fit
+    g = _grid((64, 64, 64))
+    p = ops.lncc_params(15)
+    assert L.ffdp_lncc_workspace_bytes(C.byref(g), C.byref(p)) > 8 * 65538
+    rc = L.ffdp_warp_lncc_bwd_noalloc(fake, fake, fake, C.byref(g), C.byref(p), None, fake, fake, None)
+    assert rc == 5, rc
+    assert b"scratch" in L.ffdp_last_error()
 
 
 @pytest.mark.gpu
@@ -35,7 +43,8 @@ def test_noalloc_matches_workspace_entry_point_twice():
     L = _lib.lib()
     stream = torch.cuda.current_stream(torch.device(DEV)).cuda_stream
     for k, (shape, roi, window, ants) in enumerate([((40, 56, 72), ((3, 37), (2, 50), (5, 70)), 5, 0),
-                                                    ((24, 32, 40), None, 3, 0)]):
+                                                    ((24, 32, 40), None, 3, 0),
+                                                    ((12, 14, 16), None, 15, 0)]):
         p = synth.make_pair(synth.PairSpec(shape, (3.0, 6.0), 3.0), seed=synth.BASE_SEED + 40 + k, device=DEV)
         F, M, u = p["F"], p["M"], (-0.8 * p["d"]).contiguous()
         print(f"[noalloc] call {k} shape {shape} roi {roi} window {window}", flush=True)
