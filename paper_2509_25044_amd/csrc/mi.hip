@@ -96,18 +96,17 @@ __device__ __forceinline__ void sample_disp(const MiArgs& a, int x, int y, int z
     else { dx = ux; dy = uy; dz = uz; }
 }
 
+// round(x 2^32) for 0 <= x < 2^24 in fp32 and integer steps: the integer part
+// hi, then the fraction f = x - hi (exact) scaled by 2^32 (exact) plus 1/2
+// and truncated.  Where x >= 2^-9, f is a multiple of 2^-32, so f 2^32 is an
+// integer and the rounding of the + 1/2 can move it by at most one unit
+// (2^-32 of a voxel); below, f 2^32 + 1/2 is exact and the result is the
+// rounded value.  The same input always gives the same integer.
 __device__ __forceinline__ unsigned long long to_fix(float x)
 {
-    // round(x 2^32) for 0 <= x < 2^24 in exact fp32 and integer steps (the
-    // same value as the float64 fma x * 2^32 + 0.5 truncated, without
-    // half-rate float64 work): integer part, then the fraction scaled by 2^32
-    // (exact), truncated, plus one where the exact remainder is >= 1/2
     const unsigned hi = (unsigned)x;
-    const float f = x - (float)hi;
-    const float t = f * 4294967296.0f;
-    const unsigned lo = (unsigned)t;
-    const unsigned up = (t - (float)lo) >= 0.5f ? 1u : 0u;
-    return ((unsigned long long)hi << 32) + (lo + up);
+    const unsigned lo = (unsigned)fmaf(x - (float)hi, 4294967296.0f, 0.5f);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 // Loads of one voxel's sample, issued one z-step ahead of their use (the
@@ -264,13 +263,17 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
     bool bad = false;
 
     auto flush = [&]() {
+        int row[4], col[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            row[i] = (int)__umul24((unsigned)fold(cm + i, B), (unsigned)B);
+            col[i] = fold(cn + i, B);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const unsigned long long v = to_fix(acc[i * 4 + jj]);
-                atomicAdd(&mine[fold(cm + i, B) * B + fold(cn + jj, B)], v);  // unconditional: no branch per tap
-            }
+            for (int jj = 0; jj < 4; ++jj)
+                atomicAdd(&mine[row[i] + col[jj]], to_fix(acc[i * 4 + jj]));  // unconditional: no branch per tap
     };
 
     if (active && zb < ze) {
