@@ -499,6 +499,160 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_taps_kernel(ConvGeom g, c
     }
 }
 
+// Backward-weight of the stride-1 layers with Cout <= 64, staged in LDS.  A
+// block takes one tap plane dz and one chunk of 4 NG input channels, and walks
+// a chunk of row segments: 32 consecutive output voxels along x at one
+// (n, z, y).  Per segment it stages
+//   Ps[co][k]          = bf16(P[o0 + k][co])                    (A operand)
+//   Xs[dx][c][dy][k]   = X[n, z+dz-1, y+dy-1, x0+k+dx-1][c0+c]   (B operand)
+// with each input row loaded once, coalesced over channels, and written to
+// the three x-shifted copies, so that every MFMA operand is one aligned
+// 16-byte LDS read (8 consecutive voxels of one channel: the K layout of
+// v_mfma_f32_16x16x32_bf16).  All staging loads of a thread are issued
+// before its LDS writes.  Wave w accumulates the work items w, w+4, ... of
+// the 9 (dy, dx) taps x NG/4 channel tiles x TM output-channel tiles.
+// part[chunk][co][t][ci] as conv_bwd_weight_kernel.
+constexpr int WR_KP = 40;  // LDS row pitch (bf16): 32 voxels + 8
+template <int TM, int NG>
+__global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
+                                                              const unsigned short* __restrict__ xb,
+                                                              const float* __restrict__ dy,
+                                                              const unsigned short* __restrict__ y, float slope,
+                                                              long long VS, float* __restrict__ part)
+{
+    constexpr int CC = 4 * NG;            // channels per block (whole 16-channel tiles)
+    constexpr int NT = NG / 4;            // channel tiles
+    constexpr int NI = 9 * NT * TM;       // work items per block
+    constexpr int QI = (NI + 3) / 4;      // per wave
+    constexpr int NIT = 3 * 34 * NG;      // staging loads of X per segment
+    constexpr int XPT = (NIT + 255) / 256;
+    constexpr int NPT = (32 * TM * 4 + 255) / 256;
+    __shared__ __attribute__((aligned(16))) unsigned short Xs[3 * CC * 3 * WR_KP];
+    __shared__ __attribute__((aligned(16))) unsigned short Ps[TM * 16 * WR_KP];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Cin = g.Ca + g.Cb;
+    const int nsx = (g.Wo + 31) / 32;
+    const long long S = (long long)g.N * g.Do * g.Ho * nsx;
+    const int dz = blockIdx.y % 3, c0 = (blockIdx.y / 3) * CC;
+    const int ncv = min(CC, Cin - c0);  // valid channels of this chunk
+    const long long sb = (long long)blockIdx.x * VS, se = min(S, sb + VS);
+    const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
+    f4v acc[QI];
+#pragma unroll
+    for (int q = 0; q < QI; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (long long sg = sb; sg < se; ++sg) {
+        long long q = sg;
+        const int xs = (int)(q % nsx); q /= nsx;
+        const int yo = (int)(q % g.Ho); q /= g.Ho;
+        const int zo = (int)(q % g.Do);
+        const int n = (int)(q / g.Do);
+        const int x0 = xs * 32;
+        // element offsets of the three input rows (x = 0) of plane dz
+        const int zi = zo + dz - 1;
+        size_t rowa[3], rowb[3];
+        bool rok[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int yi = yo + r - 1;
+            rok[r] = (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi;
+            const int zc = rok[r] ? zi : 0, yc = rok[r] ? yi : 0;
+            rowa[r] = g.ups ? (((size_t)n * Da + (zc >> 1)) * Ha + (yc >> 1)) * (size_t)Wa * g.Ca
+                            : (((size_t)n * g.Di + zc) * g.Hi + yc) * (size_t)g.Wi * g.Ca;
+            rowb[r] = (((size_t)n * g.Di + zc) * g.Hi + yc) * (size_t)g.Wi * g.Cb;
+        }
+        s4v xv[XPT];
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int it = threadIdx.x + 256 * u;
+            const int cg = it % NG, rest = it / NG;
+            const int xi = x0 - 1 + rest % 34, r = rest / 34;
+            const int c = c0 + 4 * cg;
+            xv[u] = s4v{0, 0, 0, 0};
+            if (it < NIT && 4 * cg < ncv && (unsigned)xi < (unsigned)g.Wi) {
+                const size_t ra = r == 0 ? rowa[0] : (r == 1 ? rowa[1] : rowa[2]);
+                const size_t rb = r == 0 ? rowb[0] : (r == 1 ? rowb[1] : rowb[2]);
+                const bool ok = r == 0 ? rok[0] : (r == 1 ? rok[1] : rok[2]);
+                if (ok) {
+                    if (c < g.Ca) xv[u] = ld4bf(xa + ra + (unsigned)((g.ups ? (xi >> 1) : xi) * g.Ca + c));
+                    else xv[u] = ld4bf(xb + rb + (unsigned)(xi * g.Cb + (c - g.Ca)));
+                }
+            }
+        }
+        // A operand: P of the 32 voxels for TM * 16 output channels
+        const size_t orow = (((size_t)n * g.Do + zo) * g.Ho + yo) * g.Wo + x0;
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int it = threadIdx.x + 256 * u;
+            if (it >= 32 * TM * 4) break;
+            const int cg = (it % (TM * 4)) * 4, k = it / (TM * 4);
+            float pv[4] = {0.f, 0.f, 0.f, 0.f};
+            if (x0 + k < g.Wo && cg < g.Cout) {  // Cout is a multiple of 4
+                const size_t o = (orow + k) * g.Cout + cg;
+                const float4 d = *reinterpret_cast<const float4*>(dy + o);
+                pv[0] = d.x; pv[1] = d.y; pv[2] = d.z; pv[3] = d.w;
+                if (y) {
+                    const s4v yv = ld4bf(y + o);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) pv[c] *= lrelu_d((unsigned short)yv[c], slope);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Ps[(cg + c) * WR_KP + k] = f2bf(pv[c]);
+        }
+#pragma unroll
+        for (int u = 0; u < XPT; ++u) {
+            const int it = threadIdx.x + 256 * u;
+            if (it >= NIT) break;
+            const int cg = it % NG, rest = it / NG;
+            const int kx = rest % 34, r = rest / 34;  // k of the dx = 0 copy: xi - x0 + 1
+            unsigned short* dst = Xs + ((4 * cg) * 3 + r) * WR_KP + kx;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                if (kx - dx >= 0 && kx - dx < 32)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) dst[(dx * CC + c) * 3 * WR_KP - dx] = (unsigned short)xv[u][c];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int qi = 0; qi < QI; ++qi) {
+            const int item = wave + 4 * qi;
+            const int tap = item % 9, ct = (item / 9) % NT, cm = item / (9 * NT);
+            if (item >= NI || ct * 16 >= ncv) continue;  // uniform over the wave
+            const int dyy = tap / 3, dx = tap % 3;
+            const uint4 av = *reinterpret_cast<const uint4*>(Ps + (cm * 16 + (lane & 15)) * WR_KP + (lane >> 4) * 8);
+            const uint4 bv = *reinterpret_cast<const uint4*>(
+                Xs + ((dx * CC + ct * 16 + (lane & 15)) * 3 + dyy) * WR_KP + (lane >> 4) * 8);
+            acc[qi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, av), __builtin_bit_cast(bf8v, bv),
+                                                              acc[qi], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D[i = co][j = ci]: lane holds co = 16 cm + 4 (l/16) + e, ci = c0 + 16 ct + l % 16
+    float* P = part + (size_t)blockIdx.x * g.Cout * 27 * Cin;
+#pragma unroll
+    for (int qi = 0; qi < QI; ++qi) {
+        const int item = wave + 4 * qi;
+        const int tap = item % 9, ct = (item / 9) % NT, cm = item / (9 * NT);
+        const int t = dz * 9 + tap;
+        const int ci = c0 + ct * 16 + (lane & 15);
+        if (item >= NI || ct * 16 >= ncv || ci >= Cin) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int co = cm * 16 + (lane >> 4) * 4 + e;
+            if (co < g.Cout) P[((size_t)co * 27 + t) * Cin + ci] = acc[qi][e];
+        }
+    }
+}
+
+// channel groups of 4 per block of the row-segment kernel: whole 16-channel
+// tiles, at most 64 channels
+static int wgrad_rows_ng(const ConvGeom& g)
+{
+    const int c16 = ((g.Ca + g.Cb + 15) / 16) * 16;
+    return c16 >= 64 ? 16 : c16 / 4;
+}
+
 // dW[q] = sum_c part[c][q] (fixed order), dW fp32
 __global__ void __launch_bounds__(256) reduce_parts_kernel(const float* __restrict__ part, int nparts, long long q_n,
                                                            float* __restrict__ out)
@@ -700,10 +854,28 @@ static bool wgrad_all_taps(const ConvGeom& g)
     return tm * tn <= 3;
 }
 
+static bool wgrad_rows(const ConvGeom& g) { return g.stride == 1 && g.Cout <= 64; }
+
 ConvWgradPlan conv_wgrad_plan(const ConvGeom& g)
 {
     ConvWgradPlan p;
     const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
+    p.rows = 0;
+    p.VS = 0;
+    if (wgrad_rows(g)) {
+        // about 2048 blocks over (chunk, dz, channel chunk)
+        const long long S = (long long)g.N * g.Do * g.Ho * ((g.Wo + 31) / 32);
+        const int ncc = (g.Ca + g.Cb + 4 * wgrad_rows_ng(g) - 1) / (4 * wgrad_rows_ng(g));
+        long long want = (2048 + 3 * ncc - 1) / (3 * ncc);
+        if (want > S) want = S;
+        p.rows = 1;
+        p.VS = (S + want - 1) / want;
+        p.nchunks = (int)((S + p.VS - 1) / p.VS);
+        p.VC = (M + p.nchunks - 1) / p.nchunks;  // bias partials: the same number of chunks
+        const long long q = (long long)g.Cout * 27 * (g.Ca + g.Cb);
+        p.part_floats = (long long)p.nchunks * q + (long long)p.nchunks * g.Cout;
+        return p;
+    }
     // all-taps kernel: about 1024 chunks (each block covers every tap);
     // tap-per-block kernel: about 256 chunks x 27 taps
     long long vc = (M + (wgrad_all_taps(g) ? 1023 : 255)) / (wgrad_all_taps(g) ? 1024 : 256);
@@ -726,6 +898,26 @@ static void launch_wg_tm(int tnw, dim3 grid, hipStream_t st, const ConvGeom& g, 
     else hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 3>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VC, part);
 }
 
+template <int TM>
+static void launch_wgrad_rows_tm(int ng, dim3 grid, hipStream_t st, const ConvGeom& g, const unsigned short* xa,
+                                 const unsigned short* xb, const float* dy, const unsigned short* y, float slope,
+                                 long long VS, float* part)
+{
+    if (ng == 4) hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 4>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VS, part);
+    else if (ng == 8) hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 8>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VS, part);
+    else if (ng == 12) hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 12>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VS, part);
+    else hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 16>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VS, part);
+}
+
+static void launch_wgrad_rows(int tm, int ng, dim3 grid, hipStream_t st, const ConvGeom& g, const unsigned short* xa,
+                              const unsigned short* xb, const float* dy, const unsigned short* y, float slope,
+                              long long VS, float* part)
+{
+    if (tm == 1) launch_wgrad_rows_tm<1>(ng, grid, st, g, xa, xb, dy, y, slope, VS, part);
+    else if (tm == 2) launch_wgrad_rows_tm<2>(ng, grid, st, g, xa, xb, dy, y, slope, VS, part);
+    else launch_wgrad_rows_tm<4>(ng, grid, st, g, xa, xb, dy, y, slope, VS, part);
+}
+
 hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
                                   const float* dy, const unsigned short* y, float slope, float* dw, float* db,
                                   float* part, hipStream_t st)
@@ -734,7 +926,11 @@ hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, c
     const int Cin = g.Ca + g.Cb;
     const int tm = (g.Cout + 15) / 16, tn = (Cin + 15) / 16, tnw = (tn + 3) / 4;
     if (tnw > 3 || tm > 8) return hipErrorInvalidValue;
-    if (wgrad_all_taps(g)) {
+    if (p.rows) {
+        const int ng = wgrad_rows_ng(g);
+        dim3 grid(p.nchunks, 3 * ((Cin + 4 * ng - 1) / (4 * ng)));
+        launch_wgrad_rows(tm, ng, grid, st, g, xa, xb, dy, y, slope, p.VS, part);
+    } else if (wgrad_all_taps(g)) {
         dim3 grid1(p.nchunks);
         if (tm == 1 && tn == 1) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 1>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
         else if (tm == 1 && tn == 2) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 2>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);

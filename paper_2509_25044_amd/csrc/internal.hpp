@@ -146,9 +146,11 @@ struct ConvGeom {
     int ups;         // part a stored at half resolution, nearest x2
 };
 struct ConvWgradPlan {
-    long long VC;          // output voxels per chunk
+    long long VC;          // output voxels per chunk (bias partials; the voxel-chunk kernels)
     int nchunks;
     long long part_floats;  // workspace floats
+    int rows;              // 1: the row-segment kernel (stride 1, Cout <= 64)
+    long long VS;          // row segments of 32 output voxels per chunk (row-segment kernel)
 };
 ConvWgradPlan conv_wgrad_plan(const ConvGeom& g);
 hipError_t conv_fwd_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,

@@ -20,6 +20,10 @@ CASES = [
     (1, 4, 6, 8, 32, 16, 16, 1, True),
     (2, 5, 7, 6, 16, 0, 4, 1, False),
     (1, 7, 5, 9, 8, 4, 8, 2, False),
+    # rows longer than one 32-voxel segment, ragged tails, two channel chunks
+    (1, 4, 6, 70, 32, 16, 16, 1, True),
+    (1, 4, 4, 40, 64, 32, 32, 1, True),
+    (2, 3, 5, 45, 16, 0, 4, 1, False),
 ]
 
 
