@@ -89,6 +89,32 @@ __device__ __forceinline__ bf8v cat8(s4v lo, s4v hi)
     return __builtin_bit_cast(bf8v, r);
 }
 
+// Output-voxel cursor (n, z, y, x) advanced by d voxels without divisions
+// (the loop runs about d / W + 1 times).
+struct Vox {
+    int n, z, y, x;
+};
+__device__ __forceinline__ Vox vox_of(long long o, int D, int H, int W)
+{
+    Vox v;
+    v.x = (int)(o % W); o /= W;
+    v.y = (int)(o % H); o /= H;
+    v.z = (int)(o % D);
+    v.n = (int)(o / D);
+    return v;
+}
+__device__ __forceinline__ void vox_add(Vox& v, int d, int D, int H, int W)
+{
+    v.x += d;
+    while (v.x >= W) {
+        v.x -= W;
+        if (++v.y == H) {
+            v.y = 0;
+            if (++v.z == D) { v.z = 0; ++v.n; }
+        }
+    }
+}
+
 constexpr int CONV_KC = 128;            // K columns of the weight tile staged per round
 constexpr int CONV_KCP = CONV_KC + 8;   // LDS row pitch (bf16)
 
@@ -291,30 +317,33 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const 
 #pragma unroll
         for (int j = 0; j < TNW; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
     const int kg = (lane >> 4) * 8;
+    Vox cur = vox_of(ob + kg, g.Do, g.Ho, g.Wo);  // the lane's first voxel of the K step
     for (long long o0 = ob; o0 < oe; o0 += 32) {
         // this lane's 8 output voxels o0 + kg + e and their shifted input voxels
-        long long iv[8];
+        long long iv[8], iva[8];  // input voxel; its coarse voxel where part a is upsampled
         bool ov[8], iok[8];
         size_t ooff[8];
+        Vox v = cur;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
+            if (e) vox_add(v, 1, g.Do, g.Ho, g.Wo);
             const long long o = o0 + kg + e;
             ov[e] = o < oe;
             iok[e] = false;
             iv[e] = 0;
+            iva[e] = 0;
             ooff[e] = 0;
             if (ov[e]) {
-                long long q = o;
-                const int xo = (int)(q % g.Wo); q /= g.Wo;
-                const int yo = (int)(q % g.Ho); q /= g.Ho;
-                const int zo = (int)(q % g.Do);
-                const int n = (int)(q / g.Do);
-                const int zi = zo * g.stride + dz - 1, yi = yo * g.stride + dyy - 1, xi = xo * g.stride + dx_ - 1;
+                const int zi = v.z * g.stride + dz - 1, yi = v.y * g.stride + dyy - 1, xi = v.x * g.stride + dx_ - 1;
                 iok[e] = (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi && (unsigned)xi < (unsigned)g.Wi;
-                iv[e] = (((long long)n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                iv[e] = (((long long)v.n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                if (g.ups)
+                    iva[e] = (((long long)v.n * (g.Di >> 1) + (zi >> 1)) * (g.Hi >> 1) + (yi >> 1)) * (g.Wi >> 1) +
+                             (xi >> 1);
                 ooff[e] = (size_t)o * g.Cout;
             }
         }
+        vox_add(cur, 32, g.Do, g.Ho, g.Wo);
         // A operands: P[o][co] for the co-tiles
         bf8v a[TM];
 #pragma unroll
@@ -344,14 +373,7 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const 
                     const long long v = iv[e];
                     if (ci < g.Ca) {
                         if (g.ups) {
-                            long long q = v;
-                            const int xi = (int)(q % g.Wi); q /= g.Wi;
-                            const int yi = (int)(q % g.Hi); q /= g.Hi;
-                            const int zi = (int)(q % g.Di);
-                            const int n = (int)(q / g.Di);
-                            const size_t va = (((size_t)n * (g.Di >> 1) + (zi >> 1)) * (g.Hi >> 1) + (yi >> 1)) *
-                                                  (g.Wi >> 1) + (xi >> 1);
-                            h = xa[va * g.Ca + ci];
+                            h = xa[(size_t)iva[e] * g.Ca + ci];
                         } else {
                             h = xa[(size_t)v * g.Ca + ci];
                         }
@@ -411,24 +433,24 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_taps_kernel(ConvGeom g, c
 #pragma unroll
             for (int j = 0; j < TN; ++j) acc[q][i][j] = f4v{0.f, 0.f, 0.f, 0.f};
     const int kg = (lane >> 4) * 8;
+    Vox cur = vox_of(ob + kg, g.Do, g.Ho, g.Wo);  // the lane's first voxel of the K step
     for (long long o0 = ob; o0 < oe; o0 += 32) {
         // the lane's 8 output voxels o0 + kg + e: batch index and the input
         // corner (tap 0, 0, 0) of each
         int vn[8], vz[8], vy[8], vx[8];
         bool ov[8];
         size_t ooff[8];
+        Vox v = cur;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
+            if (e) vox_add(v, 1, g.Do, g.Ho, g.Wo);
             const long long o = o0 + kg + e;
             ov[e] = o < oe;
-            long long q = ov[e] ? o : 0;
-            const int xo = (int)(q % g.Wo); q /= g.Wo;
-            const int yo = (int)(q % g.Ho); q /= g.Ho;
-            const int zo = (int)(q % g.Do);
-            vn[e] = (int)(q / g.Do);
-            vz[e] = zo * g.stride - 1; vy[e] = yo * g.stride - 1; vx[e] = xo * g.stride - 1;
+            vn[e] = ov[e] ? v.n : 0;
+            vz[e] = v.z * g.stride - 1; vy[e] = v.y * g.stride - 1; vx[e] = v.x * g.stride - 1;
             ooff[e] = (size_t)(ov[e] ? o : 0) * g.Cout;
         }
+        vox_add(cur, 32, g.Do, g.Ho, g.Wo);
         bf8v a[TM];
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
@@ -501,18 +523,21 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_taps_kernel(ConvGeom g, c
 
 // Backward-weight of the stride-1 layers with Cout <= 64, staged in LDS.  A
 // block takes one tap plane dz and one chunk of 4 NG input channels, and walks
-// a chunk of row segments: 32 consecutive output voxels along x at one
-// (n, z, y).  Per segment it stages
-//   Ps[co][k]          = bf16(P[o0 + k][co])                    (A operand)
-//   Xs[dx][c][dy][k]   = X[n, z+dz-1, y+dy-1, x0+k+dx-1][c0+c]   (B operand)
-// with each input row loaded once, coalesced over channels, and written to
-// the three x-shifted copies, so that every MFMA operand is one aligned
-// 16-byte LDS read (8 consecutive voxels of one channel: the K layout of
-// v_mfma_f32_16x16x32_bf16).  All staging loads of a thread are issued
-// before its LDS writes.  Wave w accumulates the work items w, w+4, ... of
-// the 9 (dy, dx) taps x NG/4 channel tiles x TM output-channel tiles.
+// a chunk of row segments along y: 30 consecutive output voxels along x at
+// one (n, z, y), whose taps read the 32 input voxels x0 - 1 .. x0 + 30 of the
+// rows y - 1, y, y + 1.  LDS holds
+//   Xs[c][slot][k]     input row yi in slot (yi + 3) % 3, k = xi - x0 + 1
+//   Ps[dx][co][k]      = bf16(P[x0 + k - dx][co]) (0 outside the segment)
+// so that the product for tap (dy, dx) is sum_k Ps[dx][co][k] Xs[c][dy][k]
+// and every MFMA operand is one aligned 16-byte LDS read (8 consecutive k:
+// the K layout of v_mfma_f32_16x16x32_bf16).  Walking along y, a segment
+// stages one new input row (three at the start of a run) and P; the global
+// loads of the next segment are in flight during the MFMAs of the current
+// one.  Wave w accumulates the work items w, w+4, ... of the 9 (dy, dx) taps
+// x NG/4 channel tiles x TM output-channel tiles.
 // part[chunk][co][t][ci] as conv_bwd_weight_kernel.
-constexpr int WR_KP = 40;  // LDS row pitch (bf16): 32 voxels + 8
+constexpr int WR_KP = 40;   // LDS row pitch (bf16): 32 voxels + 8
+constexpr int WR_SEG = 30;  // output voxels per segment
 template <int TM, int NG>
 __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
                                                               const unsigned short* __restrict__ xb,
@@ -524,105 +549,134 @@ __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const 
     constexpr int NT = NG / 4;            // channel tiles
     constexpr int NI = 9 * NT * TM;       // work items per block
     constexpr int QI = (NI + 3) / 4;      // per wave
-    constexpr int NIT = 3 * 34 * NG;      // staging loads of X per segment
-    constexpr int XPT = (NIT + 255) / 256;
-    constexpr int NPT = (32 * TM * 4 + 255) / 256;
-    __shared__ __attribute__((aligned(16))) unsigned short Xs[3 * CC * 3 * WR_KP];
-    __shared__ __attribute__((aligned(16))) unsigned short Ps[TM * 16 * WR_KP];
+    constexpr int XPT = (3 * 2 * NT + 3) / 4;  // staging wave-items per wave (3 rows)
+    constexpr int NP = WR_SEG * TM * 4;   // P loads: 30 voxels x 4-channel groups
+    constexpr int NPT = (NP + 255) / 256;
+    __shared__ __attribute__((aligned(16))) unsigned short Xs[CC * 3 * WR_KP];
+    __shared__ __attribute__((aligned(16))) unsigned short Ps[3 * TM * 16 * WR_KP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int Cin = g.Ca + g.Cb;
-    const int nsx = (g.Wo + 31) / 32;
+    const int nsx = (g.Wo + WR_SEG - 1) / WR_SEG;
     const long long S = (long long)g.N * g.Do * g.Ho * nsx;
     const int dz = blockIdx.y % 3, c0 = (blockIdx.y / 3) * CC;
     const int ncv = min(CC, Cin - c0);  // valid channels of this chunk
     const long long sb = (long long)blockIdx.x * VS, se = min(S, sb + VS);
     const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
+    const int kxl = lane & 15, cgl = lane >> 4;
+    // P slots never written (k = 30, 31 for dx = 0; 0, 31 for dx = 1; 0, 1
+    // for dx = 2) stay zero
+    for (int i = threadIdx.x; i < 3 * TM * 16 * WR_KP / 2; i += 256) reinterpret_cast<unsigned*>(Ps)[i] = 0u;
+    __syncthreads();
     f4v acc[QI];
 #pragma unroll
     for (int q = 0; q < QI; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
-    for (long long sg = sb; sg < se; ++sg) {
-        long long q = sg;
-        const int xs = (int)(q % nsx); q /= nsx;
-        const int yo = (int)(q % g.Ho); q /= g.Ho;
-        const int zo = (int)(q % g.Do);
-        const int n = (int)(q / g.Do);
-        const int x0 = xs * 32;
-        // element offsets of the three input rows (x = 0) of plane dz
+    // global loads of one segment's operands into registers, raw (xr: 4 bf16
+    // channels of X; dr, yr: dL/dy and y)
+    uint2 xr[XPT], yr[NPT];
+    float4 dr[NPT];
+    int nrow_ld = 0, row0_ld = 0;  // rows held in xr: dy = row0 .. row0 + nrow - 1
+    // coordinates of the next segment to load, advanced without divisions
+    int yo, xs, zo, n;
+    {
+        long long q = sb;
+        yo = (int)(q % g.Ho); q /= g.Ho;
+        xs = (int)(q % nsx); q /= nsx;
+        zo = (int)(q % g.Do);
+        n = (int)(q / g.Do);
+    }
+    bool first = true;
+    int yo_ld = 0;  // y of the segment held in registers
+    auto load_seg = [&]() {
+        const int x0 = xs * WR_SEG;
         const int zi = zo + dz - 1;
-        size_t rowa[3], rowb[3];
-        bool rok[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const int yi = yo + r - 1;
-            rok[r] = (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi;
-            const int zc = rok[r] ? zi : 0, yc = rok[r] ? yi : 0;
-            rowa[r] = g.ups ? (((size_t)n * Da + (zc >> 1)) * Ha + (yc >> 1)) * (size_t)Wa * g.Ca
-                            : (((size_t)n * g.Di + zc) * g.Hi + yc) * (size_t)g.Wi * g.Ca;
-            rowb[r] = (((size_t)n * g.Di + zc) * g.Hi + yc) * (size_t)g.Wi * g.Cb;
-        }
-        s4v xv[XPT];
+        const bool run = first || yo == 0;  // a new run along y: all three rows
+        nrow_ld = run ? 3 : 1;
+        row0_ld = run ? 0 : 2;
+        yo_ld = yo;
+        const bool zok = (unsigned)zi < (unsigned)g.Di;
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
-            const int it = threadIdx.x + 256 * u;
-            const int cg = it % NG, rest = it / NG;
-            const int xi = x0 - 1 + rest % 34, r = rest / 34;
-            const int c = c0 + 4 * cg;
-            xv[u] = s4v{0, 0, 0, 0};
-            if (it < NIT && 4 * cg < ncv && (unsigned)xi < (unsigned)g.Wi) {
-                const size_t ra = r == 0 ? rowa[0] : (r == 1 ? rowa[1] : rowa[2]);
-                const size_t rb = r == 0 ? rowb[0] : (r == 1 ? rowb[1] : rowb[2]);
-                const bool ok = r == 0 ? rok[0] : (r == 1 ? rok[1] : rok[2]);
-                if (ok) {
-                    if (c < g.Ca) xv[u] = ld4bf(xa + ra + (unsigned)((g.ups ? (xi >> 1) : xi) * g.Ca + c));
-                    else xv[u] = ld4bf(xb + rb + (unsigned)(xi * g.Cb + (c - g.Ca)));
+            const int wi = wave + 4 * u;
+            const int r = row0_ld + wi / (2 * NT), kxc = (wi / NT) % 2, ct = wi % NT;
+            const int xi = x0 - 1 + 16 * kxc + kxl, yi = yo + r - 1;
+            const int c = c0 + 16 * ct + 4 * cgl;
+            xr[u] = make_uint2(0u, 0u);
+            if (wi < 2 * NT * nrow_ld && zok && c - c0 < ncv && (unsigned)xi < (unsigned)g.Wi &&
+                (unsigned)yi < (unsigned)g.Hi) {
+                const unsigned short* src;
+                if (c < g.Ca) {
+                    const size_t va = g.ups ? (((size_t)n * Da + (zi >> 1)) * Ha + (yi >> 1)) * Wa + (xi >> 1)
+                                            : (((size_t)n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                    src = xa + va * g.Ca + c;
+                } else {
+                    src = xb + ((((size_t)n * g.Di + zi) * g.Hi + yi) * g.Wi + xi) * g.Cb + (c - g.Ca);
                 }
+                xr[u] = *reinterpret_cast<const uint2*>(src);
             }
         }
-        // A operand: P of the 32 voxels for TM * 16 output channels
         const size_t orow = (((size_t)n * g.Do + zo) * g.Ho + yo) * g.Wo + x0;
 #pragma unroll
         for (int u = 0; u < NPT; ++u) {
             const int it = threadIdx.x + 256 * u;
-            if (it >= 32 * TM * 4) break;
-            const int cg = (it % (TM * 4)) * 4, k = it / (TM * 4);
-            float pv[4] = {0.f, 0.f, 0.f, 0.f};
-            if (x0 + k < g.Wo && cg < g.Cout) {  // Cout is a multiple of 4
-                const size_t o = (orow + k) * g.Cout + cg;
-                const float4 d = *reinterpret_cast<const float4*>(dy + o);
-                pv[0] = d.x; pv[1] = d.y; pv[2] = d.z; pv[3] = d.w;
-                if (y) {
-                    const s4v yv = ld4bf(y + o);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) pv[c] *= lrelu_d((unsigned short)yv[c], slope);
-                }
+            const int cg = (it % (TM * 4)) * 4, j = it / (TM * 4);
+            dr[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            yr[u] = make_uint2(0x3f803f80u, 0x3f803f80u);  // y = 1: no activation factor
+            if (it < NP && x0 + j < g.Wo && cg < g.Cout) {  // Cout is a multiple of 4
+                const size_t o = (orow + j) * g.Cout + cg;
+                dr[u] = *reinterpret_cast<const float4*>(dy + o);
+                if (y) yr[u] = *reinterpret_cast<const uint2*>(y + o);
             }
+        }
+        first = false;
+        if (++yo == g.Ho) {
+            yo = 0;
+            if (++xs == nsx) {
+                xs = 0;
+                if (++zo == g.Do) { zo = 0; ++n; }
+            }
+        }
+    };
+    if (sb < se) load_seg();
+    for (long long sg = sb; sg < se; ++sg) {
+        const int ys = yo_ld;  // this segment's y
 #pragma unroll
-            for (int c = 0; c < 4; ++c) Ps[(cg + c) * WR_KP + k] = f2bf(pv[c]);
+        for (int u = 0; u < NPT; ++u) {
+            const int it = threadIdx.x + 256 * u;
+            if (it >= NP) break;
+            const int cg = (it % (TM * 4)) * 4, j = it / (TM * 4);
+            const float pv[4] = {dr[u].x, dr[u].y, dr[u].z, dr[u].w};
+            const unsigned short yv[4] = {(unsigned short)(yr[u].x & 0xffffu), (unsigned short)(yr[u].x >> 16),
+                                          (unsigned short)(yr[u].y & 0xffffu), (unsigned short)(yr[u].y >> 16)};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const unsigned short h = f2bf(pv[c] * lrelu_d(yv[c], slope));
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) Ps[(dx * TM * 16 + cg + c) * WR_KP + j + dx] = h;
+            }
         }
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
-            const int it = threadIdx.x + 256 * u;
-            if (it >= NIT) break;
-            const int cg = it % NG, rest = it / NG;
-            const int kx = rest % 34, r = rest / 34;  // k of the dx = 0 copy: xi - x0 + 1
-            unsigned short* dst = Xs + ((4 * cg) * 3 + r) * WR_KP + kx;
+            const int wi = wave + 4 * u;
+            if (wi >= 2 * NT * nrow_ld) break;
+            const int r = row0_ld + wi / (2 * NT), kxc = (wi / NT) % 2, ct = wi % NT;
+            const int slot = (ys + r + 2) % 3;  // input row ys + r - 1
+            unsigned short* dst = Xs + ((16 * ct + 4 * cgl) * 3 + slot) * WR_KP + 16 * kxc + kxl;
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                if (kx - dx >= 0 && kx - dx < 32)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) dst[(dx * CC + c) * 3 * WR_KP - dx] = (unsigned short)xv[u][c];
-            }
+            for (int c = 0; c < 4; ++c) dst[c * 3 * WR_KP] = (unsigned short)((c < 2 ? xr[u].x : xr[u].y) >> (16 * (c & 1)));
         }
         __syncthreads();
+        if (sg + 1 < se) load_seg();
 #pragma unroll
         for (int qi = 0; qi < QI; ++qi) {
             const int item = wave + 4 * qi;
             const int tap = item % 9, ct = (item / 9) % NT, cm = item / (9 * NT);
             if (item >= NI || ct * 16 >= ncv) continue;  // uniform over the wave
             const int dyy = tap / 3, dx = tap % 3;
-            const uint4 av = *reinterpret_cast<const uint4*>(Ps + (cm * 16 + (lane & 15)) * WR_KP + (lane >> 4) * 8);
+            const int slot = (ys + dyy + 2) % 3;
+            const uint4 av = *reinterpret_cast<const uint4*>(
+                Ps + ((dx * TM + cm) * 16 + (lane & 15)) * WR_KP + (lane >> 4) * 8);
             const uint4 bv = *reinterpret_cast<const uint4*>(
-                Xs + ((dx * CC + ct * 16 + (lane & 15)) * 3 + dyy) * WR_KP + (lane >> 4) * 8);
+                Xs + ((ct * 16 + (lane & 15)) * 3 + slot) * WR_KP + (lane >> 4) * 8);
             acc[qi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, av), __builtin_bit_cast(bf8v, bv),
                                                               acc[qi], 0, 0, 0);
         }
@@ -864,7 +918,7 @@ ConvWgradPlan conv_wgrad_plan(const ConvGeom& g)
     p.VS = 0;
     if (wgrad_rows(g)) {
         // about 2048 blocks over (chunk, dz, channel chunk)
-        const long long S = (long long)g.N * g.Do * g.Ho * ((g.Wo + 31) / 32);
+        const long long S = (long long)g.N * g.Do * g.Ho * ((g.Wo + WR_SEG - 1) / WR_SEG);
         const int ncc = (g.Ca + g.Cb + 4 * wgrad_rows_ng(g) - 1) / (4 * wgrad_rows_ng(g));
         long long want = (2048 + 3 * ncc - 1) / (3 * ncc);
         if (want > S) want = S;
