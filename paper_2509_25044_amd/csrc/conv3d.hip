@@ -523,21 +523,23 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_taps_kernel(ConvGeom g, c
 
 // Backward-weight of the stride-1 layers with Cout <= 64, staged in LDS.  A
 // block takes one tap plane dz and one chunk of 4 NG input channels, and walks
-// a chunk of row segments along y: 30 consecutive output voxels along x at
-// one (n, z, y), whose taps read the 32 input voxels x0 - 1 .. x0 + 30 of the
-// rows y - 1, y, y + 1.  LDS holds
-//   Xs[c][slot][k]     input row yi in slot (yi + 3) % 3, k = xi - x0 + 1
-//   Ps[dx][co][k]      = bf16(P[x0 + k - dx][co]) (0 outside the segment)
-// so that the product for tap (dy, dx) is sum_k Ps[dx][co][k] Xs[c][dy][k]
-// and every MFMA operand is one aligned 16-byte LDS read (8 consecutive k:
-// the K layout of v_mfma_f32_16x16x32_bf16).  Walking along y, a segment
-// stages one new input row (three at the start of a run) and P; the global
-// loads of the next segment are in flight during the MFMAs of the current
-// one.  Wave w accumulates the work items w, w+4, ... of the 9 (dy, dx) taps
-// x NG/4 channel tiles x TM output-channel tiles.
-// part[chunk][co][t][ci] as conv_bwd_weight_kernel.
+// a chunk of steps along y: a step is YB rows of 30 consecutive output voxels
+// along x at one (n, z), rows y0 .. y0 + YB - 1, whose taps read the 32
+// input voxels x0 - 1 .. x0 + 30 of the rows y0 - 1 .. y0 + YB.  LDS holds
+//   Xs[c][slot][k]       input row yi in slot (yi + 1) % (YB + 2), k = xi - x0 + 1
+//   Ps[dx][co][j][k]     = bf16(P[row y0 + j, x0 + k - dx][co]) (0 outside)
+// so that the product for tap (dy, dx) and row j is
+// sum_k Ps[dx][co][j][k] Xs[c][slot(y0 + j + dy - 1)][k], and every MFMA
+// operand is one aligned 16-byte LDS read (8 consecutive k: the K layout of
+// v_mfma_f32_16x16x32_bf16).  Walking along y, a step stages YB new input
+// rows (YB + 2 at the start of a run) and P; the global loads of the next
+// step are in flight during the MFMAs of the current one.  Wave w
+// accumulates the work items w, w+4, ... of the 9 (dy, dx) taps x NG/4
+// channel tiles x TM output-channel tiles.  part[chunk][co][t][ci] as
+// conv_bwd_weight_kernel.
 constexpr int WR_KP = 40;   // LDS row pitch (bf16): 32 voxels + 8
-constexpr int WR_SEG = 30;  // output voxels per segment
+constexpr int WR_SEG = 30;  // output voxels per row of a step
+__host__ __device__ constexpr int wgrad_rows_yb(int tm) { return tm == 1 ? 4 : (tm == 2 ? 2 : 1); }
 template <int TM, int NG>
 __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
                                                               const unsigned short* __restrict__ xb,
@@ -545,19 +547,21 @@ __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const 
                                                               const unsigned short* __restrict__ y, float slope,
                                                               long long VS, float* __restrict__ part)
 {
-    constexpr int CC = 4 * NG;            // channels per block (whole 16-channel tiles)
-    constexpr int NT = NG / 4;            // channel tiles
-    constexpr int NI = 9 * NT * TM;       // work items per block
-    constexpr int QI = (NI + 3) / 4;      // per wave
-    constexpr int XPT = (3 * 2 * NT + 3) / 4;  // staging wave-items per wave (3 rows)
-    constexpr int NP = WR_SEG * TM * 4;   // P loads: 30 voxels x 4-channel groups
+    constexpr int YB = wgrad_rows_yb(TM);  // output rows per step
+    constexpr int R = YB + 2;              // ring slots of input rows
+    constexpr int CC = 4 * NG;             // channels per block (whole 16-channel tiles)
+    constexpr int NT = NG / 4;             // channel tiles
+    constexpr int NI = 9 * NT * TM;        // work items per block
+    constexpr int QI = (NI + 3) / 4;       // per wave
+    constexpr int XPT = (R * 2 * NT + 3) / 4;  // staging wave-items per wave (a run start)
+    constexpr int NP = YB * WR_SEG * TM * 4;   // P loads: rows x 30 voxels x 4-channel groups
     constexpr int NPT = (NP + 255) / 256;
-    __shared__ __attribute__((aligned(16))) unsigned short Xs[CC * 3 * WR_KP];
-    __shared__ __attribute__((aligned(16))) unsigned short Ps[3 * TM * 16 * WR_KP];
+    __shared__ __attribute__((aligned(16))) unsigned short Xs[CC * R * WR_KP];
+    __shared__ __attribute__((aligned(16))) unsigned short Ps[3 * TM * 16 * YB * WR_KP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int Cin = g.Ca + g.Cb;
-    const int nsx = (g.Wo + WR_SEG - 1) / WR_SEG;
-    const long long S = (long long)g.N * g.Do * g.Ho * nsx;
+    const int nsx = (g.Wo + WR_SEG - 1) / WR_SEG, nyb = (g.Ho + YB - 1) / YB;
+    const long long S = (long long)g.N * g.Do * nsx * nyb;
     const int dz = blockIdx.y % 3, c0 = (blockIdx.y / 3) * CC;
     const int ncv = min(CC, Cin - c0);  // valid channels of this chunk
     const long long sb = (long long)blockIdx.x * VS, se = min(S, sb + VS);
@@ -565,44 +569,42 @@ __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const 
     const int kxl = lane & 15, cgl = lane >> 4;
     // P slots never written (k = 30, 31 for dx = 0; 0, 31 for dx = 1; 0, 1
     // for dx = 2) stay zero
-    for (int i = threadIdx.x; i < 3 * TM * 16 * WR_KP / 2; i += 256) reinterpret_cast<unsigned*>(Ps)[i] = 0u;
+    for (int i = threadIdx.x; i < 3 * TM * 16 * YB * WR_KP / 2; i += 256) reinterpret_cast<unsigned*>(Ps)[i] = 0u;
     __syncthreads();
     f4v acc[QI];
 #pragma unroll
     for (int q = 0; q < QI; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
-    // global loads of one segment's operands into registers, raw (xr: 4 bf16
+    // global loads of one step's operands into registers, raw (xr: 4 bf16
     // channels of X; dr, yr: dL/dy and y)
     uint2 xr[XPT], yr[NPT];
     float4 dr[NPT];
-    int nrow_ld = 0, row0_ld = 0;  // rows held in xr: dy = row0 .. row0 + nrow - 1
-    // coordinates of the next segment to load, advanced without divisions
-    int yo, xs, zo, n;
+    int nrow_ld = 0, row0_ld = 0, y0_ld = 0;  // staged rows yi = y0 + row0 + r, r < nrow
+    // coordinates of the next step to load, advanced without divisions
+    int yb, xs, zo, n;
     {
         long long q = sb;
-        yo = (int)(q % g.Ho); q /= g.Ho;
+        yb = (int)(q % nyb); q /= nyb;
         xs = (int)(q % nsx); q /= nsx;
         zo = (int)(q % g.Do);
         n = (int)(q / g.Do);
     }
     bool first = true;
-    int yo_ld = 0;  // y of the segment held in registers
-    auto load_seg = [&]() {
-        const int x0 = xs * WR_SEG;
+    auto load_step = [&]() {
+        const int x0 = xs * WR_SEG, y0 = yb * YB;
         const int zi = zo + dz - 1;
-        const bool run = first || yo == 0;  // a new run along y: all three rows
-        nrow_ld = run ? 3 : 1;
-        row0_ld = run ? 0 : 2;
-        yo_ld = yo;
+        const bool run = first || yb == 0;  // a new run along y: YB + 2 rows
+        nrow_ld = run ? R : YB;
+        row0_ld = run ? -1 : 1;
+        y0_ld = y0;
         const bool zok = (unsigned)zi < (unsigned)g.Di;
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
             const int wi = wave + 4 * u;
-            const int r = row0_ld + wi / (2 * NT), kxc = (wi / NT) % 2, ct = wi % NT;
-            const int xi = x0 - 1 + 16 * kxc + kxl, yi = yo + r - 1;
+            const int r = wi / (2 * NT), kxc = (wi / NT) % 2, ct = wi % NT;
+            const int xi = x0 - 1 + 16 * kxc + kxl, yi = y0 + row0_ld + r;
             const int c = c0 + 16 * ct + 4 * cgl;
             xr[u] = make_uint2(0u, 0u);
-            if (wi < 2 * NT * nrow_ld && zok && c - c0 < ncv && (unsigned)xi < (unsigned)g.Wi &&
-                (unsigned)yi < (unsigned)g.Hi) {
+            if (r < nrow_ld && zok && c - c0 < ncv && (unsigned)xi < (unsigned)g.Wi && (unsigned)yi < (unsigned)g.Hi) {
                 const unsigned short* src;
                 if (c < g.Ca) {
                     const size_t va = g.ups ? (((size_t)n * Da + (zi >> 1)) * Ha + (yi >> 1)) * Wa + (xi >> 1)
@@ -614,36 +616,38 @@ __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const 
                 xr[u] = *reinterpret_cast<const uint2*>(src);
             }
         }
-        const size_t orow = (((size_t)n * g.Do + zo) * g.Ho + yo) * g.Wo + x0;
+        const size_t oplane = ((size_t)n * g.Do + zo) * g.Ho;
 #pragma unroll
         for (int u = 0; u < NPT; ++u) {
             const int it = threadIdx.x + 256 * u;
-            const int cg = (it % (TM * 4)) * 4, j = it / (TM * 4);
+            const int cg = (it % (TM * 4)) * 4, rest = it / (TM * 4);
+            const int jx = rest % WR_SEG, jy = rest / WR_SEG;
             dr[u] = make_float4(0.f, 0.f, 0.f, 0.f);
             yr[u] = make_uint2(0x3f803f80u, 0x3f803f80u);  // y = 1: no activation factor
-            if (it < NP && x0 + j < g.Wo && cg < g.Cout) {  // Cout is a multiple of 4
-                const size_t o = (orow + j) * g.Cout + cg;
+            if (it < NP && x0 + jx < g.Wo && y0 + jy < g.Ho && cg < g.Cout) {  // Cout is a multiple of 4
+                const size_t o = ((oplane + y0 + jy) * g.Wo + x0 + jx) * g.Cout + cg;
                 dr[u] = *reinterpret_cast<const float4*>(dy + o);
                 if (y) yr[u] = *reinterpret_cast<const uint2*>(y + o);
             }
         }
         first = false;
-        if (++yo == g.Ho) {
-            yo = 0;
+        if (++yb == nyb) {
+            yb = 0;
             if (++xs == nsx) {
                 xs = 0;
                 if (++zo == g.Do) { zo = 0; ++n; }
             }
         }
     };
-    if (sb < se) load_seg();
+    if (sb < se) load_step();
     for (long long sg = sb; sg < se; ++sg) {
-        const int ys = yo_ld;  // this segment's y
+        const int y0 = y0_ld;  // this step's first row
 #pragma unroll
         for (int u = 0; u < NPT; ++u) {
             const int it = threadIdx.x + 256 * u;
             if (it >= NP) break;
-            const int cg = (it % (TM * 4)) * 4, j = it / (TM * 4);
+            const int cg = (it % (TM * 4)) * 4, rest = it / (TM * 4);
+            const int jx = rest % WR_SEG, jy = rest / WR_SEG;
             const float pv[4] = {dr[u].x, dr[u].y, dr[u].z, dr[u].w};
             const unsigned short yv[4] = {(unsigned short)(yr[u].x & 0xffffu), (unsigned short)(yr[u].x >> 16),
                                           (unsigned short)(yr[u].y & 0xffffu), (unsigned short)(yr[u].y >> 16)};
@@ -651,34 +655,37 @@ __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const 
             for (int c = 0; c < 4; ++c) {
                 const unsigned short h = f2bf(pv[c] * lrelu_d(yv[c], slope));
 #pragma unroll
-                for (int dx = 0; dx < 3; ++dx) Ps[(dx * TM * 16 + cg + c) * WR_KP + j + dx] = h;
+                for (int dx = 0; dx < 3; ++dx) Ps[(((dx * TM * 16 + cg + c) * YB) + jy) * WR_KP + jx + dx] = h;
             }
         }
 #pragma unroll
         for (int u = 0; u < XPT; ++u) {
             const int wi = wave + 4 * u;
-            if (wi >= 2 * NT * nrow_ld) break;
-            const int r = row0_ld + wi / (2 * NT), kxc = (wi / NT) % 2, ct = wi % NT;
-            const int slot = (ys + r + 2) % 3;  // input row ys + r - 1
-            unsigned short* dst = Xs + ((16 * ct + 4 * cgl) * 3 + slot) * WR_KP + 16 * kxc + kxl;
+            const int r = wi / (2 * NT), kxc = (wi / NT) % 2, ct = wi % NT;
+            if (r >= nrow_ld) break;
+            const int slot = (y0 + row0_ld + r + 1) % R;  // input row y0 + row0 + r
+            unsigned short* dst = Xs + ((16 * ct + 4 * cgl) * R + slot) * WR_KP + 16 * kxc + kxl;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) dst[c * 3 * WR_KP] = (unsigned short)((c < 2 ? xr[u].x : xr[u].y) >> (16 * (c & 1)));
+            for (int c = 0; c < 4; ++c) dst[c * R * WR_KP] = (unsigned short)((c < 2 ? xr[u].x : xr[u].y) >> (16 * (c & 1)));
         }
         __syncthreads();
-        if (sg + 1 < se) load_seg();
+        if (sg + 1 < se) load_step();
 #pragma unroll
         for (int qi = 0; qi < QI; ++qi) {
             const int item = wave + 4 * qi;
             const int tap = item % 9, ct = (item / 9) % NT, cm = item / (9 * NT);
             if (item >= NI || ct * 16 >= ncv) continue;  // uniform over the wave
             const int dyy = tap / 3, dx = tap % 3;
-            const int slot = (ys + dyy + 2) % 3;
-            const uint4 av = *reinterpret_cast<const uint4*>(
-                Ps + ((dx * TM + cm) * 16 + (lane & 15)) * WR_KP + (lane >> 4) * 8);
-            const uint4 bv = *reinterpret_cast<const uint4*>(
-                Xs + ((ct * 16 + (lane & 15)) * 3 + slot) * WR_KP + (lane >> 4) * 8);
-            acc[qi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, av), __builtin_bit_cast(bf8v, bv),
-                                                              acc[qi], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < YB; ++j) {
+                const int slot = (y0 + j + dyy) % R;  // input row y0 + j + dy - 1
+                const uint4 av = *reinterpret_cast<const uint4*>(
+                    Ps + (((dx * TM + cm) * 16 + (lane & 15)) * YB + j) * WR_KP + (lane >> 4) * 8);
+                const uint4 bv = *reinterpret_cast<const uint4*>(
+                    Xs + ((ct * 16 + (lane & 15)) * R + slot) * WR_KP + (lane >> 4) * 8);
+                acc[qi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, av),
+                                                                  __builtin_bit_cast(bf8v, bv), acc[qi], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
@@ -718,30 +725,49 @@ __global__ void __launch_bounds__(256) reduce_parts_kernel(const float* __restri
     }
 }
 
-// bias gradient partials: part[chunk][co] = sum_{o in chunk} P[o][co]
+// bias gradient partials: part[chunk][co] = sum_{o in chunk} P[o][co], one
+// pass over dL/dy: thread t takes channel group t % G (4 channels, one 16-byte
+// load) of the voxels o = t / G, t / G + 256 / G, ... (G = Cout / 4), then
+// the threads of a group are summed in a fixed tree order.
 __global__ void __launch_bounds__(256) bias_grad_kernel(const float* __restrict__ dy, const unsigned short* __restrict__ y,
                                                         float slope, long long M, int Cout, long long VC,
                                                         float* __restrict__ part)
 {
-    __shared__ float red[256];
+    __shared__ float red[4][256];
+    const int G = Cout / 4;                  // Cout is a multiple of 4, at most 1024
+    const int T = (256 / G) * G;             // threads in use
+    const int cg = (int)threadIdx.x % G, vs = (int)threadIdx.x / G, nv = 256 / G;
     const long long ob = (long long)blockIdx.x * VC, oe = min(M, ob + VC);
-    for (int co = 0; co < Cout; ++co) {
-        float s = 0.f;
-        for (long long o = ob + threadIdx.x; o < oe; o += 256) {
-            const size_t i = (size_t)o * Cout + co;
-            float v = dy[i];
-            if (y) v *= lrelu_d(y[i], slope);
-            s += __uint_as_float((unsigned)f2bf(v) << 16);  // the same bf16 operand the weight gradient uses
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    if ((int)threadIdx.x < T) {
+        for (long long o = ob + vs; o < oe; o += nv) {
+            const size_t i = (size_t)o * Cout + 4 * cg;
+            const float4 d = *reinterpret_cast<const float4*>(dy + i);
+            const float pv[4] = {d.x, d.y, d.z, d.w};
+            float f[4] = {1.f, 1.f, 1.f, 1.f};
+            if (y) {
+                const s4v yv = ld4bf(y + i);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) f[c] = lrelu_d((unsigned short)yv[c], slope);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c)  // the same bf16 operand the weight gradient uses
+                s[c] += __uint_as_float((unsigned)f2bf(pv[c] * f[c]) << 16);
         }
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * Cout + co] = red[0];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = s[c];
+    __syncthreads();
+    // sum over the voxel slots vs of each group: slot stride G in the thread index
+    for (int h = 1; h < nv; h <<= 1) {  // nv is a power of two (G divides 256 only then is T = 256)
+        if (vs % (2 * h) == 0 && vs + h < nv && (int)threadIdx.x < T)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + h * G];
         __syncthreads();
     }
+    if (vs == 0 && (int)threadIdx.x < G)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) part[(size_t)blockIdx.x * Cout + 4 * cg + c] = red[c][threadIdx.x];
 }
 
 // ------------------------------------------------------------ small kernels --
@@ -918,7 +944,8 @@ ConvWgradPlan conv_wgrad_plan(const ConvGeom& g)
     p.VS = 0;
     if (wgrad_rows(g)) {
         // about 2048 blocks over (chunk, dz, channel chunk)
-        const long long S = (long long)g.N * g.Do * g.Ho * ((g.Wo + WR_SEG - 1) / WR_SEG);
+        const int yb = wgrad_rows_yb((g.Cout + 15) / 16);
+        const long long S = (long long)g.N * g.Do * ((g.Ho + yb - 1) / yb) * ((g.Wo + WR_SEG - 1) / WR_SEG);
         const int ncc = (g.Ca + g.Cb + 4 * wgrad_rows_ng(g) - 1) / (4 * wgrad_rows_ng(g));
         long long want = (2048 + 3 * ncc - 1) / (3 * ncc);
         if (want > S) want = S;
