@@ -301,6 +301,7 @@ typedef struct ffdp_conv_geom {
     int32_t Cout;
     int32_t stride;     /* 1 or 2 */
     int32_t ups;        /* 1: part a is upsampled x2 (Di, Hi, Wi even) */
+    /* N * Di * Hi * Wi below 2^31 (voxel indices are 32-bit) */
 } ffdp_conv_geom;
 
 /* Forward: y[o][co] = act(bias[co] + sum_{t, ci} X[o*stride + t - 1][ci] * w[co][t][ci]).

@@ -667,6 +667,8 @@ int conv_geom(const ffdp_conv_geom* cg, ConvGeom& g, bool need_b_ptr_ok)
         return fail(FFDP_ERR_PARAM, "Ca >= 4, Cb >= 0, Cout >= 4, all multiples of 4 required");
     if (cg->Ca + cg->Cb > 192 || cg->Cout > 128) return fail(FFDP_ERR_PARAM, "Ca + Cb <= 192 and Cout <= 128 required");
     if (cg->ups && ((cg->Di | cg->Hi | cg->Wi) & 1)) return fail(FFDP_ERR_SHAPE, "ups = 1 needs even Di, Hi, Wi");
+    if ((double)cg->N * cg->Di * cg->Hi * cg->Wi >= 2147483648.0)
+        return fail(FFDP_ERR_SHAPE, "N Di Hi Wi must stay below 2^31 voxels");
     (void)need_b_ptr_ok;
     g.N = cg->N; g.Di = cg->Di; g.Hi = cg->Hi; g.Wi = cg->Wi;
     g.stride = cg->stride; g.ups = cg->ups;

@@ -61,24 +61,6 @@ __device__ __forceinline__ s4v pack4(float a, float b, float c, float d)
 
 __device__ __forceinline__ float lrelu_d(unsigned short y, float slope) { return bf2f(y) > 0.0f ? 1.0f : slope; }
 
-// element of the virtual input X (concat of upsampled xa and xb) at input
-// voxel (n, z, y, x), channels c..c+3 (c multiple of 4, within one part)
-__device__ __forceinline__ s4v load_x4(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
-                                       int n, int z, int y, int x, int c)
-{
-    if (c < g.Ca) {
-        if (g.ups) {
-            const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
-            const size_t v = (((size_t)n * Da + (z >> 1)) * Ha + (y >> 1)) * Wa + (x >> 1);
-            return ld4bf(xa + v * g.Ca + c);
-        }
-        const size_t v = (((size_t)n * g.Di + z) * g.Hi + y) * g.Wi + x;
-        return ld4bf(xa + v * g.Ca + c);
-    }
-    const size_t v = (((size_t)n * g.Di + z) * g.Hi + y) * g.Wi + x;
-    return ld4bf(xb + v * g.Cb + (c - g.Ca));
-}
-
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef short s8v __attribute__((ext_vector_type(8)));
 
@@ -159,25 +141,33 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
     const long long m0 = ((long long)blockIdx.x * 4 + wave) * 16;
     const long long m = m0 + (lane & 15);
     const bool mvalid = m < M;
-    int n = 0, zo = 0, yo = 0, xo = 0;
+    int n = 0, zs = 0, ys = 0, xs = 0;  // the row's input corner (tap 0, 0, 0)
     if (mvalid) {
-        long long q = m;
-        xo = (int)(q % g.Wo); q /= g.Wo;
-        yo = (int)(q % g.Ho); q /= g.Ho;
-        zo = (int)(q % g.Do); n = (int)(q / g.Do);
+        const Vox v = vox_of(m, g.Do, g.Ho, g.Wo);
+        n = v.n;
+        zs = v.z * g.stride - 1; ys = v.y * g.stride - 1; xs = v.x * g.stride - 1;
     }
-    auto load_a4 = [&](int k) {  // channels k..k+3 of (tap, channel) index k
+    const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
+    auto load_a4 = [&](int t, int c) {  // channels c..c+3 of tap t (32-bit voxel indices)
         s4v a = s4v{0, 0, 0, 0};
-        if (mvalid && k < K) {
-            const int t = k / Cin, c = k - t * Cin;
-            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            const int zi = zo * g.stride + dz - 1, yi = yo * g.stride + dy - 1, xi = xo * g.stride + dx - 1;
-            if ((unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi && (unsigned)xi < (unsigned)g.Wi)
-                a = load_x4(g, xa, xb, n, zi, yi, xi, c);
+        const int dz = t / 9, dy = (t - 9 * dz) / 3, dx = t - 9 * dz - 3 * dy;
+        const int zi = zs + dz, yi = ys + dy, xi = xs + dx;
+        if (mvalid && t < 27 && (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi &&
+            (unsigned)xi < (unsigned)g.Wi) {
+            if (c < g.Ca) {
+                const unsigned v = g.ups ? ((unsigned)(n * Da + (zi >> 1)) * Ha + (yi >> 1)) * Wa + (xi >> 1)
+                                         : ((unsigned)(n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                a = ld4bf(xa + (size_t)v * g.Ca + c);
+            } else {
+                const unsigned v = ((unsigned)(n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                a = ld4bf(xb + (size_t)v * g.Cb + (c - g.Ca));
+            }
         }
         return a;
     };
     const int kg = (lane >> 4) * 8;
+    // the lane's K index k = (tap t, channel c), advanced by 32 per step
+    int t = kg / Cin, c = kg - t * Cin;
     f4v acc[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
@@ -187,11 +177,13 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < CONV_KC; kk += 32) {
-            const int k = k0 + kk + kg;
-            const bf8v a = cat8(load_a4(k), load_a4(k + 4));
+            const bool wrap = c + 4 >= Cin;  // channels c + 4 .. c + 7 start the next tap (Cin % 4 == 0)
+            const bf8v a = cat8(load_a4(t, c), load_a4(wrap ? t + 1 : t, wrap ? c + 4 - Cin : c + 4));
 #pragma unroll
             for (int j = 0; j < NT; ++j)
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b_from_lds(ws, j, lane, kk), acc[j], 0, 0, 0);
+            c += 32;
+            while (c >= Cin) { c -= Cin; ++t; }
         }
     }
 #pragma unroll
@@ -229,16 +221,13 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
     const bool mvalid = m < M;
     int n = 0, zi = 0, yi = 0, xi = 0;
     if (mvalid) {
-        long long q = m;
-        xi = (int)(q % g.Wi); q /= g.Wi;
-        yi = (int)(q % g.Hi); q /= g.Hi;
-        zi = (int)(q % g.Di); n = (int)(q / g.Di);
+        const Vox v = vox_of(m, g.Di, g.Hi, g.Wi);
+        n = v.n; zi = v.z; yi = v.y; xi = v.x;
     }
-    auto load_p4 = [&](int k) {  // P = dL/dy * act'(y) at output channels k..k+3 of (tap, channel) index k
+    auto load_p4 = [&](int t, int co) {  // P = dL/dy * act'(y) at output channels co..co+3 of tap t
         s4v a = s4v{0, 0, 0, 0};
-        if (mvalid && k < K) {
-            const int t = k / g.Cout, co = k - t * g.Cout;
-            const int dz = t / 9, dyy = (t / 3) % 3, dx_ = t % 3;
+        if (mvalid && t < 27) {
+            const int dz = t / 9, dyy = (t - 9 * dz) / 3, dx_ = t - 9 * dz - 3 * dyy;
             int oz = zi + 1 - dz, oy = yi + 1 - dyy, ox = xi + 1 - dx_;
             bool ok = oz >= 0 && oy >= 0 && ox >= 0;
             if (g.stride == 2) {
@@ -247,7 +236,7 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
             }
             ok = ok && oz < g.Do && oy < g.Ho && ox < g.Wo;
             if (ok) {
-                const size_t o = ((((size_t)n * g.Do + oz) * g.Ho + oy) * g.Wo + ox) * g.Cout + co;
+                const size_t o = (size_t)(((unsigned)(n * g.Do + oz) * g.Ho + oy) * g.Wo + ox) * g.Cout + co;
                 const float4 d4 = *reinterpret_cast<const float4*>(dy + o);
                 float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
                 if (y) {
@@ -260,6 +249,8 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
         return a;
     };
     const int kg = (lane >> 4) * 8;
+    // the lane's K index k = (tap t, output channel c), advanced by 32 per step
+    int t = kg / g.Cout, c = kg - t * g.Cout;
     f4v acc[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
@@ -269,11 +260,13 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < CONV_KC; kk += 32) {
-            const int k = k0 + kk + kg;
-            const bf8v a = cat8(load_p4(k), load_p4(k + 4));
+            const bool wrap = c + 4 >= g.Cout;  // Cout % 4 == 0
+            const bf8v a = cat8(load_p4(t, c), load_p4(wrap ? t + 1 : t, wrap ? c + 4 - g.Cout : c + 4));
 #pragma unroll
             for (int j = 0; j < NT; ++j)
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b_from_lds(ws, j, lane, kk), acc[j], 0, 0, 0);
+            c += 32;
+            while (c >= g.Cout) { c -= g.Cout; ++t; }
         }
     }
 #pragma unroll
