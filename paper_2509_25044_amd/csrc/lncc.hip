@@ -133,6 +133,15 @@ __device__ __forceinline__ unsigned imul(int a, int b)
     return __umul24((unsigned)a, (unsigned)b);
 }
 
+// Two consecutive floats at element offset idx (4-byte aligned: one 8-byte load)
+typedef float lncc_f2a __attribute__((ext_vector_type(2), aligned(4)));
+template <int ADDR>
+__device__ __forceinline__ lncc_f2a ld2(const float* __restrict__ base, unsigned idx)
+{
+    if (ADDR == LNCC_ADDR64) return *reinterpret_cast<const lncc_f2a*>(base + idx);
+    return *reinterpret_cast<const lncc_f2a*>(reinterpret_cast<const char*>(base) + idx * 4u);
+}
+
 // grad_u is written once and not read again here: non-temporal stores
 template <int ADDR>
 __device__ __forceinline__ void st(float* __restrict__ base, unsigned idx, float v)
@@ -169,32 +178,38 @@ __device__ __forceinline__ void issue_point(Pend& g, const float* __restrict__ M
     const float fx = fminf(fmaxf(floorf(ux), -268435456.0f), 268435456.0f);
     const float fy = fminf(fmaxf(floorf(uy), -268435456.0f), 268435456.0f);
     const float fz = fminf(fmaxf(floorf(uz), -268435456.0f), 268435456.0f);
-    g.ax = ux - fx; g.ay = uy - fy; g.az = uz - fz;
+    const float ax = ux - fx;
+    g.ay = uy - fy; g.az = uz - fz;
     const int ix = x + (int)fx, iy = y + (int)fy, iz = z + (int)fz;
-    const int x0 = min(max(ix, 0), W - 1), x1 = min(max(ix + 1, 0), W - 1);
     const int y0 = min(max(iy, 0), H - 1), y1 = min(max(iy + 1, 0), H - 1);
     const int z0 = min(max(iz, 0), D - 1), z1 = min(max(iz + 1, 0), D - 1);
     const unsigned p0 = imul<ADDR>(y0, W), p1 = imul<ADDR>(y1, W);
+    // x corners: one 8-byte load of columns xp, xp + 1 (W >= 2).  A point
+    // clamped at the low border takes the first of the pair (weight 0), at
+    // the high border the second (weight 1, equal to it up to one rounding);
+    // either way its x derivative is zero (flag bit 0).
+    const bool xlo = ix < 0, xhi = ix >= W - 1;
+    const int xp = W >= 2 ? min(max(ix, 0), W - 2) : 0;
+    g.ax = xlo ? 0.0f : (xhi ? 1.0f : ax);
     bool fast = true;
     if (ADDR == LNCC_ADDRWIN)  // both corner slices inside the window, for every lane of the wave
         fast = __builtin_amdgcn_ballot_w64(!((unsigned)(z0 - zb) < (unsigned)zspan &&
                                              (unsigned)(z1 - zb) < (unsigned)zspan)) == 0;
-    if (ADDR != LNCC_ADDRWIN || fast) {
+    if (W >= 2 && (ADDR != LNCC_ADDRWIN || fast)) {  // uniform over the wave
         const unsigned q0 = imul<ADDR>(z0 - zb, HW), q1 = imul<ADDR>(z1 - zb, HW);
-        const unsigned r00 = q0 + p0, r01 = q0 + p1, r10 = q1 + p0, r11 = q1 + p1;
-        g.c[0] = ld<ADDR>(Mb, r00 + x0); g.c[1] = ld<ADDR>(Mb, r00 + x1);
-        g.c[2] = ld<ADDR>(Mb, r01 + x0); g.c[3] = ld<ADDR>(Mb, r01 + x1);
-        g.c[4] = ld<ADDR>(Mb, r10 + x0); g.c[5] = ld<ADDR>(Mb, r10 + x1);
-        g.c[6] = ld<ADDR>(Mb, r11 + x0); g.c[7] = ld<ADDR>(Mb, r11 + x1);
-    } else {
+        const lncc_f2a v00 = ld2<ADDR>(Mb, q0 + p0 + xp), v01 = ld2<ADDR>(Mb, q0 + p1 + xp);
+        const lncc_f2a v10 = ld2<ADDR>(Mb, q1 + p0 + xp), v11 = ld2<ADDR>(Mb, q1 + p1 + xp);
+        g.c[0] = v00.x; g.c[1] = v00.y; g.c[2] = v01.x; g.c[3] = v01.y;
+        g.c[4] = v10.x; g.c[5] = v10.y; g.c[6] = v11.x; g.c[7] = v11.y;
+    } else {  // 64-bit offsets, one float per corner (x1 = xp for a single column)
         const size_t q0 = (size_t)z0 * (size_t)HW, q1 = (size_t)z1 * (size_t)HW;
-        const size_t r00 = q0 + p0, r01 = q0 + p1, r10 = q1 + p0, r11 = q1 + p1;
-        g.c[0] = M[r00 + x0]; g.c[1] = M[r00 + x1];
-        g.c[2] = M[r01 + x0]; g.c[3] = M[r01 + x1];
-        g.c[4] = M[r10 + x0]; g.c[5] = M[r10 + x1];
-        g.c[6] = M[r11 + x0]; g.c[7] = M[r11 + x1];
+        const int x1 = W >= 2 ? xp + 1 : xp;
+        g.c[0] = M[q0 + p0 + xp]; g.c[1] = M[q0 + p0 + x1];
+        g.c[2] = M[q0 + p1 + xp]; g.c[3] = M[q0 + p1 + x1];
+        g.c[4] = M[q1 + p0 + xp]; g.c[5] = M[q1 + p0 + x1];
+        g.c[6] = M[q1 + p1 + xp]; g.c[7] = M[q1 + p1 + x1];
     }
-    g.fl = ((ix == 0 && g.ax == 0.0f) ? 1u : 0u) | ((iy == 0 && g.ay == 0.0f) ? 2u : 0u) |
+    g.fl = ((xlo || xhi || (ix == 0 && ax == 0.0f)) ? 1u : 0u) | ((iy == 0 && g.ay == 0.0f) ? 2u : 0u) |
            ((iz == 0 && g.az == 0.0f) ? 4u : 0u);
 }
 

@@ -116,6 +116,8 @@ __device__ __forceinline__ unsigned long long to_fix(float x)
 // on index 0 (zero derivative there, as trilinear<PAD_BORDER>; the clamped
 // corners make value and derivative right elsewhere).  Zero padding: one
 // validity bit per corner, applied when the values are consumed.
+typedef float mi_f2a __attribute__((ext_vector_type(2), aligned(4)));  // 4-byte aligned pair: one 8-byte load
+
 struct MiPend {
     float c[8];
     float ax, ay, az;
@@ -134,10 +136,29 @@ __device__ __forceinline__ void mi_issue(const MiArgs& a, int x, int y, int z, f
     const float fz = fminf(fmaxf(floorf(dz), -268435456.0f), 268435456.0f);
     g.ax = dx - fx; g.ay = dy - fy; g.az = dz - fz;
     const int ix = x + (int)fx, iy = y + (int)fy, iz = z + (int)fz;
-    const int x0 = min(max(ix, 0), W - 1), x1 = min(max(ix + 1, 0), W - 1);
     const int y0 = min(max(iy, 0), H - 1), y1 = min(max(iy + 1, 0), H - 1);
     const int z0 = min(max(iz, 0), D - 1), z1 = min(max(iz + 1, 0), D - 1);
     const int r00 = (z0 * H + y0) * W, r01 = (z0 * H + y1) * W, r10 = (z1 * H + y0) * W, r11 = (z1 * H + y1) * W;
+    if (PAD == PAD_BORDER && W >= 2) {
+        // x corners: one 8-byte load of columns xp, xp + 1; a point clamped
+        // at the low border takes the first of the pair (weight 0), at the
+        // high border the second (weight 1, equal to it up to one rounding),
+        // with a zero x derivative either way (flag bit 0)
+        const bool xlo = ix < 0, xhi = ix >= W - 1;
+        const int xp = min(max(ix, 0), W - 2);
+        const float ax = g.ax;
+        g.ax = xlo ? 0.0f : (xhi ? 1.0f : ax);
+        const mi_f2a v00 = *reinterpret_cast<const mi_f2a*>(a.M + r00 + xp);
+        const mi_f2a v01 = *reinterpret_cast<const mi_f2a*>(a.M + r01 + xp);
+        const mi_f2a v10 = *reinterpret_cast<const mi_f2a*>(a.M + r10 + xp);
+        const mi_f2a v11 = *reinterpret_cast<const mi_f2a*>(a.M + r11 + xp);
+        g.c[0] = v00.x; g.c[1] = v00.y; g.c[2] = v01.x; g.c[3] = v01.y;
+        g.c[4] = v10.x; g.c[5] = v10.y; g.c[6] = v11.x; g.c[7] = v11.y;
+        g.fl = ((xlo || xhi || (ix == 0 && ax == 0.0f)) ? 1u : 0u) | ((iy == 0 && g.ay == 0.0f) ? 2u : 0u) |
+               ((iz == 0 && g.az == 0.0f) ? 4u : 0u);
+        return;
+    }
+    const int x0 = min(max(ix, 0), W - 1), x1 = min(max(ix + 1, 0), W - 1);
     g.c[0] = a.M[r00 + x0]; g.c[1] = a.M[r00 + x1]; g.c[2] = a.M[r01 + x0]; g.c[3] = a.M[r01 + x1];
     g.c[4] = a.M[r10 + x0]; g.c[5] = a.M[r10 + x1]; g.c[6] = a.M[r11 + x0]; g.c[7] = a.M[r11 + x1];
     if (PAD == PAD_BORDER) {
