@@ -478,9 +478,9 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "lncc_kernel<5,BWD,border> (+1-block loss finalize)",
                      "algorithmic_bytes_per_launch": LNCC_BYTES_PER_VOXEL * nroi,
-                     "limiter": "VALU issue and latency, not HBM bandwidth (rocprofv3 SQ counters: about 500 VALU "
-                                "instructions per ROI voxel on the 1040^3 share and 430 on the 512^3 pair, SIMD VALU "
-                                "busy 0.54)"},
+                     "limiter": "VALU issue and latency, not HBM bandwidth (rocprofv3 SQ counters on the 1040^3 "
+                                "share: about 490 VALU and 18 vector-memory instructions per ROI voxel, SIMD VALU "
+                                "busy 0.62)"},
         "breakdown_ms": {"lncc_fwd_bwd": round(t_lncc, 4), "adam": round(t_adam, 4), "mi_fwd": round(t_mif, 4),
                          "mi_bwd": round(t_mib, 4)},
         "breakdown_hbm_frac": {
