@@ -184,31 +184,44 @@ __device__ __forceinline__ void issue_point(Pend& g, const float* __restrict__ M
     const int y0 = min(max(iy, 0), H - 1), y1 = min(max(iy + 1, 0), H - 1);
     const int z0 = min(max(iz, 0), D - 1), z1 = min(max(iz + 1, 0), D - 1);
     const unsigned p0 = imul<ADDR>(y0, W), p1 = imul<ADDR>(y1, W);
-    // x corners: one 8-byte load of columns xp, xp + 1 (W >= 2).  A point
-    // clamped at the low border takes the first of the pair (weight 0), at
-    // the high border the second (weight 1, equal to it up to one rounding);
-    // either way its x derivative is zero (flag bit 0).
+    if (ADDR == LNCC_ADDR64) {  // also every width-1 volume: one float per corner
+        const int x0 = min(max(ix, 0), W - 1), x1 = min(max(ix + 1, 0), W - 1);
+        const size_t q0 = (size_t)z0 * (size_t)HW, q1 = (size_t)z1 * (size_t)HW;
+        g.ax = ax;
+        g.c[0] = M[q0 + p0 + x0]; g.c[1] = M[q0 + p0 + x1];
+        g.c[2] = M[q0 + p1 + x0]; g.c[3] = M[q0 + p1 + x1];
+        g.c[4] = M[q1 + p0 + x0]; g.c[5] = M[q1 + p0 + x1];
+        g.c[6] = M[q1 + p1 + x0]; g.c[7] = M[q1 + p1 + x1];
+        g.fl = ((ix == 0 && ax == 0.0f) ? 1u : 0u) | ((iy == 0 && g.ay == 0.0f) ? 2u : 0u) |
+               ((iz == 0 && g.az == 0.0f) ? 4u : 0u);
+        return;
+    }
+    // x corners: one 8-byte load of columns xp, xp + 1 (the planner takes
+    // these forms only for W >= 2).  A point clamped at the low border takes
+    // the first of the pair (weight 0), at the high border the second
+    // (weight 1, equal to it up to one rounding); either way its x
+    // derivative is zero (flag bit 0).
     const bool xlo = ix < 0, xhi = ix >= W - 1;
-    const int xp = W >= 2 ? min(max(ix, 0), W - 2) : 0;
+    const int xp = min(max(ix, 0), W - 2);
     g.ax = xlo ? 0.0f : (xhi ? 1.0f : ax);
     bool fast = true;
     if (ADDR == LNCC_ADDRWIN)  // both corner slices inside the window, for every lane of the wave
         fast = __builtin_amdgcn_ballot_w64(!((unsigned)(z0 - zb) < (unsigned)zspan &&
                                              (unsigned)(z1 - zb) < (unsigned)zspan)) == 0;
-    if (W >= 2 && (ADDR != LNCC_ADDRWIN || fast)) {  // uniform over the wave
+    lncc_f2a v00, v01, v10, v11;
+    if (ADDR != LNCC_ADDRWIN || fast) {
         const unsigned q0 = imul<ADDR>(z0 - zb, HW), q1 = imul<ADDR>(z1 - zb, HW);
-        const lncc_f2a v00 = ld2<ADDR>(Mb, q0 + p0 + xp), v01 = ld2<ADDR>(Mb, q0 + p1 + xp);
-        const lncc_f2a v10 = ld2<ADDR>(Mb, q1 + p0 + xp), v11 = ld2<ADDR>(Mb, q1 + p1 + xp);
-        g.c[0] = v00.x; g.c[1] = v00.y; g.c[2] = v01.x; g.c[3] = v01.y;
-        g.c[4] = v10.x; g.c[5] = v10.y; g.c[6] = v11.x; g.c[7] = v11.y;
-    } else {  // 64-bit offsets, one float per corner (x1 = xp for a single column)
+        v00 = ld2<ADDR>(Mb, q0 + p0 + xp); v01 = ld2<ADDR>(Mb, q0 + p1 + xp);
+        v10 = ld2<ADDR>(Mb, q1 + p0 + xp); v11 = ld2<ADDR>(Mb, q1 + p1 + xp);
+    } else {  // a corner slice outside the window: 64-bit offsets
         const size_t q0 = (size_t)z0 * (size_t)HW, q1 = (size_t)z1 * (size_t)HW;
-        const int x1 = W >= 2 ? xp + 1 : xp;
-        g.c[0] = M[q0 + p0 + xp]; g.c[1] = M[q0 + p0 + x1];
-        g.c[2] = M[q0 + p1 + xp]; g.c[3] = M[q0 + p1 + x1];
-        g.c[4] = M[q1 + p0 + xp]; g.c[5] = M[q1 + p0 + x1];
-        g.c[6] = M[q1 + p1 + xp]; g.c[7] = M[q1 + p1 + x1];
+        v00 = *reinterpret_cast<const lncc_f2a*>(M + (q0 + p0 + xp));
+        v01 = *reinterpret_cast<const lncc_f2a*>(M + (q0 + p1 + xp));
+        v10 = *reinterpret_cast<const lncc_f2a*>(M + (q1 + p0 + xp));
+        v11 = *reinterpret_cast<const lncc_f2a*>(M + (q1 + p1 + xp));
     }
+    g.c[0] = v00.x; g.c[1] = v00.y; g.c[2] = v01.x; g.c[3] = v01.y;
+    g.c[4] = v10.x; g.c[5] = v10.y; g.c[6] = v11.x; g.c[7] = v11.y;
     g.fl = ((xlo || xhi || (ix == 0 && ax == 0.0f)) ? 1u : 0u) | ((iy == 0 && g.ay == 0.0f) ? 2u : 0u) |
            ((iz == 0 && g.az == 0.0f) ? 4u : 0u);
 }
@@ -347,19 +360,17 @@ lncc_kernel(LnccArgs a)
     // slice zi+2 are in flight, so HBM and L2 latency overlaps the LDS
     // stages.  Every load is in bounds (slice index clamped, off-array
     // points read voxel 0, corner indices clamped) and results are selected
-    // when consumed.  With several halo points per thread (w >= 7, ALLH),
-    // lanes without one also sample (voxel 0, in bounds) and only skip the
-    // LDS writes: branching around their loads makes the compiler copy the
-    // pending registers of the skipped lanes (measured: w = 7 adjoint 4%
-    // faster without the branch; at w = 5 the branch is 7% faster).
-    constexpr bool ALLH = T::PH > 1;
+    // when consumed.  Lanes without a halo point also sample (voxel 0, in
+    // bounds) and only skip the LDS writes: branching around their loads
+    // makes the compiler merge the pending registers of the skipped lanes
+    // after the loads, which waits for the loads just issued (measured: the
+    // w = 5 adjoint 10% faster on the 512^3 pair, w = 7 4%).
     float pu[P][3];
     Pend pend[P];
     auto load_u = [&](int zs, int k0, int k1) {
         const unsigned zoff = imul<ADDR>(min(max(zs, 0), D - 1) - zb, HW);
 #pragma unroll
         for (int k = k0; k < k1; ++k) {
-            if (!ALLH && k > 0 && hx[k - 1] < 0) continue;
             if (U) {
                 pu[k][0] = ld<ADDR>(U0, zoff + pxy[k]);
                 pu[k][1] = ld<ADDR>(U1, zoff + pxy[k]);
@@ -373,9 +384,8 @@ lncc_kernel(LnccArgs a)
         const unsigned zoff = imul<ADDR>(min(max(zs, 0), D - 1) - zb, HW);
 #pragma unroll
         for (int k = k0; k < k1; ++k)
-            if (ALLH || k == 0 || hx[k - 1] >= 0)
-                issue_point<PAD, ADDR>(pend[k], M, Mb, Fb, D, H, W, HW, zb, a.zspan, pgx[k], pgy[k], zs,
-                                       zoff + pxy[k], pu[k][0], pu[k][1], pu[k][2]);
+            issue_point<PAD, ADDR>(pend[k], M, Mb, Fb, D, H, W, HW, zb, a.zspan, pgx[k], pgy[k], zs,
+                                   zoff + pxy[k], pu[k][0], pu[k][1], pu[k][2]);
     };
     // Schedule: the gathers of slice zi+1 are issued at the end of stage A of
     // slice zi, from u loaded two slices ahead.  Forward and ANTs kernels load
@@ -410,7 +420,7 @@ lncc_kernel(LnccArgs a)
 #pragma unroll
             for (int k = 0; k < P; ++k) {
                 const bool act = k == 0 || hx[k - 1] >= 0;
-                if (ALLH || act) {
+                {
                     const bool ok = zin && pin[k];
                     float f = -sF, m = -sM;  // padded voxels are 0 before the shift
                     float d0 = 0.f, d1 = 0.f, d2 = 0.f;
@@ -676,9 +686,9 @@ LnccLaunch lncc_plan(int D, int H, int W, int win, int mode)
     const bool fit24 = D < (1 << 24) && HW < (1 << 24);
     const long long span = 4294967295LL / (4 * HW);  // whole slices within 4 GB of a base
     L.zspan = (int)min(span, (long long)D);
-    if (fit24 && N * 4 <= 4294967295LL) L.addr = LNCC_ADDR32;
-    else if (fit24 && span >= L.zchunk + 2 * R2 + 4) L.addr = LNCC_ADDRWIN;
-    else L.addr = LNCC_ADDR64;
+    if (W >= 2 && fit24 && N * 4 <= 4294967295LL) L.addr = LNCC_ADDR32;
+    else if (W >= 2 && fit24 && span >= L.zchunk + 2 * R2 + 4) L.addr = LNCC_ADDRWIN;
+    else L.addr = LNCC_ADDR64;  // also width-1 volumes (no x pairs)
     return L;
 }
 

@@ -37,6 +37,10 @@
 
 namespace ffdp {
 
+// Border padding of a volume one column wide: the x corners are loaded one
+// by one (PAD_BORDER loads them as one 8-byte pair, which needs W >= 2).
+constexpr int MI_PAD_BORDER1 = 2;
+
 // Hard bin min(floor(v B), B-1) of a value v in [0, 1], taken on the exact
 // product v B rather than its fp32 rounding: p = fl(v B) and its residual
 // fma(v, B, -p) is exact, so floor(v B) = floor(p) except where p is an
@@ -139,7 +143,7 @@ __device__ __forceinline__ void mi_issue(const MiArgs& a, int x, int y, int z, f
     const int y0 = min(max(iy, 0), H - 1), y1 = min(max(iy + 1, 0), H - 1);
     const int z0 = min(max(iz, 0), D - 1), z1 = min(max(iz + 1, 0), D - 1);
     const int r00 = (z0 * H + y0) * W, r01 = (z0 * H + y1) * W, r10 = (z1 * H + y0) * W, r11 = (z1 * H + y1) * W;
-    if (PAD == PAD_BORDER && W >= 2) {
+    if (PAD == PAD_BORDER) {  // W >= 2 (single columns run MI_PAD_BORDER1)
         // x corners: one 8-byte load of columns xp, xp + 1; a point clamped
         // at the low border takes the first of the pair (weight 0), at the
         // high border the second (weight 1, equal to it up to one rounding),
@@ -161,7 +165,7 @@ __device__ __forceinline__ void mi_issue(const MiArgs& a, int x, int y, int z, f
     const int x0 = min(max(ix, 0), W - 1), x1 = min(max(ix + 1, 0), W - 1);
     g.c[0] = a.M[r00 + x0]; g.c[1] = a.M[r00 + x1]; g.c[2] = a.M[r01 + x0]; g.c[3] = a.M[r01 + x1];
     g.c[4] = a.M[r10 + x0]; g.c[5] = a.M[r10 + x1]; g.c[6] = a.M[r11 + x0]; g.c[7] = a.M[r11 + x1];
-    if (PAD == PAD_BORDER) {
+    if (PAD == MI_PAD_BORDER1) {
         g.fl = ((ix == 0 && g.ax == 0.0f) ? 1u : 0u) | ((iy == 0 && g.ay == 0.0f) ? 2u : 0u) |
                ((iz == 0 && g.az == 0.0f) ? 4u : 0u);
     } else {
@@ -191,8 +195,8 @@ __device__ __forceinline__ Tri mi_interp(const MiPend& g)
     Tri t;
     t.v = fmaf(g.az, c1 - c0, c0);
     if (DERIV) {
-        const bool bx = PAD == PAD_BORDER && (g.fl & 1u), by = PAD == PAD_BORDER && (g.fl & 2u);
-        const bool bz = PAD == PAD_BORDER && (g.fl & 4u);
+        const bool bx = PAD != PAD_ZEROS && (g.fl & 1u), by = PAD != PAD_ZEROS && (g.fl & 2u);
+        const bool bz = PAD != PAD_ZEROS && (g.fl & 4u);
         const float gx0 = fmaf(g.ay, e01 - e00, e00), gx1 = fmaf(g.ay, e11 - e10, e10);
         t.dx = bx ? 0.0f : fmaf(g.az, gx1 - gx0, gx0);
         t.dy = by ? 0.0f : fmaf(g.az, f1 - f0, f0);
@@ -630,6 +634,7 @@ static hipError_t mi_fwd_dispatch(const MiArgs& a, int hard, int pad, unsigned l
     if (hard == 2) {
         const size_t lds32 = sizeof(unsigned int) * a.ncopy * (BB + 1);
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_count_kernel<PAD_BORDER, AFF>), grid, block, lds32, st, a, hist, flag);
+        else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_count_kernel<MI_PAD_BORDER1, AFF>), grid, block, lds32, st, a, hist, flag);
         else hipLaunchKernelGGL((mi_count_kernel<PAD_ZEROS, AFF>), grid, block, lds32, st, a, hist, flag);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -640,16 +645,20 @@ static hipError_t mi_fwd_dispatch(const MiArgs& a, int hard, int pad, unsigned l
     if (a.ncopy == 0) {
         if (hard) {
             if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER, AFF, true>), grid, block, 0, st, a, hist, flag);
+            else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_hist_kernel<true, MI_PAD_BORDER1, AFF, true>), grid, block, 0, st, a, hist, flag);
             else hipLaunchKernelGGL((mi_hist_kernel<true, PAD_ZEROS, AFF, true>), grid, block, 0, st, a, hist, flag);
         } else {
             if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<false, PAD_BORDER, AFF, true>), grid, block, 0, st, a, hist, flag);
+            else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_hist_kernel<false, MI_PAD_BORDER1, AFF, true>), grid, block, 0, st, a, hist, flag);
             else hipLaunchKernelGGL((mi_hist_kernel<false, PAD_ZEROS, AFF, true>), grid, block, 0, st, a, hist, flag);
         }
     } else if (hard) {
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER, AFF, false>), grid, block, lds, st, a, hist, flag);
+        else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_hist_kernel<true, MI_PAD_BORDER1, AFF, false>), grid, block, lds, st, a, hist, flag);
         else hipLaunchKernelGGL((mi_hist_kernel<true, PAD_ZEROS, AFF, false>), grid, block, lds, st, a, hist, flag);
     } else {
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<false, PAD_BORDER, AFF, false>), grid, block, lds, st, a, hist, flag);
+        else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_hist_kernel<false, MI_PAD_BORDER1, AFF, false>), grid, block, lds, st, a, hist, flag);
         else hipLaunchKernelGGL((mi_hist_kernel<false, PAD_ZEROS, AFF, false>), grid, block, lds, st, a, hist, flag);
     }
     hipError_t e = hipGetLastError();
@@ -676,8 +685,9 @@ hipError_t mi_fwd_launch(const MiArgs& a0, int hard, int pad, unsigned long long
     hipLaunchKernelGGL(mi_zero, dim3((BB + 1 + 255) / 256), dim3(256), 0, st, hist, BB + 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return a.affine ? mi_fwd_dispatch<true>(a, hard, pad, hist, flag, state, loss, st)
-                    : mi_fwd_dispatch<false>(a, hard, pad, hist, flag, state, loss, st);
+    const int p = (pad == PAD_BORDER && a.W < 2) ? MI_PAD_BORDER1 : pad;
+    return a.affine ? mi_fwd_dispatch<true>(a, hard, p, hist, flag, state, loss, st)
+                    : mi_fwd_dispatch<false>(a, hard, p, hist, flag, state, loss, st);
 }
 
 template <bool AFF>
@@ -689,12 +699,15 @@ static hipError_t mi_bwd_dispatch(const MiArgs& a, int hard, int pad, const floa
     dim3 grid(a.nblocks), block(MI_NT);
     if (hard == 1) {  // box kernel: zero gradient, the table is not read
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<true, PAD_BORDER, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
+        else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_grad_kernel<true, MI_PAD_BORDER1, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
         else hipLaunchKernelGGL((mi_grad_kernel<true, PAD_ZEROS, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
     } else if (ldst) {
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<false, PAD_BORDER, AFF, true>), grid, block, lds, st, a, state, grad_scale, nin, gu);
+        else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_grad_kernel<false, MI_PAD_BORDER1, AFF, true>), grid, block, lds, st, a, state, grad_scale, nin, gu);
         else hipLaunchKernelGGL((mi_grad_kernel<false, PAD_ZEROS, AFF, true>), grid, block, lds, st, a, state, grad_scale, nin, gu);
     } else {
         if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<false, PAD_BORDER, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
+        else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_grad_kernel<false, MI_PAD_BORDER1, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
         else hipLaunchKernelGGL((mi_grad_kernel<false, PAD_ZEROS, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
     }
     return hipGetLastError();
@@ -704,8 +717,9 @@ hipError_t mi_bwd_launch(const MiArgs& a, int hard, int pad, const float* state,
                          float* gu, double nroi, hipStream_t st)
 {
     const float nin = (float)(-1.0 / nroi);
-    return a.affine ? mi_bwd_dispatch<true>(a, hard, pad, state, grad_scale, nin, gu, st)
-                    : mi_bwd_dispatch<false>(a, hard, pad, state, grad_scale, nin, gu, st);
+    const int p = (pad == PAD_BORDER && a.W < 2) ? MI_PAD_BORDER1 : pad;
+    return a.affine ? mi_bwd_dispatch<true>(a, hard, p, state, grad_scale, nin, gu, st)
+                    : mi_bwd_dispatch<false>(a, hard, p, state, grad_scale, nin, gu, st);
 }
 
 }  // namespace ffdp

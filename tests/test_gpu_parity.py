@@ -210,7 +210,7 @@ def test_lncc_wide_window_clinical_samples(c2):
     assert_loss(l_gpu, l_ref, "clinical w15 sub-ROI")
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (2, 40, 3), (37, 45, 70), (20, 17, 130)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (6, 7, 1), (6, 7, 2), (3, 5, 7), (2, 40, 3), (37, 45, 70), (20, 17, 130)])
 def test_lncc_ragged_shapes(shape):
     F, M, u = _rand_case(shape, 130)
     _lncc_case(F, M, u, window=5, eps=1e-3, what="ragged")
@@ -436,7 +436,7 @@ def test_checked_mode(c1):
     refused(lambda: ops.warp_lncc_fwd(C, C, None, eps=0.0, check_finite=True))
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (37, 45, 70)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 9, 1), (4, 6, 2), (3, 5, 7), (37, 45, 70)])
 def test_mi_ragged_shapes(shape):
     F, M, u = _rand_case(shape, 140)
     _mi_case(F, M, u, bins=16, what="ragged")
