@@ -540,19 +540,26 @@ __global__ void __launch_bounds__(1024) mi_finalize(const unsigned long long* __
     }
 }
 
-// LDST: the log table is staged in LDS (B <= MI_LDS_TABLE_BINS); larger
-// tables are read from the state through the caches.  (Compile-time, so the
-// table reads are LDS or global loads, never flat.)
-template <bool HARD, int PAD, bool AFF, bool LDST>
+// TP > 0: the log table is staged in LDS, padded (B <= MI_LDS_TABLE_BINS);
+// TP = 0: larger tables are read from the state through the caches.
+// (Compile-time, so the table reads are LDS or global loads, never flat.)
+template <bool HARD, int PAD, bool AFF, int TP>
 __global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* __restrict__ state,
                                                         const float* __restrict__ grad_scale, float neg_inv_nroi,
                                                         float* __restrict__ gu)
 {
-    extern __shared__ float Ts[];  // [B*B] when LDST
-    const int B = a.bins, BB = B * B;
-    for (int q = threadIdx.x; LDST && q < BB; q += MI_NT) Ts[q] = state[q];
+    // TP > 0: the log table in LDS with 2 entries of padding on every side
+    // and row pitch TP >= B + 4, Tp[(m + 2) TP + n + 2] = T[fold(m)][fold(n)]
+    // for m, n in [-2, B + 1], so that the 4 x 4 lookups of a voxel need no
+    // folding and sit at compile-time offsets from one address.  TP = 0: T
+    // read from global memory with folded indices.
+    extern __shared__ float Ts[];  // [TP * TP] when TP > 0
+    const int B = a.bins;
+    for (int q = threadIdx.x; TP > 0 && q < TP * TP; q += MI_NT) {
+        const int m = q / TP - 2, n = q % TP - 2;
+        Ts[q] = (m < B + 2 && n < B + 2) ? state[fold(m, B) * B + fold(n, B)] : 0.0f;
+    }
     __syncthreads();
-    const float* __restrict__ T = LDST ? Ts : state;
     const float g = neg_inv_nroi * (grad_scale ? *grad_scale : 1.0f);
 
     const int bid = xcd_remap(blockIdx.x, a.nblocks);
@@ -581,13 +588,24 @@ __global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* _
             parzen4<false, false>(cur.f, B, jf, wf, dd);
             parzen4<false, true>(t.v, B, jm, wm, dm);
             float S = 0.0f;
+            if (TP > 0) {
+                const float* base = Ts + (jf + 2) * TP + (jm + 2);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float* row = T + fold(jf + i, B) * B;
-                float si = 0.0f;
+                for (int i = 0; i < 4; ++i) {
+                    float si = 0.0f;
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) si = fmaf(dm[jj], row[fold(jm + jj, B)], si);
-                S = fmaf(wf[i], si, S);
+                    for (int jj = 0; jj < 4; ++jj) si = fmaf(dm[jj], base[i * TP + jj], si);
+                    S = fmaf(wf[i], si, S);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float* row = state + fold(jf + i, B) * B;
+                    float si = 0.0f;
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) si = fmaf(dm[jj], row[fold(jm + jj, B)], si);
+                    S = fmaf(wf[i], si, S);
+                }
             }
             const float gm = g * S;
             g0 = gm * t.dx; g1 = gm * t.dy; g2 = gm * t.dz;
@@ -690,26 +708,36 @@ hipError_t mi_fwd_launch(const MiArgs& a0, int hard, int pad, unsigned long long
                     : mi_fwd_dispatch<false>(a, hard, p, hist, flag, state, loss, st);
 }
 
+template <bool HARD, bool AFF, int TP>
+static void mi_grad_launch_pad(int pad, dim3 grid, size_t lds, hipStream_t st, const MiArgs& a, const float* state,
+                               const float* grad_scale, float nin, float* gu)
+{
+    if (pad == PAD_BORDER)
+        hipLaunchKernelGGL((mi_grad_kernel<HARD, PAD_BORDER, AFF, TP>), grid, dim3(MI_NT), lds, st, a, state, grad_scale, nin, gu);
+    else if (pad == MI_PAD_BORDER1)
+        hipLaunchKernelGGL((mi_grad_kernel<HARD, MI_PAD_BORDER1, AFF, TP>), grid, dim3(MI_NT), lds, st, a, state, grad_scale, nin, gu);
+    else
+        hipLaunchKernelGGL((mi_grad_kernel<HARD, PAD_ZEROS, AFF, TP>), grid, dim3(MI_NT), lds, st, a, state, grad_scale, nin, gu);
+}
+
+// The padded LDS table pitch: the smallest of 36, 68, 132 that holds B + 4
+// columns (B <= 128); larger tables are read from global memory.
 template <bool AFF>
 static hipError_t mi_bwd_dispatch(const MiArgs& a, int hard, int pad, const float* state, const float* grad_scale,
                                   float nin, float* gu, hipStream_t st)
 {
-    const bool ldst = a.bins <= MI_LDS_TABLE_BINS;
-    const size_t lds = ldst ? sizeof(float) * a.bins * a.bins : 0;
-    dim3 grid(a.nblocks), block(MI_NT);
-    if (hard == 1) {  // box kernel: zero gradient, the table is not read
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<true, PAD_BORDER, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
-        else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_grad_kernel<true, MI_PAD_BORDER1, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
-        else hipLaunchKernelGGL((mi_grad_kernel<true, PAD_ZEROS, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
-    } else if (ldst) {
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<false, PAD_BORDER, AFF, true>), grid, block, lds, st, a, state, grad_scale, nin, gu);
-        else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_grad_kernel<false, MI_PAD_BORDER1, AFF, true>), grid, block, lds, st, a, state, grad_scale, nin, gu);
-        else hipLaunchKernelGGL((mi_grad_kernel<false, PAD_ZEROS, AFF, true>), grid, block, lds, st, a, state, grad_scale, nin, gu);
-    } else {
-        if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_grad_kernel<false, PAD_BORDER, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
-        else if (pad == MI_PAD_BORDER1) hipLaunchKernelGGL((mi_grad_kernel<false, MI_PAD_BORDER1, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
-        else hipLaunchKernelGGL((mi_grad_kernel<false, PAD_ZEROS, AFF, false>), grid, block, 0, st, a, state, grad_scale, nin, gu);
-    }
+    const int B = a.bins;
+    const dim3 grid(a.nblocks);
+    if (hard == 1)  // box kernel: zero gradient, the table is not read
+        mi_grad_launch_pad<true, AFF, 0>(pad, grid, 0, st, a, state, grad_scale, nin, gu);
+    else if (B + 4 <= 36)
+        mi_grad_launch_pad<false, AFF, 36>(pad, grid, sizeof(float) * 36 * 36, st, a, state, grad_scale, nin, gu);
+    else if (B + 4 <= 68)
+        mi_grad_launch_pad<false, AFF, 68>(pad, grid, sizeof(float) * 68 * 68, st, a, state, grad_scale, nin, gu);
+    else if (B <= MI_LDS_TABLE_BINS)
+        mi_grad_launch_pad<false, AFF, 132>(pad, grid, sizeof(float) * 132 * 132, st, a, state, grad_scale, nin, gu);
+    else
+        mi_grad_launch_pad<false, AFF, 0>(pad, grid, 0, st, a, state, grad_scale, nin, gu);
     return hipGetLastError();
 }
 
