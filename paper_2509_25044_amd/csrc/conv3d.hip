@@ -126,7 +126,9 @@ __device__ __forceinline__ bf8v b_from_lds(const unsigned short* __restrict__ ws
 }
 
 // ---------------------------------------------------------------- forward --
-template <int NT>
+// C8: Ca and Cb are multiples of 8, so a lane's 8 K elements are 8
+// contiguous channels of one tap and one 16-byte load.
+template <int NT, bool C8>
 __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
                                                        const unsigned short* __restrict__ xb,
                                                        const unsigned short* __restrict__ w,
@@ -165,6 +167,23 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
         }
         return a;
     };
+    auto load_a8 = [&](int t, int c) {  // channels c..c+7 of tap t (C8)
+        uint4 a = make_uint4(0u, 0u, 0u, 0u);
+        const int dz = t / 9, dy = (t - 9 * dz) / 3, dx = t - 9 * dz - 3 * dy;
+        const int zi = zs + dz, yi = ys + dy, xi = xs + dx;
+        if (mvalid && t < 27 && (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi &&
+            (unsigned)xi < (unsigned)g.Wi) {
+            if (c < g.Ca) {
+                const unsigned v = g.ups ? ((unsigned)(n * Da + (zi >> 1)) * Ha + (yi >> 1)) * Wa + (xi >> 1)
+                                         : ((unsigned)(n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                a = *reinterpret_cast<const uint4*>(xa + (size_t)v * g.Ca + c);
+            } else {
+                const unsigned v = ((unsigned)(n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                a = *reinterpret_cast<const uint4*>(xb + (size_t)v * g.Cb + (c - g.Ca));
+            }
+        }
+        return __builtin_bit_cast(bf8v, a);
+    };
     const int kg = (lane >> 4) * 8;
     // the lane's K index k = (tap t, channel c), advanced by 32 per step
     int t = kg / Cin, c = kg - t * Cin;
@@ -177,8 +196,13 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < CONV_KC; kk += 32) {
-            const bool wrap = c + 4 >= Cin;  // channels c + 4 .. c + 7 start the next tap (Cin % 4 == 0)
-            const bf8v a = cat8(load_a4(t, c), load_a4(wrap ? t + 1 : t, wrap ? c + 4 - Cin : c + 4));
+            bf8v a;
+            if (C8) {
+                a = load_a8(t, c);
+            } else {
+                const bool wrap = c + 4 >= Cin;  // channels c + 4 .. c + 7 start the next tap (Cin % 4 == 0)
+                a = cat8(load_a4(t, c), load_a4(wrap ? t + 1 : t, wrap ? c + 4 - Cin : c + 4));
+            }
 #pragma unroll
             for (int j = 0; j < NT; ++j)
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b_from_lds(ws, j, lane, kk), acc[j], 0, 0, 0);
@@ -205,7 +229,9 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
 // ----------------------------------------------------------- backward data --
 // dX over the virtual (concatenated, fine-resolution) input, fp32 [N][Di][Hi][Wi][Cin];
 // accumulate = 1 adds to dX.  wt is the weight in [Cin][27][Cout] order.
-template <int NT>
+// C8: Cout is a multiple of 8, so a lane's 8 K elements are 8 contiguous
+// output channels of one tap (two 16-byte loads of dL/dy, one of y).
+template <int NT, bool C8>
 __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const float* __restrict__ dy,
                                                             const unsigned short* __restrict__ y, float slope,
                                                             const unsigned short* __restrict__ wt,
@@ -224,29 +250,52 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
         const Vox v = vox_of(m, g.Di, g.Hi, g.Wi);
         n = v.n; zi = v.z; yi = v.y; xi = v.x;
     }
+    // element offset of P at output channel co of tap t, or -1 where the tap
+    // reaches no output voxel (a non-integer or out-of-range output index)
+    auto p_offset = [&](int t, int co) -> long long {
+        if (!mvalid || t >= 27) return -1;
+        const int dz = t / 9, dyy = (t - 9 * dz) / 3, dx_ = t - 9 * dz - 3 * dyy;
+        int oz = zi + 1 - dz, oy = yi + 1 - dyy, ox = xi + 1 - dx_;
+        bool ok = oz >= 0 && oy >= 0 && ox >= 0;
+        if (g.stride == 2) {
+            ok = ok && !(oz & 1) && !(oy & 1) && !(ox & 1);
+            oz >>= 1; oy >>= 1; ox >>= 1;
+        }
+        ok = ok && oz < g.Do && oy < g.Ho && ox < g.Wo;
+        return ok ? (long long)(((unsigned)(n * g.Do + oz) * g.Ho + oy) * g.Wo + ox) * g.Cout + co : -1;
+    };
     auto load_p4 = [&](int t, int co) {  // P = dL/dy * act'(y) at output channels co..co+3 of tap t
         s4v a = s4v{0, 0, 0, 0};
-        if (mvalid && t < 27) {
-            const int dz = t / 9, dyy = (t - 9 * dz) / 3, dx_ = t - 9 * dz - 3 * dyy;
-            int oz = zi + 1 - dz, oy = yi + 1 - dyy, ox = xi + 1 - dx_;
-            bool ok = oz >= 0 && oy >= 0 && ox >= 0;
-            if (g.stride == 2) {
-                ok = ok && !(oz & 1) && !(oy & 1) && !(ox & 1);
-                oz >>= 1; oy >>= 1; ox >>= 1;
+        const long long o = p_offset(t, co);
+        if (o >= 0) {
+            const float4 d4 = *reinterpret_cast<const float4*>(dy + o);
+            float f[4] = {1.f, 1.f, 1.f, 1.f};
+            if (y) {
+                const s4v yv = ld4bf(y + o);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) f[q] = lrelu_d((unsigned short)yv[q], slope);
             }
-            ok = ok && oz < g.Do && oy < g.Ho && ox < g.Wo;
-            if (ok) {
-                const size_t o = (size_t)(((unsigned)(n * g.Do + oz) * g.Ho + oy) * g.Wo + ox) * g.Cout + co;
-                const float4 d4 = *reinterpret_cast<const float4*>(dy + o);
-                float s0 = 1.f, s1 = 1.f, s2 = 1.f, s3 = 1.f;
-                if (y) {
-                    s0 = lrelu_d(y[o], slope); s1 = lrelu_d(y[o + 1], slope);
-                    s2 = lrelu_d(y[o + 2], slope); s3 = lrelu_d(y[o + 3], slope);
-                }
-                a = pack4(d4.x * s0, d4.y * s1, d4.z * s2, d4.w * s3);
-            }
+            a = pack4(d4.x * f[0], d4.y * f[1], d4.z * f[2], d4.w * f[3]);
         }
         return a;
+    };
+    auto load_p8 = [&](int t, int co) {  // channels co..co+7 of tap t (C8)
+        s4v lo = s4v{0, 0, 0, 0}, hi = s4v{0, 0, 0, 0};
+        const long long o = p_offset(t, co);
+        if (o >= 0) {
+            const float4 d0 = *reinterpret_cast<const float4*>(dy + o);
+            const float4 d1 = *reinterpret_cast<const float4*>(dy + o + 4);
+            float f[8] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
+            if (y) {
+                const uint4 yv = *reinterpret_cast<const uint4*>(y + o);
+                const unsigned yw[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+                for (int q = 0; q < 8; ++q) f[q] = lrelu_d((unsigned short)(yw[q >> 1] >> (16 * (q & 1))), slope);
+            }
+            lo = pack4(d0.x * f[0], d0.y * f[1], d0.z * f[2], d0.w * f[3]);
+            hi = pack4(d1.x * f[4], d1.y * f[5], d1.z * f[6], d1.w * f[7]);
+        }
+        return cat8(lo, hi);
     };
     const int kg = (lane >> 4) * 8;
     // the lane's K index k = (tap t, output channel c), advanced by 32 per step
@@ -260,8 +309,13 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < CONV_KC; kk += 32) {
-            const bool wrap = c + 4 >= g.Cout;  // Cout % 4 == 0
-            const bf8v a = cat8(load_p4(t, c), load_p4(wrap ? t + 1 : t, wrap ? c + 4 - g.Cout : c + 4));
+            bf8v a;
+            if (C8) {
+                a = load_p8(t, c);
+            } else {
+                const bool wrap = c + 4 >= g.Cout;  // Cout % 4 == 0
+                a = cat8(load_p4(t, c), load_p4(wrap ? t + 1 : t, wrap ? c + 4 - g.Cout : c + 4));
+            }
 #pragma unroll
             for (int j = 0; j < NT; ++j)
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b_from_lds(ws, j, lane, kk), acc[j], 0, 0, 0);
@@ -890,6 +944,17 @@ static unsigned grid_for(long long n, int per = 256, long long cap = 16384)
     return (unsigned)b;
 }
 
+template <bool C8>
+static void launch_fwd(int nt, unsigned blocks, hipStream_t st, const ConvGeom& g, const unsigned short* xa,
+                       const unsigned short* xb, const unsigned short* w, const float* bias, int act, float slope,
+                       unsigned short* ybf, float* yf)
+{
+    if (nt <= 1) hipLaunchKernelGGL((conv_fwd_kernel<1, C8>), dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else if (nt <= 2) hipLaunchKernelGGL((conv_fwd_kernel<2, C8>), dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else if (nt <= 4) hipLaunchKernelGGL((conv_fwd_kernel<4, C8>), dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else hipLaunchKernelGGL((conv_fwd_kernel<8, C8>), dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+}
+
 hipError_t conv_fwd_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
                            const unsigned short* w, const float* bias, int act, float slope, unsigned short* ybf,
                            float* yf, hipStream_t st)
@@ -897,12 +962,21 @@ hipError_t conv_fwd_launch(const ConvGeom& g, const unsigned short* xa, const un
     const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
     const unsigned blocks = (unsigned)((M + 63) / 64);
     const int nt = (g.Cout + 15) / 16;
-    if (nt <= 1) hipLaunchKernelGGL(conv_fwd_kernel<1>, dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
-    else if (nt <= 2) hipLaunchKernelGGL(conv_fwd_kernel<2>, dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
-    else if (nt <= 4) hipLaunchKernelGGL(conv_fwd_kernel<4>, dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
-    else if (nt <= 8) hipLaunchKernelGGL(conv_fwd_kernel<8>, dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
-    else return hipErrorInvalidValue;
+    if (nt > 8) return hipErrorInvalidValue;
+    if (g.Ca % 8 == 0 && g.Cb % 8 == 0) launch_fwd<true>(nt, blocks, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else launch_fwd<false>(nt, blocks, st, g, xa, xb, w, bias, act, slope, ybf, yf);
     return hipGetLastError();
+}
+
+template <bool C8>
+static void launch_bwd_data(int nt, unsigned blocks, hipStream_t st, const ConvGeom& g, const float* dy,
+                            const unsigned short* y, float slope, const unsigned short* wt, float* dx, int accumulate)
+{
+    if (nt <= 1) hipLaunchKernelGGL((conv_bwd_data_kernel<1, C8>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else if (nt <= 2) hipLaunchKernelGGL((conv_bwd_data_kernel<2, C8>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else if (nt <= 4) hipLaunchKernelGGL((conv_bwd_data_kernel<4, C8>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else if (nt <= 8) hipLaunchKernelGGL((conv_bwd_data_kernel<8, C8>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else hipLaunchKernelGGL((conv_bwd_data_kernel<12, C8>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
 }
 
 hipError_t conv_bwd_data_launch(const ConvGeom& g, const float* dy, const unsigned short* y, float slope,
@@ -911,12 +985,9 @@ hipError_t conv_bwd_data_launch(const ConvGeom& g, const float* dy, const unsign
     const long long M = (long long)g.N * g.Di * g.Hi * g.Wi;
     const unsigned blocks = (unsigned)((M + 63) / 64);
     const int nt = (g.Ca + g.Cb + 15) / 16;
-    if (nt <= 1) hipLaunchKernelGGL(conv_bwd_data_kernel<1>, dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else if (nt <= 2) hipLaunchKernelGGL(conv_bwd_data_kernel<2>, dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else if (nt <= 4) hipLaunchKernelGGL(conv_bwd_data_kernel<4>, dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else if (nt <= 8) hipLaunchKernelGGL(conv_bwd_data_kernel<8>, dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else if (nt <= 12) hipLaunchKernelGGL(conv_bwd_data_kernel<12>, dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else return hipErrorInvalidValue;
+    if (nt > 12) return hipErrorInvalidValue;
+    if (g.Cout % 8 == 0) launch_bwd_data<true>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
+    else launch_bwd_data<false>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
     return hipGetLastError();
 }
 
