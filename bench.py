@@ -479,8 +479,8 @@ def main():
                      "kernel": "lncc_kernel<5,BWD,border> (+1-block loss finalize)",
                      "algorithmic_bytes_per_launch": LNCC_BYTES_PER_VOXEL * nroi,
                      "limiter": "VALU issue and latency, not HBM bandwidth (rocprofv3 SQ counters on the 1040^3 "
-                                "share: about 490 VALU and 18 vector-memory instructions per ROI voxel, SIMD VALU "
-                                "busy 0.62)"},
+                                "share: about 465 VALU and 18 vector-memory instructions per ROI voxel, SIMD VALU "
+                                "busy 0.60)"},
         "breakdown_ms": {"lncc_fwd_bwd": round(t_lncc, 4), "adam": round(t_adam, 4), "mi_fwd": round(t_mif, 4),
                          "mi_bwd": round(t_mib, 4)},
         "breakdown_hbm_frac": {
