@@ -325,7 +325,9 @@ int ffdp_conv3d_bwd_data(const float* dy, const uint16_t* y, float slope, const 
 /* Backward to the weights: dw[co][t][ci] = sum_o P[o][co] X[o*stride + t - 1][ci]
  * and db[co] = sum_o P[o][co] (db may be NULL), fp32, overwritten; the sums
  * over output voxels run in chunks whose partials (caller workspace) are
- * added in a fixed order. */
+ * added in a fixed order.  For the stride-2 layers and those with more than
+ * 64 output channels the workspace also holds P as bf16 in [Cout][voxel]
+ * order (2 bytes per output voxel and channel). */
 size_t ffdp_conv3d_bwd_weight_workspace_bytes(const ffdp_conv_geom* g);
 int ffdp_conv3d_bwd_weight(const uint16_t* xa, const uint16_t* xb, const float* dy, const uint16_t* y, float slope,
                            const ffdp_conv_geom* g, float* dw, float* db, void* ws, size_t ws_bytes, void* stream);

@@ -338,6 +338,54 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
 }
 
 // --------------------------------------------------------- backward weight --
+// P^T = bf16(dL/dy act'(y)) in [Cout][MP] order (MP = M rounded up to 8,
+// zeros past M) for the voxel-chunk weight-gradient kernels: their MFMA A
+// operand, 8 consecutive output voxels of one channel, is then one aligned
+// 16-byte load.  A block transposes 64 voxels x Cout channels through LDS
+// (coalesced reads along channels, coalesced writes along voxels).  The
+// rounding is that of the operand packing (round to nearest even).
+constexpr int PT_MAXC = 128;
+__global__ void __launch_bounds__(256) p_transpose_kernel(const float* __restrict__ dy,
+                                                          const unsigned short* __restrict__ y, float slope,
+                                                          long long M, int Cout, long long MP,
+                                                          unsigned short* __restrict__ pt)
+{
+    __shared__ unsigned short tile[PT_MAXC][64 + 2];
+    const long long o0 = (long long)blockIdx.x * 64;
+    const long long nv = min(64LL, M - o0);  // <= 0 in the padding past M
+    for (int q = threadIdx.x; q < 64 * Cout; q += 256) {
+        const int v = q / Cout, co = q - v * Cout;
+        float p = 0.0f;
+        if (v < nv) {
+            const size_t k = (size_t)(o0 + v) * Cout + co;
+            p = dy[k];
+            if (y) p *= lrelu_d(y[k], slope);
+        }
+        tile[co][v] = f2bf(p);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < Cout * 64; q += 256) {
+        const int co = q >> 6, v = q & 63;
+        if (o0 + v < MP) pt[(size_t)co * MP + o0 + v] = tile[co][v];
+    }
+}
+
+// A operand of output channel co for the 8 output voxels o .. o + 7 (o a
+// multiple of 8): one 16-byte load of P^T, the voxels at or past oe zeroed.
+__device__ __forceinline__ bf8v load_pt8(const unsigned short* __restrict__ pt, long long MP, int co, int Cout,
+                                         long long o, long long oe)
+{
+    s8v r = s8v{0, 0, 0, 0, 0, 0, 0, 0};
+    if (co < Cout && o < oe) {
+        r = *reinterpret_cast<const s8v*>(pt + (size_t)co * MP + o);
+        if (o + 8 > oe)
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (o + e >= oe) r[e] = 0;
+    }
+    return __builtin_bit_cast(bf8v, r);
+}
+
 // Block (chunk, tap t): partial dW[co][t][ci] over output voxels
 // [chunk*VC, chunk*VC + VC), written to part[chunk][co][t][ci].  Wave w owns
 // the ci-tiles w, w+4, ... and all co-tiles.  GEMM rows co, columns ci, K =
@@ -346,8 +394,7 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
 template <int TM, int TNW>
 __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
                                                               const unsigned short* __restrict__ xb,
-                                                              const float* __restrict__ dy,
-                                                              const unsigned short* __restrict__ y, float slope,
+                                                              const unsigned short* __restrict__ pt, long long MP,
                                                               long long VC, float* __restrict__ part)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -369,7 +416,6 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const 
         // this lane's 8 output voxels o0 + kg + e and their shifted input voxels
         long long iv[8], iva[8];  // input voxel; its coarse voxel where part a is upsampled
         bool ov[8], iok[8];
-        size_t ooff[8];
         Vox v = cur;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -379,7 +425,6 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const 
             iok[e] = false;
             iv[e] = 0;
             iva[e] = 0;
-            ooff[e] = 0;
             if (ov[e]) {
                 const int zi = v.z * g.stride + dz - 1, yi = v.y * g.stride + dyy - 1, xi = v.x * g.stride + dx_ - 1;
                 iok[e] = (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi && (unsigned)xi < (unsigned)g.Wi;
@@ -387,26 +432,13 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const 
                 if (g.ups)
                     iva[e] = (((long long)v.n * (g.Di >> 1) + (zi >> 1)) * (g.Hi >> 1) + (yi >> 1)) * (g.Wi >> 1) +
                              (xi >> 1);
-                ooff[e] = (size_t)o * g.Cout;
             }
         }
         vox_add(cur, 32, g.Do, g.Ho, g.Wo);
         // A operands: P[o][co] for the co-tiles
         bf8v a[TM];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const int co = i * 16 + (lane & 15);
-            float pv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                pv[e] = 0.f;
-                if (ov[e] && co < g.Cout) {
-                    pv[e] = dy[ooff[e] + co];
-                    if (y) pv[e] *= lrelu_d(y[ooff[e] + co], slope);
-                }
-            }
-            a[i] = cat8(pack4(pv[0], pv[1], pv[2], pv[3]), pack4(pv[4], pv[5], pv[6], pv[7]));
-        }
+        for (int i = 0; i < TM; ++i) a[i] = load_pt8(pt, MP, i * 16 + (lane & 15), g.Cout, o0 + kg, oe);
 #pragma unroll
         for (int jj = 0; jj < TNW; ++jj) {
             const int jt = wave + 4 * jj;
@@ -461,9 +493,9 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_kernel(ConvGeom g, const 
 template <int TM, int TN>
 __global__ void __launch_bounds__(256) conv_bwd_weight_taps_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
                                                                    const unsigned short* __restrict__ xb,
-                                                                   const float* __restrict__ dy,
-                                                                   const unsigned short* __restrict__ y, float slope,
-                                                                   long long VC, float* __restrict__ part)
+                                                                   const unsigned short* __restrict__ pt,
+                                                                   long long MP, long long VC,
+                                                                   float* __restrict__ part)
 {
     constexpr int QT = 7;  // taps per wave: 27 = 4 * 7 - 1
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -486,7 +518,6 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_taps_kernel(ConvGeom g, c
         // corner (tap 0, 0, 0) of each
         int vn[8], vz[8], vy[8], vx[8];
         bool ov[8];
-        size_t ooff[8];
         Vox v = cur;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -495,24 +526,11 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_taps_kernel(ConvGeom g, c
             ov[e] = o < oe;
             vn[e] = ov[e] ? v.n : 0;
             vz[e] = v.z * g.stride - 1; vy[e] = v.y * g.stride - 1; vx[e] = v.x * g.stride - 1;
-            ooff[e] = (size_t)(ov[e] ? o : 0) * g.Cout;
         }
         vox_add(cur, 32, g.Do, g.Ho, g.Wo);
         bf8v a[TM];
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const int co = i * 16 + (lane & 15);
-            float pv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                pv[e] = 0.f;
-                if (ov[e] && co < g.Cout) {
-                    pv[e] = dy[ooff[e] + co];
-                    if (y) pv[e] *= lrelu_d(y[ooff[e] + co], slope);
-                }
-            }
-            a[i] = cat8(pack4(pv[0], pv[1], pv[2], pv[3]), pack4(pv[4], pv[5], pv[6], pv[7]));
-        }
+        for (int i = 0; i < TM; ++i) a[i] = load_pt8(pt, MP, i * 16 + (lane & 15), g.Cout, o0 + kg, oe);
 #pragma unroll
         for (int q = 0; q < QT; ++q) {
             const int t = wave + 4 * q;
@@ -991,6 +1009,9 @@ hipError_t conv_bwd_data_launch(const ConvGeom& g, const float* dy, const unsign
     return hipGetLastError();
 }
 
+// Row pitch of P^T: the output voxels rounded up to 8.
+static long long wgrad_mp(long long M) { return (M + 7) / 8 * 8; }
+
 // The all-taps kernel for layers with at most 3 tiles of 16 x 16 (co, ci).
 static bool wgrad_all_taps(const ConvGeom& g)
 {
@@ -1029,18 +1050,18 @@ ConvWgradPlan conv_wgrad_plan(const ConvGeom& g)
     p.VC = vc;
     p.nchunks = (int)((M + vc - 1) / vc);
     const long long q = (long long)g.Cout * 27 * (g.Ca + g.Cb);
-    p.part_floats = (long long)p.nchunks * q + (long long)p.nchunks * g.Cout;
+    // partials, bias partials, then P^T (bf16 [Cout][MP], 16-byte aligned)
+    p.part_floats = (long long)p.nchunks * q + (long long)p.nchunks * g.Cout + (g.Cout * wgrad_mp(M) + 1) / 2 + 4;
     return p;
 }
 
 template <int TM>
 static void launch_wg_tm(int tnw, dim3 grid, hipStream_t st, const ConvGeom& g, const unsigned short* xa,
-                         const unsigned short* xb, const float* dy, const unsigned short* y, float slope, long long VC,
-                         float* part)
+                         const unsigned short* xb, const unsigned short* pt, long long MP, long long VC, float* part)
 {
-    if (tnw <= 1) hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 1>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VC, part);
-    else if (tnw <= 2) hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 2>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VC, part);
-    else hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 3>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VC, part);
+    if (tnw <= 1) hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 1>), grid, dim3(256), 0, st, g, xa, xb, pt, MP, VC, part);
+    else if (tnw <= 2) hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 2>), grid, dim3(256), 0, st, g, xa, xb, pt, MP, VC, part);
+    else hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 3>), grid, dim3(256), 0, st, g, xa, xb, pt, MP, VC, part);
 }
 
 template <int TM>
@@ -1075,20 +1096,28 @@ hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, c
         const int ng = wgrad_rows_ng(g);
         dim3 grid(p.nchunks, 3 * ((Cin + 4 * ng - 1) / (4 * ng)));
         launch_wgrad_rows(tm, ng, grid, st, g, xa, xb, dy, y, slope, p.VS, part);
-    } else if (wgrad_all_taps(g)) {
-        dim3 grid1(p.nchunks);
-        if (tm == 1 && tn == 1) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 1>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
-        else if (tm == 1 && tn == 2) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 2>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
-        else if (tm == 1) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 3>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
-        else if (tm == 2) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<2, 1>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
-        else hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<3, 1>), grid1, dim3(256), 0, st, g, xa, xb, dy, y, slope, p.VC, part);
     } else {
-        dim3 grid(p.nchunks, 27);
-        switch (tm) {
-            case 1: launch_wg_tm<1>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
-            case 2: launch_wg_tm<2>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
-            case 3: case 4: launch_wg_tm<4>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
-            default: launch_wg_tm<8>(tnw, grid, st, g, xa, xb, dy, y, slope, p.VC, part); break;
+        // P^T first (the voxel-chunk kernels read their A operands from it)
+        const long long M = (long long)g.N * g.Do * g.Ho * g.Wo, MP = wgrad_mp(M);
+        const uintptr_t pa = reinterpret_cast<uintptr_t>(part + (size_t)p.nchunks * (g.Cout * 27LL * Cin + g.Cout));
+        unsigned short* pt = reinterpret_cast<unsigned short*>((pa + 15) & ~(uintptr_t)15);
+        hipLaunchKernelGGL(p_transpose_kernel, dim3((unsigned)((MP + 63) / 64)), dim3(256), 0, st, dy, y, slope, M,
+                           g.Cout, MP, pt);
+        if (wgrad_all_taps(g)) {
+            dim3 grid1(p.nchunks);
+            if (tm == 1 && tn == 1) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 1>), grid1, dim3(256), 0, st, g, xa, xb, pt, MP, p.VC, part);
+            else if (tm == 1 && tn == 2) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 2>), grid1, dim3(256), 0, st, g, xa, xb, pt, MP, p.VC, part);
+            else if (tm == 1) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 3>), grid1, dim3(256), 0, st, g, xa, xb, pt, MP, p.VC, part);
+            else if (tm == 2) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<2, 1>), grid1, dim3(256), 0, st, g, xa, xb, pt, MP, p.VC, part);
+            else hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<3, 1>), grid1, dim3(256), 0, st, g, xa, xb, pt, MP, p.VC, part);
+        } else {
+            dim3 grid(p.nchunks, 27);
+            switch (tm) {
+                case 1: launch_wg_tm<1>(tnw, grid, st, g, xa, xb, pt, MP, p.VC, part); break;
+                case 2: launch_wg_tm<2>(tnw, grid, st, g, xa, xb, pt, MP, p.VC, part); break;
+                case 3: case 4: launch_wg_tm<4>(tnw, grid, st, g, xa, xb, pt, MP, p.VC, part); break;
+                default: launch_wg_tm<8>(tnw, grid, st, g, xa, xb, pt, MP, p.VC, part); break;
+            }
         }
     }
     hipError_t e = hipGetLastError();

@@ -24,6 +24,10 @@ CASES = [
     (1, 4, 6, 70, 32, 16, 16, 1, True),
     (1, 4, 4, 40, 64, 32, 32, 1, True),
     (2, 3, 5, 45, 16, 0, 4, 1, False),
+    # voxel-chunk weight gradients: stride 2 with two input-channel tiles, and
+    # stride 1 with more than 64 output channels (odd voxel count: padded P^T rows)
+    (1, 8, 8, 12, 32, 0, 64, 2, False),
+    (1, 3, 5, 7, 16, 0, 80, 1, False),
 ]
 
 
