@@ -231,7 +231,12 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
 // accumulate = 1 adds to dX.  wt is the weight in [Cin][27][Cout] order.
 // C8: Cout is a multiple of 8, so a lane's 8 K elements are 8 contiguous
 // output channels of one tap (two 16-byte loads of dL/dy, one of y).
-template <int NT, bool C8>
+// PAR (stride 2): an input voxel i receives tap d along an axis only where
+// i + 1 - d is even (d = 1 for even i, d = 0 or 2 for odd i), so the input
+// voxels are split into the 8 parity classes of (z, y, x) and a block takes
+// 64 voxels of one class: its K runs over that class's 1 to 8 taps instead
+// of all 27 (3.375 on average), and no product is a structural zero.
+template <int NT, bool C8, bool PAR>
 __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const float* __restrict__ dy,
                                                             const unsigned short* __restrict__ y, float slope,
                                                             const unsigned short* __restrict__ wt,
@@ -240,20 +245,45 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
     __shared__ __attribute__((aligned(16))) unsigned short ws[NT * 16 * CONV_KCP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int Cin = g.Ca + g.Cb;
-    const int K = 27 * g.Cout;
     const long long M = (long long)g.N * g.Di * g.Hi * g.Wi;
-    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 16;
+    // parity class (PAR): bits 2, 1, 0 = z, y, x parity; rows index the class's
+    // voxels over the half-resolution grid Dc x Hc x Wc (rounded up)
+    const int Dc = (g.Di + 1) >> 1, Hc = (g.Hi + 1) >> 1, Wc = (g.Wi + 1) >> 1;
+    const long long Mc = (long long)g.N * Dc * Hc * Wc;
+    const int bpc = PAR ? (int)((Mc + 63) / 64) : 0;  // blocks per class
+    const int cls = PAR ? (int)blockIdx.x / bpc : 0;
+    const int pz = (cls >> 2) & 1, py = (cls >> 1) & 1, px = cls & 1;
+    const int ny = PAR ? 1 + py : 3, nx = PAR ? 1 + px : 3;  // taps per axis
+    const int ntap = PAR ? (1 + pz) * ny * nx : 27;
+    const int K = ntap * g.Cout;
+    const long long m0 = ((long long)(PAR ? (int)blockIdx.x - cls * bpc : (int)blockIdx.x) * 4 + wave) * 16;
     const long long m = m0 + (lane & 15);
-    const bool mvalid = m < M;
+    auto voxel = [&](long long r, int& n_, int& z_, int& y_, int& x_) -> bool {  // row -> voxel
+        if (!PAR) {
+            if (r >= M) return false;
+            const Vox v = vox_of(r, g.Di, g.Hi, g.Wi);
+            n_ = v.n; z_ = v.z; y_ = v.y; x_ = v.x;
+            return true;
+        }
+        if (r >= Mc) return false;
+        const Vox v = vox_of(r, Dc, Hc, Wc);
+        n_ = v.n; z_ = 2 * v.z + pz; y_ = 2 * v.y + py; x_ = 2 * v.x + px;
+        return z_ < g.Di && y_ < g.Hi && x_ < g.Wi;
+    };
     int n = 0, zi = 0, yi = 0, xi = 0;
-    if (mvalid) {
-        const Vox v = vox_of(m, g.Di, g.Hi, g.Wi);
-        n = v.n; zi = v.z; yi = v.y; xi = v.x;
-    }
+    const bool mvalid = voxel(m, n, zi, yi, xi);
+    // tap number of the class's j-th tap (PAR), else j itself
+    auto tap_of = [&](int j) -> int {
+        if (!PAR) return j;
+        const int jz = j / (ny * nx), jr = j - jz * ny * nx, jy = jr / nx, jx = jr - jy * nx;
+        const int dz = pz ? 2 * jz : 1, dyy = py ? 2 * jy : 1, dx_ = px ? 2 * jx : 1;
+        return dz * 9 + dyy * 3 + dx_;
+    };
     // element offset of P at output channel co of tap t, or -1 where the tap
     // reaches no output voxel (a non-integer or out-of-range output index)
-    auto p_offset = [&](int t, int co) -> long long {
-        if (!mvalid || t >= 27) return -1;
+    auto p_offset = [&](int j, int co) -> long long {  // j: tap index within the class (PAR) or tap
+        if (!mvalid || j >= ntap) return -1;
+        const int t = tap_of(j);
         const int dz = t / 9, dyy = (t - 9 * dz) / 3, dx_ = t - 9 * dz - 3 * dyy;
         int oz = zi + 1 - dz, oy = yi + 1 - dyy, ox = xi + 1 - dx_;
         bool ok = oz >= 0 && oy >= 0 && ox >= 0;
@@ -305,10 +335,28 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
     for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += CONV_KC) {
         __syncthreads();
-        stage_weights<NT>(ws, wt, Cin, K, k0);
+        if (PAR) {
+            // the class's K columns (j, c) from wt [Cin][27][Cout]: groups of 4
+            // channels of one tap (Cout % 4 == 0) are contiguous there
+            constexpr int Q = NT * 16 * (CONV_KC / 4);
+            const int K27 = 27 * g.Cout;
+            for (int q = threadIdx.x; q < Q; q += 256) {
+                const int r = q / (CONV_KC / 4), cc = (q - r * (CONV_KC / 4)) * 4;
+                uint2 v = make_uint2(0u, 0u);
+                const int k = k0 + cc;
+                if (r < Cin && k < K) {
+                    const int j = k / g.Cout, c4 = k - j * g.Cout;
+                    v = *reinterpret_cast<const uint2*>(wt + (size_t)r * K27 + tap_of(j) * g.Cout + c4);
+                }
+                *reinterpret_cast<uint2*>(ws + r * CONV_KCP + cc) = v;
+            }
+        } else {
+            stage_weights<NT>(ws, wt, Cin, K, k0);
+        }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < CONV_KC; kk += 32) {
+            if (k0 + kk >= K) break;  // uniform: past the last K column
             bf8v a;
             if (C8) {
                 a = load_p8(t, c);
@@ -323,14 +371,21 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
             while (c >= g.Cout) { c -= g.Cout; ++t; }
         }
     }
+    long long vo[4];  // voxels of the lane's 4 output rows (-1: none)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        int n_, z_, y_, x_;
+        const long long r = m0 + (lane >> 4) * 4 + e;
+        vo[e] = -1;
+        if (voxel(r, n_, z_, y_, x_)) vo[e] = PAR ? (((long long)n_ * g.Di + z_) * g.Hi + y_) * g.Wi + x_ : r;
+    }
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int ci = j * 16 + (lane & 15);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const long long mo = m0 + (lane >> 4) * 4 + e;
-            if (mo < M && ci < Cin) {
-                float* p = dx + mo * Cin + ci;
+            if (vo[e] >= 0 && ci < Cin) {
+                float* p = dx + vo[e] * Cin + ci;
                 *p = accumulate ? *p + acc[j][e] : acc[j][e];
             }
         }
@@ -986,26 +1041,33 @@ hipError_t conv_fwd_launch(const ConvGeom& g, const unsigned short* xa, const un
     return hipGetLastError();
 }
 
-template <bool C8>
+template <bool C8, bool PAR>
 static void launch_bwd_data(int nt, unsigned blocks, hipStream_t st, const ConvGeom& g, const float* dy,
                             const unsigned short* y, float slope, const unsigned short* wt, float* dx, int accumulate)
 {
-    if (nt <= 1) hipLaunchKernelGGL((conv_bwd_data_kernel<1, C8>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else if (nt <= 2) hipLaunchKernelGGL((conv_bwd_data_kernel<2, C8>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else if (nt <= 4) hipLaunchKernelGGL((conv_bwd_data_kernel<4, C8>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else if (nt <= 8) hipLaunchKernelGGL((conv_bwd_data_kernel<8, C8>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else hipLaunchKernelGGL((conv_bwd_data_kernel<12, C8>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    if (nt <= 1) hipLaunchKernelGGL((conv_bwd_data_kernel<1, C8, PAR>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else if (nt <= 2) hipLaunchKernelGGL((conv_bwd_data_kernel<2, C8, PAR>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else if (nt <= 4) hipLaunchKernelGGL((conv_bwd_data_kernel<4, C8, PAR>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else if (nt <= 8) hipLaunchKernelGGL((conv_bwd_data_kernel<8, C8, PAR>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+    else hipLaunchKernelGGL((conv_bwd_data_kernel<12, C8, PAR>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
 }
 
 hipError_t conv_bwd_data_launch(const ConvGeom& g, const float* dy, const unsigned short* y, float slope,
                                 const unsigned short* wt, float* dx, int accumulate, hipStream_t st)
 {
-    const long long M = (long long)g.N * g.Di * g.Hi * g.Wi;
-    const unsigned blocks = (unsigned)((M + 63) / 64);
     const int nt = (g.Ca + g.Cb + 15) / 16;
     if (nt > 12) return hipErrorInvalidValue;
-    if (g.Cout % 8 == 0) launch_bwd_data<true>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
-    else launch_bwd_data<false>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
+    if (g.stride == 2) {  // 8 parity classes of the half-resolution grid (rounded up)
+        const long long Mc = (long long)g.N * ((g.Di + 1) / 2) * ((g.Hi + 1) / 2) * ((g.Wi + 1) / 2);
+        const unsigned blocks = (unsigned)(8 * ((Mc + 63) / 64));
+        if (g.Cout % 8 == 0) launch_bwd_data<true, true>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
+        else launch_bwd_data<false, true>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
+    } else {
+        const long long M = (long long)g.N * g.Di * g.Hi * g.Wi;
+        const unsigned blocks = (unsigned)((M + 63) / 64);
+        if (g.Cout % 8 == 0) launch_bwd_data<true, false>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
+        else launch_bwd_data<false, false>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
+    }
     return hipGetLastError();
 }
 
