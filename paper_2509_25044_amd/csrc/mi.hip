@@ -263,8 +263,13 @@ template <bool HARD, int PAD, bool AFF, bool GLOB>
 __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long long* __restrict__ ghist,
                                                         unsigned long long* __restrict__ gflag)
 {
-    extern __shared__ unsigned long long hist[];  // a.ncopy copies of [B*B], stride B*B+1
-    const int B = a.bins, BB = B * B, CS = BB + 1;
+    // a.ncopy copies of [B][B + 1] (row pitch B + 1), stride B (B + 1) + 1.
+    // With a pitch of B the same column of any two rows falls in one LDS bank
+    // (a row is 2B banks wide), which is what lanes with equal Mw bins and
+    // different F bins hit; with B + 1 the bank follows the row plus column.
+    extern __shared__ unsigned long long hist[];
+    const int B = a.bins, BB = B * B;
+    const int RP = GLOB ? B : B + 1, CS = B * RP + 1;  // row pitch, copy stride
     for (int q = threadIdx.x; !GLOB && q < a.ncopy * CS; q += MI_NT) hist[q] = 0ull;
     unsigned long long* const mine = GLOB ? ghist : hist + (threadIdx.x & (a.ncopy - 1)) * CS;
     __shared__ int nanflag;
@@ -291,7 +296,7 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
         int row[4], col[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            row[i] = (int)__umul24((unsigned)fold(cm + i, B), (unsigned)B);
+            row[i] = (int)__umul24((unsigned)fold(cm + i, B), (unsigned)RP);
             col[i] = fold(cn + i, B);
         }
 #pragma unroll
@@ -328,8 +333,9 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
     if (bad) nanflag = 1;
     __syncthreads();
     for (int q = threadIdx.x; !GLOB && q < BB; q += MI_NT) {
+        const int lq = q + q / B;  // (q / B) RP + q % B
         unsigned long long v = 0ull;
-        for (int c = 0; c < a.ncopy; ++c) v += hist[c * CS + q];
+        for (int c = 0; c < a.ncopy; ++c) v += hist[c * CS + lq];
         if (v) atomicAdd(&ghist[q], v);
     }
     if (threadIdx.x == 0 && nanflag) atomicOr(gflag, 1ull);
@@ -659,7 +665,7 @@ static hipError_t mi_fwd_dispatch(const MiArgs& a, int hard, int pad, unsigned l
         hipLaunchKernelGGL(mi_finalize_approx, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, state, loss);
         return hipGetLastError();
     }
-    const size_t lds = sizeof(unsigned long long) * a.ncopy * (BB + 1);
+    const size_t lds = sizeof(unsigned long long) * a.ncopy * (a.bins * (a.bins + 1) + 1);
     if (a.ncopy == 0) {
         if (hard) {
             if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER, AFF, true>), grid, block, 0, st, a, hist, flag);
@@ -691,11 +697,12 @@ hipError_t mi_fwd_launch(const MiArgs& a0, int hard, int pad, unsigned long long
     (void)nroi;
     MiArgs a = a0;
     // LDS histogram copies: at most 4, and at most 66 KB of bins (u64 for the
-    // Parzen histogram: 4 copies up to 45 bins, 2 up to 64, 1 up to 90; u32
-    // counts of the approximate estimator: 1 copy up to 128 bins).  Larger
-    // histograms are added straight into the global one (ncopy = 0).
-    const size_t cell = hard == 2 ? sizeof(unsigned int) : sizeof(unsigned long long);
-    const size_t one = (size_t)(a.bins * a.bins + 1) * cell;
+    // Parzen histogram, rows padded to B + 1: 4 copies up to 45 bins, 2 up to
+    // 64, 1 up to 91; u32 counts of the approximate estimator: 1 copy up to
+    // 128 bins).  Larger histograms are added straight into the global one
+    // (ncopy = 0).
+    const size_t one = hard == 2 ? (size_t)(a.bins * a.bins + 1) * sizeof(unsigned int)
+                                 : (size_t)(a.bins * (a.bins + 1) + 1) * sizeof(unsigned long long);
     a.ncopy = one <= 67584 ? 1 : 0;
     while (a.ncopy && a.ncopy < 4 && 2 * a.ncopy * one <= 67584) a.ncopy *= 2;
     const int BB = a.bins * a.bins;
