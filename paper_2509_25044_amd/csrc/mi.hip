@@ -109,7 +109,9 @@ __device__ __forceinline__ void sample_disp(const MiArgs& a, int x, int y, int z
 __device__ __forceinline__ unsigned long long to_fix(float x)
 {
     const unsigned hi = (unsigned)x;
-    const unsigned lo = (unsigned)fmaf(x - (float)hi, 4294967296.0f, 0.5f);
+    // x - floor(x) in one instruction (exact for x >= 0, the same value as
+    // x - (float)hi)
+    const unsigned lo = (unsigned)fmaf(__builtin_amdgcn_fractf(x), 4294967296.0f, 0.5f);
     return ((unsigned long long)hi << 32) | lo;
 }
 
@@ -256,6 +258,11 @@ struct ColumnSampler {
     }
 };
 
+// Row pitch of the LDS histogram copies: at least B + 5 columns (Mw bins -2 ..
+// B + 1 of the Parzen window; the hard-bin patch j .. j + 3 of j <= B - 1
+// reaches column B + 4), odd.
+__host__ __device__ constexpr int mi_hist_pitch(int B) { return (B + 5) | 1; }
+
 // GLOB: the histogram is too large for LDS (a.ncopy == 0) and the taps are
 // added straight into the global one; otherwise into a.ncopy LDS copies.
 // (Compile-time, so that each atomic is an LDS or a global one, never flat.)
@@ -263,13 +270,18 @@ template <bool HARD, int PAD, bool AFF, bool GLOB>
 __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long long* __restrict__ ghist,
                                                         unsigned long long* __restrict__ gflag)
 {
-    // a.ncopy copies of [B][B + 1] (row pitch B + 1), stride B (B + 1) + 1.
-    // With a pitch of B the same column of any two rows falls in one LDS bank
-    // (a row is 2B banks wide), which is what lanes with equal Mw bins and
-    // different F bins hit; with B + 1 the bank follows the row plus column.
+    // LDS: a.ncopy copies of B rows (F bins, clamped) of mi_hist_pitch(B)
+    // >= B + 5 columns holding the Mw bins -2 .. B + 1 unclamped (column c at
+    // c + 2), so the four columns of a patch are consecutive and each row of
+    // the flush is one address plus immediate offsets; the clamp of those
+    // columns into bins 0 and B - 1 happens once, when the copies are added
+    // up.  The pitch is odd: with an even one (a row is twice as many banks
+    // wide) the same column of any two rows falls in one LDS bank, which is
+    // what lanes with equal Mw bins and different F bins hit.  Copy stride
+    // B pitch + 1.  GLOB: the global [B][B] histogram, columns clamped.
     extern __shared__ unsigned long long hist[];
     const int B = a.bins, BB = B * B;
-    const int RP = GLOB ? B : B + 1, CS = B * RP + 1;  // row pitch, copy stride
+    const int RP = GLOB ? B : mi_hist_pitch(B), CS = B * RP + 1;  // row pitch, copy stride
     for (int q = threadIdx.x; !GLOB && q < a.ncopy * CS; q += MI_NT) hist[q] = 0ull;
     unsigned long long* const mine = GLOB ? ghist : hist + (threadIdx.x & (a.ncopy - 1)) * CS;
     __shared__ int nanflag;
@@ -293,17 +305,26 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
     bool bad = false;
 
     auto flush = [&]() {
-        int row[4], col[4];
+        if (GLOB) {
+            int row[4], col[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            row[i] = (int)__umul24((unsigned)fold(cm + i, B), (unsigned)RP);
-            col[i] = fold(cn + i, B);
+            for (int i = 0; i < 4; ++i) {
+                row[i] = (int)__umul24((unsigned)fold(cm + i, B), (unsigned)RP);
+                col[i] = fold(cn + i, B);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    atomicAdd(&mine[row[i] + col[jj]], to_fix(acc[i * 4 + jj]));  // unconditional: no branch per tap
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                unsigned long long* rp = mine + (int)__umul24((unsigned)fold(cm + i, B), (unsigned)RP) + (cn + 2);
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) atomicAdd(rp + jj, to_fix(acc[i * 4 + jj]));
+            }
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj)
-                atomicAdd(&mine[row[i] + col[jj]], to_fix(acc[i * 4 + jj]));  // unconditional: no branch per tap
     };
 
     if (active && zb < ze) {
@@ -333,9 +354,12 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
     if (bad) nanflag = 1;
     __syncthreads();
     for (int q = threadIdx.x; !GLOB && q < BB; q += MI_NT) {
-        const int lq = q + q / B;  // (q / B) RP + q % B
+        const int r = q / B, c = q - r * B;
+        // stored columns of bin c: c + 2, and the clamped ones beside the edges
+        const int s0 = c == 0 ? 0 : c + 2, s1 = c == B - 1 ? B + 3 : c + 2;
         unsigned long long v = 0ull;
-        for (int c = 0; c < a.ncopy; ++c) v += hist[c * CS + lq];
+        for (int k = 0; k < a.ncopy; ++k)
+            for (int sc = s0; sc <= s1; ++sc) v += hist[k * CS + r * RP + sc];
         if (v) atomicAdd(&ghist[q], v);
     }
     if (threadIdx.x == 0 && nanflag) atomicOr(gflag, 1ull);
@@ -665,7 +689,7 @@ static hipError_t mi_fwd_dispatch(const MiArgs& a, int hard, int pad, unsigned l
         hipLaunchKernelGGL(mi_finalize_approx, dim3(1), dim3(1024), 0, st, hist, flag, a.bins, state, loss);
         return hipGetLastError();
     }
-    const size_t lds = sizeof(unsigned long long) * a.ncopy * (a.bins * (a.bins + 1) + 1);
+    const size_t lds = sizeof(unsigned long long) * a.ncopy * (a.bins * mi_hist_pitch(a.bins) + 1);
     if (a.ncopy == 0) {
         if (hard) {
             if (pad == PAD_BORDER) hipLaunchKernelGGL((mi_hist_kernel<true, PAD_BORDER, AFF, true>), grid, block, 0, st, a, hist, flag);
@@ -696,15 +720,16 @@ hipError_t mi_fwd_launch(const MiArgs& a0, int hard, int pad, unsigned long long
 {
     (void)nroi;
     MiArgs a = a0;
-    // LDS histogram copies: at most 4, and at most 66 KB of bins (u64 for the
-    // Parzen histogram, rows padded to B + 1: 4 copies up to 45 bins, 2 up to
-    // 64, 1 up to 91; u32 counts of the approximate estimator: 1 copy up to
-    // 128 bins).  Larger histograms are added straight into the global one
-    // (ncopy = 0).
+    // LDS histogram copies: at most 4 and at most 79 KB (two blocks per CU).
+    // u64 for the Parzen histogram, rows of mi_hist_pitch(B) entries: 4
+    // copies up to 47 bins, 2 up to 68, 1 up to 98; u32 counts of the
+    // approximate estimator within 66 KB: 1 copy up to 128 bins.  Larger
+    // histograms are added straight into the global one (ncopy = 0).
+    const size_t budget = hard == 2 ? 67584 : 80896;
     const size_t one = hard == 2 ? (size_t)(a.bins * a.bins + 1) * sizeof(unsigned int)
-                                 : (size_t)(a.bins * (a.bins + 1) + 1) * sizeof(unsigned long long);
-    a.ncopy = one <= 67584 ? 1 : 0;
-    while (a.ncopy && a.ncopy < 4 && 2 * a.ncopy * one <= 67584) a.ncopy *= 2;
+                                 : (size_t)(a.bins * mi_hist_pitch(a.bins) + 1) * sizeof(unsigned long long);
+    a.ncopy = one <= budget ? 1 : 0;
+    while (a.ncopy && a.ncopy < 4 && 2 * a.ncopy * one <= budget) a.ncopy *= 2;
     const int BB = a.bins * a.bins;
     unsigned long long* flag = hist + BB;
     hipLaunchKernelGGL(mi_zero, dim3((BB + 1 + 255) / 256), dim3(256), 0, st, hist, BB + 1);

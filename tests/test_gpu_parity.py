@@ -377,20 +377,20 @@ def test_mi_approx_estimator(c1, c2):
     _mi_case(F2, M2, u2, bins=32, hard="approx", what="c2 approx")
 
 
-@pytest.mark.parametrize("bins", [8, 45, 46, 64])
+@pytest.mark.parametrize("bins", [8, 45, 47, 48, 64, 68, 69])
 def test_mi_bin_counts_and_histogram_copies(c1, bins):
-    """Bin counts on both sides of the LDS layout change (4 histogram copies
-    up to 45 bins, 2 copies above, 64 KB of LDS at 64 bins)."""
+    """Bin counts on both sides of the LDS layout changes (4 histogram copies
+    up to 47 bins, 2 copies up to 68, 1 above, 79 KB of LDS at 47 bins)."""
     F, M, u = c1
     _mi_case(F, M, u, bins=bins, what=f"c1 b{bins}")
     if bins in (45, 64):
         _mi_case(F, M, u, bins=bins, hard="approx", what=f"c1 approx b{bins}")
 
 
-@pytest.mark.parametrize("bins", [90, 91, 128, 129, 200, 256])
+@pytest.mark.parametrize("bins", [90, 98, 99, 128, 129, 200, 256])
 def test_mi_wide_histograms(bins):
     """Bin counts beyond the LDS-resident layouts: one u64 LDS histogram up to
-    90 bins, global u64 atomics above; the approximate estimator's u32
+    98 bins, global u64 atomics above; the approximate estimator's u32
     counts in LDS up to 128 bins, global above; the adjoint's log table in
     LDS up to 128 bins, read through the caches above."""
     F, M, u = _rand_case((24, 28, 36), 160 + bins)
