@@ -164,10 +164,18 @@ __device__ __forceinline__ Tri trilinear_clamped(const float* __restrict__ M, in
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* red)
 {
+    // a tree over the largest power of two P <= NT; with NT not a power of
+    // two, threads P .. NT - 1 first add into 0 .. NT - P - 1
+    constexpr int P = (NT & (NT - 1)) == 0 ? NT : (NT >= 1024 ? 1024 : (NT >= 512 ? 512 : (NT >= 256 ? 256 : 128)));
+    static_assert(P <= NT && 2 * P > NT && NT <= 2048, "block size");
     red[threadIdx.x] = v;
     __syncthreads();
+    if (P < NT) {
+        if ((int)threadIdx.x < NT - P) red[threadIdx.x] += red[threadIdx.x + P];
+        __syncthreads();
+    }
 #pragma unroll
-    for (int s = NT / 2; s > 0; s >>= 1) {
+    for (int s = P / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }

@@ -15,7 +15,8 @@
 //
 // Design (one kernel, nothing N-sized in HBM besides inputs and grad_u):
 //  * a block of 512 threads owns a 32 x 16 column tile and a z-chunk and
-//    streams z slices through a pipeline of LDS stages;
+//    streams z slices through a pipeline of LDS stages (the w = 7 adjoint:
+//    768 threads and 32 x 24 tiles, see lncc_tile);
 //  * stage A samples F and Mw on the tile plus a halo of 2r (r for the
 //    forward) and keeps the last w slices of every column in registers; for
 //    the tile's own voxel (one per thread) it also keeps dMw/dp in a
@@ -250,7 +251,8 @@ __device__ __forceinline__ Tri interp_pending(const Pend& g)
 }
 
 // Held to 128 VGPRs where 16 waves share a CU (1024-thread blocks, or two
-// 512-thread blocks for windows up to 5).  ADDR: see ld().
+// 512-thread blocks for windows up to 5); a 768-thread block is held to 168
+// by its launch bound.  ADDR: see ld().
 template <int WIN, int MODE, int PAD, int ADDR, int TX_, int TY_>
 __global__ void __launch_bounds__(TX_ * TY_)
     __attribute__((amdgpu_waves_per_eu((TX_ * TY_ >= 1024 || WIN <= 5) ? 4 : 2, 8)))
@@ -643,12 +645,17 @@ __global__ void __launch_bounds__(256) lncc_finalize(const double* __restrict__ 
 // 32 x 32 tile with 1024 threads, which samples 1.56 instead of 1.88 points
 // per output at w = 5, runs one block per CU and spills registers at the
 // 128-VGPR limit; the adjoint took 3.72 ms against 2.81 ms at 512^3.)
+// Column tile of a launch: 32 x 16 (512 threads), except the w = 7 adjoint,
+// 32 x 24 (768 threads).  At w = 7 the 16-row tile samples 2.41 points per
+// output (its 4r halo) and its 167 VGPRs and 96 KB of LDS leave one block of
+// 8 waves per CU; 24 rows sample 2.06 points per output, and one block of
+// 12 waves fits (168 VGPRs, 134 KB): 512^3 adjoint 5.10 -> 4.74 ms, 1040^3
+// 45.6 -> 38.2 ms.  (32 x 32 does not fit the LDS; at w = 5 the two-block
+// 32 x 16 layout stays faster than any one-block tile.)
 static void lncc_tile(int win, int mode, int& tx, int& ty)
 {
     tx = 32;
-    ty = 16;
-    (void)win;
-    (void)mode;
+    ty = (win == 7 && mode == MODE_BWD) ? 24 : 16;
 }
 
 LnccLaunch lncc_plan(int D, int H, int W, int win, int mode)
@@ -719,8 +726,13 @@ static hipError_t launch_t(int pad, int addr, const LnccArgs& a, hipStream_t st)
 template <int WIN, int MODE>
 static hipError_t launch_w(int pad, const LnccLaunch& L, const LnccArgs& a, hipStream_t st)
 {
-    if (L.tx != 32 || L.ty != 16) return hipErrorInvalidValue;
-    return launch_t<WIN, MODE, 32, 16>(pad, L.addr, a, st);
+    if constexpr (WIN == 7 && MODE == MODE_BWD) {
+        if (L.tx != 32 || L.ty != 24) return hipErrorInvalidValue;
+        return launch_t<WIN, MODE, 32, 24>(pad, L.addr, a, st);
+    } else {
+        if (L.tx != 32 || L.ty != 16) return hipErrorInvalidValue;
+        return launch_t<WIN, MODE, 32, 16>(pad, L.addr, a, st);
+    }
 }
 
 template <int MODE>

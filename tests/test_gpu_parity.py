@@ -175,8 +175,9 @@ def _wide_zchunk(shape):
 
 
 def test_lncc_wide_window_clinical_samples(c2):
-    """w = 15 on the clinical pair: dloss/du at voxels on the 32 x 8 slice-tile
-    seams, the column passes' z-chunk seams, the faces and random voxels
+    """w = 15 on the clinical pair: dloss/du at voxels on the slice-tile seams
+    (32 x 32 tiles of the sampling pass, 32 x 16 of the a, c, e pass), the
+    column passes' z-chunk seams, the faces and random voxels
     against the oracle's per-voxel adjoint on the whole arrays; the loss of a
     sub-ROI box against the oracle on the warped volume."""
     F, M, u = c2
@@ -185,7 +186,7 @@ def test_lncc_wide_window_clinical_samples(c2):
     rng = np.random.default_rng(77)
     pts = set()
     xs = [0, 31, 32, 63, 64, 127, 128, W - 1]
-    ys = [0, 7, 8, 15, 16, 95, 96, H - 1]
+    ys = [0, 15, 16, 31, 32, 95, 96, 111, 112, H - 1]
     zs = sorted({0, D - 1, D // 2} | {v for k in (1, 2) for v in (k * zc - 1, k * zc) if 0 <= v < D})
     for i, z in enumerate(zs):
         for j, x in enumerate(xs):
