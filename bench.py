@@ -136,12 +136,13 @@ def extras(F, M, u, scratch, roi, nroi, wl, reps: int = 5):
     """Per-call times of the kernels outside the step, on the same volumes
     (HIP events on the current stream; not part of ms_per_step): the fused
     LNCC forward+adjoint at u = 0 (every gather aligned on a voxel, the easy
-    case) and the LNCC forward alone at the step's u, Gaussian smoothing of
+    case), the LNCC forward alone and the forward with the ANTs gradient
+    approximation (no second box filter) at the step's u, Gaussian smoothing of
     the 3-channel field, the fused smoothing + Adam step against the two
     calls, the approximate MI forward, and the composite
     sampler (a small rotation about the centre with the displacement added)
     in MI forward and adjoint.  Algorithmic bytes per unit: LNCC
-    forward+adjoint 32 and forward 20 per ROI voxel, smoothing 8 per element,
+    forward+adjoint (exact or ANTs) 32 and forward 20 per ROI voxel, smoothing 8 per element,
     MI forward 20 per ROI voxel, MI adjoint through the composite sampler 20
     per voxel (grad_u not written)."""
     stream = torch.cuda.current_stream()
@@ -174,6 +175,12 @@ def extras(F, M, u, scratch, roi, nroi, wl, reps: int = 5):
     ms = timed(lambda: ops.warp_lncc_fwd(F, M, u, window=wl.lncc_window, eps=wl.lncc_eps, roi=roi, ws=ws))
     res["lncc_fwd"] = {"ms": round(ms, 4), "gvoxel_per_s": round(nroi / (ms * 1e-3) / 1e9, 3),
                        "frac": round(20 * nroi / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    ws_a = torch.empty(ops.lncc_workspace_bytes(F.shape, roi, wl.lncc_window), dtype=torch.uint8, device=u.device)
+    ms = timed(lambda: ops.warp_lncc_bwd(F, M, u, window=wl.lncc_window, eps=wl.lncc_eps, ants=True, roi=roi,
+                                         grad_u=scratch, ws=ws_a))
+    res["lncc_fwd_bwd_ants"] = {"ms": round(ms, 4), "gvoxel_per_s": round(nroi / (ms * 1e-3) / 1e9, 3),
+                                "frac": round(32 * nroi / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del ws_a
     for sig in (1.0, 0.5):
         ms = timed(lambda: ops.gaussian_smooth(u, sig, out=scratch))
         res[f"smooth_sigma{sig:g}"] = {"ms": round(ms, 4), "frac": round(8 * n_el / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}

@@ -28,6 +28,8 @@ CASES = [
     # stride 1 with more than 64 output channels (odd voxel count: padded P^T rows)
     (1, 8, 8, 12, 32, 0, 64, 2, False),
     (1, 3, 5, 7, 16, 0, 80, 1, False),
+    # stride 2 over a batch of 2 with odd extents (parity classes of unequal size)
+    (2, 5, 7, 9, 16, 0, 32, 2, False),
 ]
 
 
