@@ -211,14 +211,19 @@ __device__ __forceinline__ Tri mi_interp(const MiPend& g)
 
 // Software pipeline of one thread's walk down its (x, y) column over
 // [z0, z1): the corners of z+1 are gathered while z is processed, and u of
-// z+2 is loaded meanwhile, so gather latency overlaps the per-voxel work.
+// z+2 is loaded meanwhile.  Two register sets alternate with the slice's
+// parity (S = (z - z0) & 1), and the kernels take two slices per loop
+// iteration (step<0> then step<1>), so pending registers are never copied:
+// a copy (what the compiler emits for a loop-carried load destination
+// written under a branch, or reused across iterations) waits for the loads
+// just issued and undoes the pipeline.
 template <int PAD, bool AFF>
 struct ColumnSampler {
     const MiArgs& a;
     int x, y, HW, z1;
     size_t N;
-    MiPend pend;
-    float un[3];
+    MiPend p[2];
+    float un[2][3];
 
     __device__ ColumnSampler(const MiArgs& a_, int x_, int y_, int z0, int z1_)
         : a(a_), x(x_), y(y_), HW(a_.H * a_.W), z1(z1_), N((size_t)a_.D * a_.H * a_.W)
@@ -226,8 +231,8 @@ struct ColumnSampler {
         if (z0 >= z1) return;  // empty column: no loads
         float u0[3];
         load_u(z0, u0);
-        issue(z0, u0);
-        if (z0 + 1 < z1) load_u(z0 + 1, un);
+        issue(z0, u0, p[0]);
+        load_u(min(z0 + 1, z1 - 1), un[1]);
     }
     __device__ void load_u(int zz, float* o)
     {
@@ -239,21 +244,22 @@ struct ColumnSampler {
         }
         else { o[0] = 0.f; o[1] = 0.f; o[2] = 0.f; }
     }
-    __device__ void issue(int zz, const float* uu)
+    __device__ void issue(int zz, const float* uu, MiPend& g)
     {
         float dx, dy, dz;
         if (AFF) affine_disp(a.aff, x, y, zz, uu[0], uu[1], uu[2], dx, dy, dz);
         else { dx = uu[0]; dy = uu[1]; dz = uu[2]; }
-        mi_issue<PAD>(a, x, y, zz, dx, dy, dz, zz * HW + y * a.W + x, pend);
+        mi_issue<PAD>(a, x, y, zz, dx, dy, dz, zz * HW + y * a.W + x, g);
     }
-    // the loads of z (issued one step ago); issues those of z + 1
-    __device__ MiPend next(int z)
+    // the loads of z (issued one step ago); issues those of z + 1 and u of
+    // z + 2, clamped into the column (past its end they repeat the last
+    // slice and are never used)
+    template <int S>
+    __device__ MiPend step(int z)
     {
-        const MiPend cur = pend;
-        if (z + 1 < z1) {
-            issue(z + 1, un);
-            if (z + 2 < z1) load_u(z + 2, un);
-        }
+        const MiPend cur = p[S];
+        issue(min(z + 1, z1 - 1), un[1 - S], p[1 - S]);
+        load_u(min(z + 2, z1 - 1), un[S]);
         return cur;
     }
 };
@@ -327,27 +333,32 @@ __global__ void __launch_bounds__(MI_NT) mi_hist_kernel(MiArgs a, unsigned long 
         }
     };
 
+    auto voxel = [&](const MiPend& sp) {
+        const float fv = sp.f;
+        const float mv = mi_interp<PAD, false>(sp).v;
+        bad |= (fv != fv) || (mv != mv);
+        int jf, jm;
+        float wf[4], wm[4], dd[4];
+        parzen4<HARD, false>(fv, B, jf, wf, dd);
+        parzen4<HARD, false>(mv, B, jm, wm, dd);
+        if (jf != cm || jm != cn) {
+            if (cm != -1000) flush();
+            cm = jf; cn = jm;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) acc[i * 4 + jj] = fmaf(wf[i], wm[jj], acc[i * 4 + jj]);
+    };
     if (active && zb < ze) {
         ColumnSampler<PAD, AFF> cs(a, x, y, zb, ze);
-        for (int z = zb; z < ze; ++z) {
-            const MiPend sp = cs.next(z);
-            const float fv = sp.f;
-            const float mv = mi_interp<PAD, false>(sp).v;
-            bad |= (fv != fv) || (mv != mv);
-            int jf, jm;
-            float wf[4], wm[4], dd[4];
-            parzen4<HARD, false>(fv, B, jf, wf, dd);
-            parzen4<HARD, false>(mv, B, jm, wm, dd);
-            if (jf != cm || jm != cn) {
-                if (cm != -1000) flush();
-                cm = jf; cn = jm;
-#pragma unroll
-                for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) acc[i * 4 + jj] = fmaf(wf[i], wm[jj], acc[i * 4 + jj]);
+        for (int z = zb; z < ze; z += 2) {
+            const MiPend s0 = cs.template step<0>(z);
+            voxel(s0);
+            const MiPend s1 = cs.template step<1>(z + 1);
+            if (z + 1 < ze) voxel(s1);
         }
         if (cm != -1000) flush();
     }
@@ -390,25 +401,30 @@ __global__ void __launch_bounds__(MI_NT) mi_count_kernel(MiArgs a, unsigned long
     int cur = -1;
     unsigned run = 0u;
     bool bad = false;
+    auto voxel = [&](const MiPend& sp) {
+        const float fv = sp.f;
+        const float mv = mi_interp<PAD, false>(sp).v;
+        bad |= (fv != fv) || (mv != mv);
+        const int bf = exact_bin(fminf(fmaxf(fv, 0.0f), 1.0f), B);
+        const int bm = exact_bin(fminf(fmaxf(mv, 0.0f), 1.0f), B);
+        const int q = bf * B + bm;
+        if (q != cur) {
+            if (run) {
+                if (glob) atomicAdd(&ghist[cur], (unsigned long long)run);
+                else atomicAdd(&mine[cur], run);
+            }
+            cur = q;
+            run = 0u;
+        }
+        ++run;
+    };
     if (active && zb < ze) {
         ColumnSampler<PAD, AFF> cs(a, x, y, zb, ze);
-        for (int z = zb; z < ze; ++z) {
-            const MiPend sp = cs.next(z);
-            const float fv = sp.f;
-            const float mv = mi_interp<PAD, false>(sp).v;
-            bad |= (fv != fv) || (mv != mv);
-            const int bf = exact_bin(fminf(fmaxf(fv, 0.0f), 1.0f), B);
-            const int bm = exact_bin(fminf(fmaxf(mv, 0.0f), 1.0f), B);
-            const int q = bf * B + bm;
-            if (q != cur) {
-                if (run) {
-                    if (glob) atomicAdd(&ghist[cur], (unsigned long long)run);
-                    else atomicAdd(&mine[cur], run);
-                }
-                cur = q;
-                run = 0u;
-            }
-            ++run;
+        for (int z = zb; z < ze; z += 2) {
+            const MiPend s0 = cs.template step<0>(z);
+            voxel(s0);
+            const MiPend s1 = cs.template step<1>(z + 1);
+            if (z + 1 < ze) voxel(s1);
         }
         if (run) {
             if (glob) atomicAdd(&ghist[cur], (unsigned long long)run);
@@ -601,52 +617,67 @@ __global__ void __launch_bounds__(MI_NT) mi_grad_kernel(MiArgs a, const float* _
     const size_t N = (size_t)a.D * HW;
     const bool active = x < W && y < H;
     const bool colroi = active && x >= a.roi[4] && x < a.roi[5] && y >= a.roi[2] && y < a.roi[3];
+    // Every lane samples: lanes past the array read a valid column and lanes
+    // outside the ROI columns have their gradient zeroed, so the sampling
+    // branches depend only on z (uniform over the block) and no lane skips
+    // the pipelined loads (see ColumnSampler).
+    const int xc = min(x, W - 1), yc = min(y, H - 1);
     double acc[AFF ? 12 : 1];
 #pragma unroll
     for (int q = 0; q < (AFF ? 12 : 1); ++q) acc[q] = 0.0;
-    const int zr0 = max(zb, a.roi[0]), zr1 = min(ze, a.roi[1]);  // ROI part of this column
-    const bool samp = !HARD && colroi && zr0 < zr1;
-    ColumnSampler<PAD, AFF> cs(a, x, y, samp ? zr0 : 0, samp ? zr1 : 0);
-    for (int z = zb; active && z < ze; ++z) {
-        const int idx = z * HW + y * W + x;
-        float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-        if (samp && z >= zr0 && z < zr1) {
-            const MiPend cur = cs.next(z);
-            const Tri t = mi_interp<PAD, true>(cur);
-            int jf, jm;
-            float wf[4], wm[4], dm[4], dd[4];
-            parzen4<false, false>(cur.f, B, jf, wf, dd);
-            parzen4<false, true>(t.v, B, jm, wm, dm);
-            float S = 0.0f;
-            if (TP > 0) {
-                const float* base = Ts + (jf + 2) * TP + (jm + 2);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    float si = 0.0f;
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) si = fmaf(dm[jj], base[i * TP + jj], si);
-                    S = fmaf(wf[i], si, S);
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float* row = state + fold(jf + i, B) * B;
-                    float si = 0.0f;
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) si = fmaf(dm[jj], row[fold(jm + jj, B)], si);
-                    S = fmaf(wf[i], si, S);
-                }
-            }
-            const float gm = g * S;
-            g0 = gm * t.dx; g1 = gm * t.dy; g2 = gm * t.dz;
-            if (AFF) affine_adjoint(a.aff, x, y, z, g0, g1, g2, acc, g0, g1, g2);
-        }
-        if (!AFF || gu) {
-            __builtin_nontemporal_store(g0, gu + idx);  // written once, never read here
+    const int zr0 = max(zb, a.roi[0]), zr1 = min(ze, a.roi[1]);  // ROI slices of this chunk
+    const bool samp = !HARD && zr0 < zr1;
+    const int s0 = samp ? zr0 : ze, s1 = samp ? zr1 : ze;      // sampled slices [s0, s1)
+    auto store = [&](int z, float g0, float g1, float g2) {
+        if (active && (!AFF || gu)) {
+            const int idx = z * HW + y * W + x;  // written once, never read here
+            __builtin_nontemporal_store(g0, gu + idx);
             __builtin_nontemporal_store(g1, gu + N + idx);
             __builtin_nontemporal_store(g2, gu + 2 * N + idx);
         }
+    };
+    auto voxel = [&](int z, const MiPend& cur) {
+        const Tri t = mi_interp<PAD, true>(cur);
+        int jf, jm;
+        float wf[4], wm[4], dm[4], dd[4];
+        parzen4<false, false>(cur.f, B, jf, wf, dd);
+        parzen4<false, true>(t.v, B, jm, wm, dm);
+        float S = 0.0f;
+        if (TP > 0) {
+            const float* base = Ts + (jf + 2) * TP + (jm + 2);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float si = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) si = fmaf(dm[jj], base[i * TP + jj], si);
+                S = fmaf(wf[i], si, S);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float* row = state + fold(jf + i, B) * B;
+                float si = 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) si = fmaf(dm[jj], row[fold(jm + jj, B)], si);
+                S = fmaf(wf[i], si, S);
+            }
+        }
+        const float gm = colroi ? g * S : 0.0f;
+        float g0 = gm * t.dx, g1 = gm * t.dy, g2 = gm * t.dz;
+        if (AFF) affine_adjoint(a.aff, xc, yc, z, g0, g1, g2, acc, g0, g1, g2);
+        store(z, g0, g1, g2);
+    };
+    for (int z = zb; z < s0; ++z) store(z, 0.f, 0.f, 0.f);
+    if (s0 < s1) {
+        ColumnSampler<PAD, AFF> cs(a, xc, yc, s0, s1);
+        for (int z = s0; z < s1; z += 2) {
+            const MiPend c0 = cs.template step<0>(z);
+            voxel(z, c0);
+            const MiPend c1 = cs.template step<1>(z + 1);
+            if (z + 1 < s1) voxel(z + 1, c1);
+        }
     }
+    for (int z = s1; z < ze; ++z) store(z, 0.f, 0.f, 0.f);
     if (AFF) {
         __shared__ double red[MI_NT];
 #pragma unroll
