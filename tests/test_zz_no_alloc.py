@@ -43,6 +43,7 @@ def test_noalloc_matches_workspace_entry_point_twice():
     L = _lib.lib()
     stream = torch.cuda.current_stream(torch.device(DEV)).cuda_stream
     for k, (shape, roi, window, ants) in enumerate([((40, 56, 72), ((3, 37), (2, 50), (5, 70)), 5, 0),
+                                                    ((30, 40, 50), None, 7, 0),
                                                     ((24, 32, 40), None, 3, 0),
                                                     ((12, 14, 16), None, 15, 0)]):
         p = synth.make_pair(synth.PairSpec(shape, (3.0, 6.0), 3.0), seed=synth.BASE_SEED + 40 + k, device=DEV)
