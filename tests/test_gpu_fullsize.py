@@ -3,8 +3,8 @@ benchmark times: the 512^3 pair and the 1040^3 pair with its 8-voxel halo
 (ROI [8, 1032)^3, the windowed 32-bit addressing path).  The oracle cannot
 take these volumes whole in seconds, so it checks
 
-* the LNCC dloss/du at 64+ sampled voxels (w = 5; w = 11, through the
-  separable FP64 passes, at 16 of them), from crops: the adjoint at voxel
+* the LNCC dloss/du at 64+ sampled voxels (w = 5; w = 7 and w = 11, the
+  latter through the separable FP64 passes, at 16 of them), from crops: the adjoint at voxel
   k depends on F, M and u within 2r + |u| + 1 of k and is linear in
   1/N_roi, so the oracle run on a crop (with the crop's share of the ROI)
   times N_roi(crop) / N_roi(full) is the full-volume value.  The samples
@@ -172,30 +172,32 @@ def _check(wl, box, n_random):
     bad = [(samples[i], got_all[i], refs[i]) for i in np.nonzero(err > 1e-4 * scale)[0]]
     assert not bad, bad[:5]
 
-    # the separable FP64 passes of the wide windows (w = 11) at 16 of the
-    # samples, the crops widened by the larger window radius
+    # w = 7 (the 32 x 24-tile adjoint) and w = 11 (the separable FP64
+    # passes of the wide windows) at 16 of the samples, the crops widened by
+    # the larger window radius
     sw = samples[:: max(1, len(samples) // 16)]
-    print(f"[fullsize {wl.name}: w = 11 adjoint at {len(sw)} sampled voxels]", flush=True)
-    g, _ = ops.warp_lncc_bwd(F, M, u, window=11, roi=roi)
-    got11 = g[:, [k[0] for k in sw], [k[1] for k in sw], [k[2] for k in sw]].double().cpu().numpy().T
-    del g
-    torch.cuda.empty_cache()
-    refs = []
-    for k in sw:
-        lo, hi = _crop_bounds(k, [c + 1 for c in k], shape, 2 * (REACH + 3))
-        croi = _rel_roi(roi, lo, hi)
-        if any(b <= a for a, b in croi):
-            refs.append(np.zeros(3))
-            continue
-        ref = oracle.lncc_grad_u_at(_crop(F, lo, hi), _crop(M, lo, hi), _crop(u, lo, hi),
-                                    [[k[0] - lo[0], k[1] - lo[1], k[2] - lo[2]]], roi=_roi6(croi), window=11)[0]
-        refs.append(ref * _nvox(croi) / n_full)
-    refs = np.array(refs)
-    scale = np.abs(refs).max()
-    assert scale > 0
-    err = np.abs(got11 - refs).max(axis=1)
-    bad = [(sw[i], got11[i], refs[i]) for i in np.nonzero(err > 1e-4 * scale)[0]]
-    assert not bad, bad[:5]
+    for win in (7, 11):
+        print(f"[fullsize {wl.name}: w = {win} adjoint at {len(sw)} sampled voxels]", flush=True)
+        g, _ = ops.warp_lncc_bwd(F, M, u, window=win, roi=roi)
+        got_w = g[:, [k[0] for k in sw], [k[1] for k in sw], [k[2] for k in sw]].double().cpu().numpy().T
+        del g
+        torch.cuda.empty_cache()
+        refs = []
+        for k in sw:
+            lo, hi = _crop_bounds(k, [c + 1 for c in k], shape, 2 * (REACH + (win - 5) // 2))
+            croi = _rel_roi(roi, lo, hi)
+            if any(b <= a for a, b in croi):
+                refs.append(np.zeros(3))
+                continue
+            ref = oracle.lncc_grad_u_at(_crop(F, lo, hi), _crop(M, lo, hi), _crop(u, lo, hi),
+                                        [[k[0] - lo[0], k[1] - lo[1], k[2] - lo[2]]], roi=_roi6(croi), window=win)[0]
+            refs.append(ref * _nvox(croi) / n_full)
+        refs = np.array(refs)
+        scale = np.abs(refs).max()
+        assert scale > 0
+        err = np.abs(got_w - refs).max(axis=1)
+        bad = [(sw[i], got_w[i], refs[i]) for i in np.nonzero(err > 1e-4 * scale)[0]]
+        assert not bad, (win, bad[:5])
 
     print(f"[fullsize {wl.name}: MI adjoint at sampled voxels, full-ROI PMF]", flush=True)
     Fh, Mh, uh = F.cpu().numpy(), M.cpu().numpy(), u.cpu().numpy()
