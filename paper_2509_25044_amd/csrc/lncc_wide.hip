@@ -17,14 +17,16 @@
 //   2. wide_z_kernel<MODE>: per (x, y) column, a running FP64 z-window sum of
 //      S gives the box sums; the statistics, the loss term (FP64 block
 //      partials, fixed-order finalize) and a, c, e (zero outside the ROI)
-//      -> E[3][N].  The ANTs mode (App. "ANTs gradient approximation") writes
-//      its gradient here and stops;
-//   3. wide_xy_kernel<3, LOAD>: xy box of E (32 x 16 tiles) -> T[3][N], stored over S;
-//   4. wide_grad_kernel: running z-window sum of T, Mw and dMw/dp resampled at
-//      the voxel, grad_u written over the whole array.
-// FP64 makes the cancellation in B = mu_FF - mu_F^2 and in the final
-// combination harmless without a shift, and keeps the running sums free of
-// drift over thousands of slices.
+//      -> E[3][N] in fp32.  The ANTs mode (App. "ANTs gradient
+//      approximation") writes its gradient here and stops;
+//   3. wide_xy_kernel<3, LOAD>: xy box of E (32 x 16 tiles, FP64 sums)
+//      -> T[3][N] in fp32, stored over S;
+//   4. wide_grad_kernel: running FP64 z-window sum of T, Mw and dMw/dp
+//      resampled at the voxel, grad_u written over the whole array.
+// FP64 for S makes the cancellation in B = mu_FF - mu_F^2 harmless without a
+// shift; every running sum accumulates in FP64 registers, free of drift over
+// thousands of slices.  a, c, e and their xy sums are stored in fp32 (the
+// precision the fused kernel keeps them in), which halves their traffic.
 #include <type_traits>
 
 #include "device.hpp"
@@ -55,8 +57,8 @@ struct WideArgs {
     const float* u;
     float* gu;
     const float* grad_scale;
-    double* S;        // [5][N] xy sums, later [3][N] xy sums of a, c, e
-    double* E;        // [3][N] a, c, e
+    double* S;        // [5][N] xy sums (FP64); later [3][N] xy sums of a, c, e (fp32) over it
+    float* E;         // [3][N] a, c, e (fp32, as the fused kernel keeps them)
     double* partial;  // [nblocks of the z passes]
     int D, H, W;
     int roi[6];
@@ -120,19 +122,20 @@ __device__ __forceinline__ Tri wide_sample(const float* __restrict__ M, int D, i
 }
 
 // Pass 1 (SAMPLE: F and Mw staged as floats, the five products formed in
-// FP64, exactly, inside the x-window) and pass 3 (LOAD: the three fields a,
-// c, e staged as doubles).  A 32 x TY slice tile plus an r halo is staged in
-// LDS; the x-window runs over 8 consecutive outputs per thread (one fresh
-// sum, then add the entering and subtract the leaving tap), the y-window over
-// TY / 16 consecutive rows per thread the same way.
+// FP64, exactly, inside the x-window, FP64 sums out) and pass 3 (LOAD: the
+// three fp32 fields a, c, e, summed in FP64, fp32 sums out).  A 32 x TY slice
+// tile plus an r halo is staged in LDS; the x-window runs over 8 consecutive
+// outputs per thread (one fresh sum, then add the entering and subtract the
+// leaving tap), the y-window over TY / 16 consecutive rows per thread the
+// same way.
 template <int NF, bool SAMPLE, int PAD, bool PAIR, int TY>
-__global__ void __launch_bounds__(WXT) wide_xy_kernel(WideArgs a, const double* __restrict__ src,
-                                                      double* __restrict__ dst)
+__global__ void __launch_bounds__(WXT) wide_xy_kernel(WideArgs a, const float* __restrict__ src, void* dstv)
 {
     constexpr int Y2M = TY + 2 * WMAXR;
     constexpr int NL = SAMPLE ? 2 : NF;
-    typedef typename std::conditional<SAMPLE, float, double>::type Lt;
-    __shared__ Lt P[NL][Y2M * WX2];
+    typedef typename std::conditional<SAMPLE, double, float>::type Dt;  // stored sums
+    Dt* __restrict__ dst = static_cast<Dt*>(dstv);
+    __shared__ float P[NL][Y2M * WX2];
     __shared__ double Q[NF][Y2M * WTX];
     const int D = a.D, H = a.H, W = a.W, r = a.r, w = 2 * r + 1;
     const int X2 = WTX + 2 * r, Y2 = TY + 2 * r;
@@ -146,9 +149,9 @@ __global__ void __launch_bounds__(WXT) wide_xy_kernel(WideArgs a, const double* 
     for (int q = threadIdx.x; q < X2 * Y2; q += WXT) {
         const int ly = q / X2, lx = q - ly * X2;
         const int gx = x0 + lx, gy = y0 + ly;
-        Lt v[NL];
+        float v[NL];
 #pragma unroll
-        for (int c = 0; c < NL; ++c) v[c] = 0;  // zero padding outside the array
+        for (int c = 0; c < NL; ++c) v[c] = 0.0f;  // zero padding outside the array
         if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
             const int k = (z * H + gy) * W + gx;
             if (SAMPLE) {
@@ -219,7 +222,7 @@ __global__ void __launch_bounds__(WXT) wide_xy_kernel(WideArgs a, const double* 
         if (gx < W && gy < H) {
             const size_t k = ((size_t)z * H + gy) * W + gx;
 #pragma unroll
-            for (int c = 0; c < NF; ++c) dst[c * N + k] = s[c];
+            for (int c = 0; c < NF; ++c) dst[c * N + k] = (Dt)s[c];
         }
     }
 }
@@ -242,11 +245,11 @@ __device__ __forceinline__ WideCol wide_col(const WideArgs& a)
     return c;
 }
 
-// Running z-window sums of NF fields at column offset col: s holds the sums
-// over slices [z - r, z + r] (clipped to the array) after slide(z).
-template <int NF>
+// Running z-window sums (FP64) of NF fields at column offset col: s holds
+// the sums over slices [z - r, z + r] (clipped to the array) after slide(z).
+template <int NF, typename T>
 struct ZWindow {
-    const double* __restrict__ src;
+    const T* __restrict__ src;
     size_t N, HW, col;
     int D, r;
     double s[NF];
@@ -284,7 +287,7 @@ __global__ void __launch_bounds__(WNT) wide_z_kernel(WideArgs a)
     if (c.x < W && c.y < H && c.z0 < c.z1) {
         const size_t col = (size_t)c.y * W + c.x;
         const bool xyroi = c.y >= a.roi[2] && c.y < a.roi[3] && c.x >= a.roi[4] && c.x < a.roi[5];
-        ZWindow<5> zw{a.S, N, HW, col, D, r, {}};
+        ZWindow<5, double> zw{a.S, N, HW, col, D, r, {}};
         zw.start(c.z0);
         for (int z = c.z0; z < c.z1; ++z) {
             if (z > c.z0) zw.slide(z);
@@ -303,9 +306,9 @@ __global__ void __launch_bounds__(WNT) wide_z_kernel(WideArgs a)
             }
             const size_t k = (size_t)z * HW + col;
             if (MODE == WMODE_BWD) {
-                a.E[k] = av;
-                a.E[N + k] = cv;
-                a.E[2 * N + k] = ev;
+                a.E[k] = (float)av;
+                a.E[N + k] = (float)cv;
+                a.E[2 * N + k] = (float)ev;
             } else if (MODE == WMODE_ANTS) {
                 // the derivative of voxel k's own term, without the second window sum
                 float g0 = 0.f, g1 = 0.f, g2 = 0.f;
@@ -338,7 +341,7 @@ __global__ void __launch_bounds__(WNT) wide_grad_kernel(WideArgs a)
     const size_t N = (size_t)D * H * W, HW = (size_t)H * W;
     const double inv = 1.0 / (double)(w * w * w);
     const size_t col = (size_t)c.y * W + c.x;
-    ZWindow<3> zw{a.S, N, HW, col, D, r, {}};
+    ZWindow<3, float> zw{reinterpret_cast<const float*>(a.S), N, HW, col, D, r, {}};
     zw.start(c.z0);
     for (int z = c.z0; z < c.z1; ++z) {
         if (z > c.z0) zw.slide(z);
@@ -372,12 +375,14 @@ hipError_t wide_run(int mode, const WideArgs& a, const WidePlan& P, hipStream_t 
     const dim3 gs((unsigned)(slices * ((a.H + WTY_S - 1) / WTY_S)));
     const dim3 gl((unsigned)(slices * ((a.H + WTY_L - 1) / WTY_L)));
     const dim3 gz((unsigned)P.nblocks);
-    hipLaunchKernelGGL((wide_xy_kernel<5, true, PAD, PAIR, WTY_S>), gs, dim3(WXT), 0, st, a, nullptr, a.S);
+    hipLaunchKernelGGL((wide_xy_kernel<5, true, PAD, PAIR, WTY_S>), gs, dim3(WXT), 0, st, a, nullptr,
+                       static_cast<void*>(a.S));
     if (mode == WMODE_FWD) hipLaunchKernelGGL((wide_z_kernel<WMODE_FWD, PAD>), gz, blk, 0, st, a);
     else if (mode == WMODE_ANTS) hipLaunchKernelGGL((wide_z_kernel<WMODE_ANTS, PAD>), gz, blk, 0, st, a);
     else {
         hipLaunchKernelGGL((wide_z_kernel<WMODE_BWD, PAD>), gz, blk, 0, st, a);
-        hipLaunchKernelGGL((wide_xy_kernel<3, false, PAD, false, WTY_L>), gl, dim3(WXT), 0, st, a, a.E, a.S);
+        hipLaunchKernelGGL((wide_xy_kernel<3, false, PAD, false, WTY_L>), gl, dim3(WXT), 0, st, a, a.E,
+                           static_cast<void*>(a.S));
         hipLaunchKernelGGL((wide_grad_kernel<PAD, PAIR>), gz, blk, 0, st, a);
     }
     return hipGetLastError();
@@ -418,7 +423,7 @@ hipError_t lncc_wide_launch(int mode, int win, int pad, const LnccArgs& la, void
     WideArgs a;
     a.F = la.F; a.M = la.M; a.u = la.u; a.gu = la.gu; a.grad_scale = la.grad_scale;
     a.S = static_cast<double*>(ws);
-    a.E = a.S + 5 * N;
+    a.E = reinterpret_cast<float*>(a.S + 5 * N);
     a.partial = a.S + 8 * N;
     a.D = la.D; a.H = la.H; a.W = la.W;
     for (int q = 0; q < 6; ++q) a.roi[q] = la.roi[q];
