@@ -322,6 +322,20 @@ int ffdp_conv3d_fwd(const uint16_t* xa, const uint16_t* xb, const uint16_t* w, c
 int ffdp_conv3d_bwd_data(const float* dy, const uint16_t* y, float slope, const uint16_t* wt,
                          const ffdp_conv_geom* g, float* dx, int32_t accumulate, void* stream);
 
+/* P = bf16(dy * act'(y)) elementwise over n elements (y NULL: act' = 1),
+ * rounded to nearest even as the backward kernels round their operands; dy
+ * fp32, y and p bf16, all in the same layout (e.g. [N][Do][Ho][Wo][Cout]).
+ * Lets a layer's backward form P once for ffdp_conv3d_bwd_data_bf16. */
+int ffdp_conv3d_act_grad(const float* dy, const uint16_t* y, float slope, int64_t n, uint16_t* p, void* stream);
+
+/* ffdp_conv3d_bwd_data with P given directly: p bf16 [N][Do][Ho][Wo][Cout]
+ * (16-byte aligned), e.g. from ffdp_conv3d_act_grad.  Bitwise the same dx
+ * as ffdp_conv3d_bwd_data(dy, y, slope, ...) for p = act_grad(dy, y, slope);
+ * one 16-byte operand load per lane and K step instead of three plus the
+ * conversion. */
+int ffdp_conv3d_bwd_data_bf16(const uint16_t* p, const uint16_t* wt, const ffdp_conv_geom* g, float* dx,
+                              int32_t accumulate, void* stream);
+
 /* Backward to the weights: dw[co][t][ci] = sum_o P[o][co] X[o*stride + t - 1][ci]
  * and db[co] = sum_o P[o][co] (db may be NULL), fp32, overwritten; the sums
  * over output voxels run in chunks whose partials (caller workspace) are

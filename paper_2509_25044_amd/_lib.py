@@ -87,6 +87,8 @@ def lib():
         "ffdp_smooth_adam_step": ([vp, vp, vp, vp, i64, i64, i64, i32, f32, f32, f32, f32, f32, i64, vp], C.c_int),
         "ffdp_conv3d_fwd": ([vp, vp, vp, vp, cg, i32, f32, vp, vp, vp], C.c_int),
         "ffdp_conv3d_bwd_data": ([vp, vp, f32, vp, cg, vp, i32, vp], C.c_int),
+        "ffdp_conv3d_act_grad": ([vp, vp, f32, i64, vp, vp], C.c_int),
+        "ffdp_conv3d_bwd_data_bf16": ([vp, vp, cg, vp, i32, vp], C.c_int),
         "ffdp_conv3d_bwd_weight_workspace_bytes": ([cg], sz),
         "ffdp_conv3d_bwd_weight": ([vp, vp, vp, vp, f32, cg, vp, vp, vp, sz, vp], C.c_int),
         "ffdp_conv3d_weight_prep": ([vp, i32, i32, vp, vp, vp], C.c_int),

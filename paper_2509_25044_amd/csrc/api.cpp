@@ -12,6 +12,7 @@
 #include "adam.hpp"
 #include "internal.hpp"
 #include "wide.hpp"
+#include "conv_p.hpp"
 
 using namespace ffdp;
 
@@ -726,6 +727,31 @@ int ffdp_conv3d_bwd_data(const float* dy, const uint16_t* y, float slope, const 
     return hip_status(conv_bwd_data_launch(g, dy, (const unsigned short*)y, slope, (const unsigned short*)wt, dx,
                                            accumulate, (hipStream_t)stream),
                       "ffdp_conv3d_bwd_data");
+}
+
+int ffdp_conv3d_act_grad(const float* dy, const uint16_t* y, float slope, int64_t n, uint16_t* p, void* stream)
+{
+    int s;
+    if (n < 0) return fail(FFDP_ERR_SHAPE, "n must be >= 0");
+    if ((s = f32_ptr(dy, "dy", n > 0, 4)) || (s = f32_ptr(y, "y", false, 2)) || (s = f32_ptr(p, "p", n > 0, 2)))
+        return s;
+    return hip_status(act_grad_launch(dy, (const unsigned short*)y, slope, (long long)n, (unsigned short*)p,
+                                      (hipStream_t)stream),
+                      "ffdp_conv3d_act_grad");
+}
+
+int ffdp_conv3d_bwd_data_bf16(const uint16_t* p, const uint16_t* wt, const ffdp_conv_geom* cg, float* dx,
+                              int32_t accumulate, void* stream)
+{
+    ConvGeom g;
+    int s = conv_geom(cg, g, true);
+    if (s) return s;
+    if ((s = f32_ptr(p, "p", true, 16)) || (s = bf16_ptr(wt, "wt", true)) || (s = f32_ptr(dx, "dx", true, 4)))
+        return s;
+    if (accumulate != 0 && accumulate != 1) return fail(FFDP_ERR_PARAM, "accumulate must be 0 or 1");
+    return hip_status(conv_bwd_data_p_launch(g, (const unsigned short*)p, (const unsigned short*)wt, dx, accumulate,
+                                             (hipStream_t)stream),
+                      "ffdp_conv3d_bwd_data_bf16");
 }
 
 size_t ffdp_conv3d_bwd_weight_workspace_bytes(const ffdp_conv_geom* cg)

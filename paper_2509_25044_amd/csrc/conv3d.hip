@@ -29,6 +29,7 @@
 // consecutive voxels per lane).
 #include "device.hpp"
 #include "internal.hpp"
+#include "conv_p.hpp"
 
 namespace ffdp {
 
@@ -236,9 +237,13 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
 // voxels are split into the 8 parity classes of (z, y, x) and a block takes
 // 64 voxels of one class: its K runs over that class's 1 to 8 taps instead
 // of all 27 (3.375 on average), and no product is a structural zero.
-template <int NT, bool C8, bool PAR>
+// PB: P = dL/dy act'(y) arrives precomputed as bf16 in dL/dy's layout (pb),
+// so a lane's 8 K elements are one 16-byte load (4 channels: 8 bytes) and no
+// conversion; dy and y are not read.
+template <int NT, bool C8, bool PAR, bool PB>
 __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const float* __restrict__ dy,
                                                             const unsigned short* __restrict__ y, float slope,
+                                                            const unsigned short* __restrict__ pb,
                                                             const unsigned short* __restrict__ wt,
                                                             float* __restrict__ dx, int accumulate)
 {
@@ -297,7 +302,9 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
     auto load_p4 = [&](int t, int co) {  // P = dL/dy * act'(y) at output channels co..co+3 of tap t
         s4v a = s4v{0, 0, 0, 0};
         const long long o = p_offset(t, co);
-        if (o >= 0) {
+        if (PB) {
+            if (o >= 0) a = ld4bf(pb + o);
+        } else if (o >= 0) {
             const float4 d4 = *reinterpret_cast<const float4*>(dy + o);
             float f[4] = {1.f, 1.f, 1.f, 1.f};
             if (y) {
@@ -312,6 +319,11 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
     auto load_p8 = [&](int t, int co) {  // channels co..co+7 of tap t (C8)
         s4v lo = s4v{0, 0, 0, 0}, hi = s4v{0, 0, 0, 0};
         const long long o = p_offset(t, co);
+        if (PB) {
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (o >= 0) v = *reinterpret_cast<const uint4*>(pb + o);
+            return __builtin_bit_cast(bf8v, v);
+        }
         if (o >= 0) {
             const float4 d0 = *reinterpret_cast<const float4*>(dy + o);
             const float4 d1 = *reinterpret_cast<const float4*>(dy + o + 4);
@@ -1041,33 +1053,73 @@ hipError_t conv_fwd_launch(const ConvGeom& g, const unsigned short* xa, const un
     return hipGetLastError();
 }
 
-template <bool C8, bool PAR>
+template <bool C8, bool PAR, bool PB>
 static void launch_bwd_data(int nt, unsigned blocks, hipStream_t st, const ConvGeom& g, const float* dy,
-                            const unsigned short* y, float slope, const unsigned short* wt, float* dx, int accumulate)
+                            const unsigned short* y, float slope, const unsigned short* pb, const unsigned short* wt,
+                            float* dx, int accumulate)
 {
-    if (nt <= 1) hipLaunchKernelGGL((conv_bwd_data_kernel<1, C8, PAR>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else if (nt <= 2) hipLaunchKernelGGL((conv_bwd_data_kernel<2, C8, PAR>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else if (nt <= 4) hipLaunchKernelGGL((conv_bwd_data_kernel<4, C8, PAR>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else if (nt <= 8) hipLaunchKernelGGL((conv_bwd_data_kernel<8, C8, PAR>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
-    else hipLaunchKernelGGL((conv_bwd_data_kernel<12, C8, PAR>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, wt, dx, accumulate);
+#define BWD_DATA(T) \
+    hipLaunchKernelGGL((conv_bwd_data_kernel<T, C8, PAR, PB>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, pb, wt, dx, accumulate)
+    if (nt <= 1) BWD_DATA(1);
+    else if (nt <= 2) BWD_DATA(2);
+    else if (nt <= 4) BWD_DATA(4);
+    else if (nt <= 8) BWD_DATA(8);
+    else BWD_DATA(12);
+#undef BWD_DATA
 }
 
-hipError_t conv_bwd_data_launch(const ConvGeom& g, const float* dy, const unsigned short* y, float slope,
-                                const unsigned short* wt, float* dx, int accumulate, hipStream_t st)
+template <bool PB>
+static hipError_t bwd_data_dispatch(const ConvGeom& g, const float* dy, const unsigned short* y, float slope,
+                                    const unsigned short* pb, const unsigned short* wt, float* dx, int accumulate,
+                                    hipStream_t st)
 {
     const int nt = (g.Ca + g.Cb + 15) / 16;
     if (nt > 12) return hipErrorInvalidValue;
     if (g.stride == 2) {  // 8 parity classes of the half-resolution grid (rounded up)
         const long long Mc = (long long)g.N * ((g.Di + 1) / 2) * ((g.Hi + 1) / 2) * ((g.Wi + 1) / 2);
         const unsigned blocks = (unsigned)(8 * ((Mc + 63) / 64));
-        if (g.Cout % 8 == 0) launch_bwd_data<true, true>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
-        else launch_bwd_data<false, true>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
+        if (g.Cout % 8 == 0) launch_bwd_data<true, true, PB>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+        else launch_bwd_data<false, true, PB>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
     } else {
         const long long M = (long long)g.N * g.Di * g.Hi * g.Wi;
         const unsigned blocks = (unsigned)((M + 63) / 64);
-        if (g.Cout % 8 == 0) launch_bwd_data<true, false>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
-        else launch_bwd_data<false, false>(nt, blocks, st, g, dy, y, slope, wt, dx, accumulate);
+        if (g.Cout % 8 == 0) launch_bwd_data<true, false, PB>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+        else launch_bwd_data<false, false, PB>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
     }
+    return hipGetLastError();
+}
+
+hipError_t conv_bwd_data_launch(const ConvGeom& g, const float* dy, const unsigned short* y, float slope,
+                                const unsigned short* wt, float* dx, int accumulate, hipStream_t st)
+{
+    return bwd_data_dispatch<false>(g, dy, y, slope, nullptr, wt, dx, accumulate, st);
+}
+
+hipError_t conv_bwd_data_p_launch(const ConvGeom& g, const unsigned short* p, const unsigned short* wt, float* dx,
+                                  int accumulate, hipStream_t st)
+{
+    return bwd_data_dispatch<true>(g, nullptr, nullptr, 0.0f, p, wt, dx, accumulate, st);
+}
+
+// P = bf16(dL/dy act'(y)) elementwise (y NULL: the identity), the rounding of
+// the operand packing in the backward kernels (round to nearest even).
+__global__ void __launch_bounds__(256) act_grad_kernel(const float* __restrict__ dy, const unsigned short* __restrict__ y,
+                                                       float slope, long long n, unsigned short* __restrict__ p)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        float v = dy[i];
+        if (y) v *= lrelu_d(y[i], slope);
+        p[i] = f2bf(v);
+    }
+}
+
+hipError_t act_grad_launch(const float* dy, const unsigned short* y, float slope, long long n, unsigned short* p,
+                           hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(act_grad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dy, y, slope, n, p);
     return hipGetLastError();
 }
 

@@ -489,6 +489,35 @@ def conv3d_bwd_data(dy, y, wt_bf16, g: ConvGeom, slope=0.2, dx=None, accumulate=
     return dx
 
 
+def conv3d_act_grad(dy, y, slope=0.2, p=None):
+    """P = bf16(dy * act'(y)) in dy's layout (ffdp_conv3d_act_grad); y None: no activation."""
+    _out(dy, "dy", tuple(dy.shape), dy.device)
+    if y is not None:
+        _out(y, "y", tuple(dy.shape), dy.device, torch.bfloat16)
+    if p is None:
+        p = torch.empty(tuple(dy.shape), dtype=torch.bfloat16, device=dy.device)
+    else:
+        _out(p, "p", tuple(dy.shape), dy.device, torch.bfloat16)
+    check("ffdp_conv3d_act_grad", _lib.lib().ffdp_conv3d_act_grad(_ptr(dy), _ptr(y), float(slope), int(dy.numel()),
+                                                                  _ptr(p), _stream(dy)))
+    return p
+
+
+def conv3d_bwd_data_bf16(p, wt_bf16, g: ConvGeom, dx=None, accumulate=False):
+    """ffdp_conv3d_bwd_data from P (bf16 [N][Do][Ho][Wo][Cout], ffdp_conv3d_bwd_data_bf16)."""
+    oshape = (g.N,) + conv_out_shape(g) + (g.Cout,)
+    _out(p, "p", oshape, p.device, torch.bfloat16)
+    _out(wt_bf16, "wt_bf16", (g.Ca + g.Cb, 27, g.Cout), p.device, torch.bfloat16)
+    if dx is None:
+        dx = torch.empty((g.N, g.Di, g.Hi, g.Wi, g.Ca + g.Cb), dtype=torch.float32, device=p.device)
+    else:
+        _out(dx, "dx", (g.N, g.Di, g.Hi, g.Wi, g.Ca + g.Cb), p.device)
+    check("ffdp_conv3d_bwd_data_bf16", _lib.lib().ffdp_conv3d_bwd_data_bf16(_ptr(p), _ptr(wt_bf16), C.byref(g),
+                                                                            _ptr(dx), int(bool(accumulate)),
+                                                                            _stream(p)))
+    return dx
+
+
 def conv3d_bwd_weight(xa, xb, dy, y, g: ConvGeom, slope=0.2, dw=None, db=None, ws=None):
     """(dW [Cout][27][Cin], db [Cout]) fp32 (ffdp_conv3d_bwd_weight)."""
     L = _lib.lib()

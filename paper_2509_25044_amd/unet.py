@@ -185,16 +185,18 @@ class UNet3D:
                                   db=self.b(L.name, self.grad), ws=self._ws)
             if L.a == "x":
                 continue
+            p = ops.conv3d_act_grad(dy, y, slope=SLOPE)  # bf16 dL/dy act'(y), read 27 times below
             if L.ups:
-                dxc = ops.conv3d_bwd_data(dy, y, self.wt[L.name], g, slope=SLOPE)
+                dxc = ops.conv3d_bwd_data_bf16(p, self.wt[L.name], g)
                 dxa, dxb = ops.concat_grad_split(dxc, g)
                 grads[L.a] = dxa
                 grads[L.b] = dxb  # first contribution to the skip's gradient
                 del dxc
             elif L.a in grads:
-                ops.conv3d_bwd_data(dy, y, self.wt[L.name], g, slope=SLOPE, dx=grads[L.a], accumulate=True)
+                ops.conv3d_bwd_data_bf16(p, self.wt[L.name], g, dx=grads[L.a], accumulate=True)
             else:
-                grads[L.a] = ops.conv3d_bwd_data(dy, y, self.wt[L.name], g, slope=SLOPE)
+                grads[L.a] = ops.conv3d_bwd_data_bf16(p, self.wt[L.name], g)
+            del p
             grads.pop(L.name, None)
         return self.grad
 

@@ -83,6 +83,11 @@ def test_conv_backward(case):
     assert_grad(dx.cpu().numpy(), ref_dx, "bwd data")
     dx2 = ops.conv3d_bwd_data(dy.to(DEV), y, wt, geom, slope=SLOPE, dx=dx.clone(), accumulate=True)
     assert_grad(dx2.cpu().numpy(), 2 * ref_dx, "bwd data accumulate")
+    # the same from P formed once in bf16: P itself bit for bit, dx bit for bit
+    pb = ops.conv3d_act_grad(dy.to(DEV), y, slope=SLOPE)
+    assert torch.equal(pb.cpu(), _bf(P))
+    assert torch.equal(ops.conv3d_bwd_data_bf16(pb, wt, geom), dx)
+    assert torch.equal(ops.conv3d_bwd_data_bf16(pb, wt, geom, dx=dx.clone(), accumulate=True), dx2)
     dw, db = ops.conv3d_bwd_weight(xad, xbd, dy.to(DEV), y, geom, slope=SLOPE)
     ref_dw, ref_db = oracle.conv3d_bwd_weight(xa.double(), None if xb is None else xb.double(), P, N, Di, Hi, Wi, Ca,
                                               Cb, Cout, stride=s, ups=ups)
@@ -99,6 +104,9 @@ def test_no_activation_backward():
     P = _bf(dy).double()
     dx = ops.conv3d_bwd_data(dy.to(DEV), None, wt, geom)
     assert_grad(dx.cpu().numpy(), oracle.conv3d_bwd_data(P, wbf.cpu().double(), N, Di, Hi, Wi, Ca, Cb, Cout), "dx")
+    pb = ops.conv3d_act_grad(dy.to(DEV), None)
+    assert torch.equal(pb.cpu(), _bf(dy))
+    assert torch.equal(ops.conv3d_bwd_data_bf16(pb, wt, geom), dx)
     dw, db = ops.conv3d_bwd_weight(xa.to(DEV), None, dy.to(DEV), None, geom)
     rdw, rdb = oracle.conv3d_bwd_weight(xa.double(), None, P, N, Di, Hi, Wi, Ca, Cb, Cout)
     assert_grad(dw.cpu().numpy(), rdw, "dw")
