@@ -358,7 +358,8 @@ int ffdp_unet_pack_pair(const float* F, const float* M, int64_t nvox, uint16_t* 
 /* Split dx of a concatenated input (layout of ffdp_conv3d_bwd_data) into the
  * skip part dxb [N][Di][Hi][Wi][Cb] and part a, summed over each 2x2x2 block
  * when ups = 1 (the adjoint of nearest upsampling) into dxa
- * [N][Di/2][Hi/2][Wi/2][Ca]; acc_a / acc_b = 1 add instead of overwrite. */
+ * [N][Di/2][Hi/2][Wi/2][Ca]; acc_a / acc_b = 1 add instead of overwrite.
+ * All three pointers 16-byte aligned (FFDP_ERR_ALIGN otherwise). */
 int ffdp_concat_grad_split(const float* dxcat, const ffdp_conv_geom* g, float* dxa, float* dxb, int32_t acc_a,
                            int32_t acc_b, void* stream);
 

@@ -806,8 +806,8 @@ int ffdp_concat_grad_split(const float* dxcat, const ffdp_conv_geom* cg, float* 
     int s = conv_geom(cg, g, true);
     if (s) return s;
     if (!g.ups) return fail(FFDP_ERR_PARAM, "ffdp_concat_grad_split needs ups = 1");
-    if ((s = f32_ptr(dxcat, "dxcat", true, 4)) || (s = f32_ptr(dxa, "dxa", true, 4)) ||
-        (s = f32_ptr(dxb, "dxb", g.Cb > 0, 4)))
+    if ((s = f32_ptr(dxcat, "dxcat", true, 16)) || (s = f32_ptr(dxa, "dxa", true, 16)) ||
+        (s = f32_ptr(dxb, "dxb", g.Cb > 0, 16)))
         return s;
     return hip_status(split_grad_launch(g, dxcat, dxa, dxb, acc_a ? 1 : 0, acc_b ? 1 : 0, (hipStream_t)stream),
                       "ffdp_concat_grad_split");

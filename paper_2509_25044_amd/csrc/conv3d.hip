@@ -846,15 +846,31 @@ static int wgrad_rows_ng(const ConvGeom& g)
     return c16 >= 64 ? 16 : c16 / 4;
 }
 
-// dW[q] = sum_c part[c][q] (fixed order), dW fp32
+// dW[q] = sum_c part[c][q], dW fp32.  A block takes 64 consecutive q; its 4
+// waves sum the parts c = w, w + 4, ... (w = wave) with 8 loads in flight,
+// then the 4 wave sums are added in wave order (a fixed order throughout).
 __global__ void __launch_bounds__(256) reduce_parts_kernel(const float* __restrict__ part, int nparts, long long q_n,
                                                            float* __restrict__ out)
 {
-    for (long long q = (long long)blockIdx.x * 256 + threadIdx.x; q < q_n; q += (long long)gridDim.x * 256) {
-        float s = 0.f;
-        for (int c = 0; c < nparts; ++c) s += part[(size_t)c * q_n + q];
-        out[q] = s;
+    __shared__ float red[4][64];
+    const int l = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+    const long long q = (long long)blockIdx.x * 64 + l;
+    float s = 0.f;
+    if (q < q_n) {
+        const float* src = part + q;
+        int c = w;
+        for (; c + 28 < nparts; c += 32) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = src[(size_t)(c + 4 * k) * q_n];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += v[k];
+        }
+        for (; c < nparts; c += 4) s += src[(size_t)c * q_n];
     }
+    red[w][l] = s;
+    __syncthreads();
+    if (w == 0 && q < q_n) out[q] = ((red[0][l] + red[1][l]) + red[2][l]) + red[3][l];
 }
 
 // bias gradient partials: part[chunk][co] = sum_{o in chunk} P[o][co], one
@@ -939,38 +955,55 @@ __global__ void __launch_bounds__(256) pack_pair_kernel(const float* __restrict_
 // split the gradient of a concatenated, upsampled input: dXcat fp32 [N][Di][Hi][Wi][Ca+Cb]
 //   dxb[n,z,y,x,c]  (+)= dXcat[..., Ca + c]
 //   dxa[n,Z,Y,X,c]  (+)= sum over the 8 fine voxels (2Z+a, 2Y+b, 2X+c) of dXcat[..., c]
+// One block per row: blocks [0, Rf) take the fine rows (n, z, y) of the skip
+// part, blocks [Rf, Rf + Rc) the coarse rows (n, Z, Y) of part a.  A thread
+// owns one 4-channel group q of every nx-th voxel of its row (16-byte loads
+// and stores; Ca and Cb are multiples of 4, the pointers 16-byte aligned).
+// The 8 fine terms of a coarse voxel are added in (a, b, c) order.
 __global__ void __launch_bounds__(256) split_grad_kernel(ConvGeom g, const float* __restrict__ dxc,
                                                          float* __restrict__ dxa, float* __restrict__ dxb, int acc_a,
-                                                         int acc_b)
+                                                         int acc_b, int Rf)
 {
     const int Cin = g.Ca + g.Cb;
-    const long long nfine = (long long)g.N * g.Di * g.Hi * g.Wi;
-    const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
-    const long long ncoarse = (long long)g.N * Da * Ha * Wa;
-    const long long tb = nfine * g.Cb, ta = ncoarse * g.Ca;
-    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < tb + ta; i += (long long)gridDim.x * 256) {
-        if (i < tb) {
-            const long long v = i / g.Cb;
-            const int c = (int)(i - v * g.Cb);
-            const float s = dxc[v * Cin + g.Ca + c];
-            dxb[i] = acc_b ? dxb[i] + s : s;
-        } else {
-            const long long j = i - tb;
-            long long v = j / g.Ca;
-            const int c = (int)(j - v * g.Ca);
-            const int X = (int)(v % Wa); v /= Wa;
-            const int Y = (int)(v % Ha); v /= Ha;
-            const int Z = (int)(v % Da);
-            const int n = (int)(v / Da);
-            float s = 0.f;
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b)
-                    for (int cc = 0; cc < 2; ++cc) {
-                        const size_t f = (((size_t)n * g.Di + 2 * Z + a) * g.Hi + 2 * Y + b) * g.Wi + 2 * X + cc;
-                        s += dxc[f * Cin + c];
-                    }
-            dxa[j] = acc_a ? dxa[j] + s : s;
+    const int r = (int)blockIdx.x;
+    if (r < Rf) {
+        const int G = g.Cb >> 2, q = (int)threadIdx.x % G, nx = 256 / G;
+        const int xs = (int)threadIdx.x / G;
+        if (xs >= nx) return;
+        const size_t base = (size_t)r * g.Wi;
+        for (int x = xs; x < g.Wi; x += nx) {
+            const float4 s = *reinterpret_cast<const float4*>(dxc + (base + x) * Cin + g.Ca + 4 * q);
+            float4* d = reinterpret_cast<float4*>(dxb + (base + x) * g.Cb + 4 * q);
+            if (acc_b) {
+                const float4 o = *d;
+                *d = make_float4(o.x + s.x, o.y + s.y, o.z + s.z, o.w + s.w);
+            } else {
+                *d = s;
+            }
         }
+        return;
+    }
+    const int R = r - Rf;
+    const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
+    const int Y = R % Ha, Z = (R / Ha) % Da, n = R / (Ha * Da);
+    const int G = g.Ca >> 2, q = (int)threadIdx.x % G, nx = 256 / G;
+    const int xs = (int)threadIdx.x / G;
+    if (xs >= nx) return;
+    for (int X = xs; X < Wa; X += nx) {
+        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 2; ++c) {
+                    const size_t f = (((size_t)n * g.Di + 2 * Z + a) * g.Hi + 2 * Y + b) * g.Wi + 2 * X + c;
+                    const float4 v = *reinterpret_cast<const float4*>(dxc + f * Cin + 4 * q);
+                    s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+                }
+        float4* d = reinterpret_cast<float4*>(dxa + ((size_t)R * Wa + X) * g.Ca + 4 * q);
+        if (acc_a) {
+            const float4 o = *d;
+            s = make_float4(o.x + s.x, o.y + s.y, o.z + s.z, o.w + s.w);
+        }
+        *d = s;
     }
 }
 
@@ -1237,14 +1270,15 @@ hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, c
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long q = (long long)g.Cout * 27 * Cin;
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(grid_for(q)), dim3(256), 0, st, part, p.nchunks, q, dw);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((q + 63) / 64)), dim3(256), 0, st, part, p.nchunks, q, dw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (db) {
         const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
         float* pb = part + (size_t)p.nchunks * q;
         hipLaunchKernelGGL(bias_grad_kernel, dim3(p.nchunks), dim3(256), 0, st, dy, y, slope, M, g.Cout, p.VC, pb);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, pb, p.nchunks, (long long)g.Cout, db);
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((g.Cout + 63) / 64)), dim3(256), 0, st, pb, p.nchunks,
+                           (long long)g.Cout, db);
         e = hipGetLastError();
     }
     return e;
@@ -1273,9 +1307,11 @@ hipError_t pack_pair_launch(const float* F, const float* M, long long nvox, unsi
 hipError_t split_grad_launch(const ConvGeom& g, const float* dxc, float* dxa, float* dxb, int acc_a, int acc_b,
                              hipStream_t st)
 {
-    const long long nfine = (long long)g.N * g.Di * g.Hi * g.Wi;
-    const long long tot = nfine * g.Cb + nfine / 8 * g.Ca;
-    hipLaunchKernelGGL(split_grad_kernel, dim3(grid_for(tot)), dim3(256), 0, st, g, dxc, dxa, dxb, acc_a, acc_b);
+    // rows: below 2^31 / Wi each, as the voxel count is below 2^31
+    const int Rf = g.Cb > 0 ? g.N * g.Di * g.Hi : 0;
+    const int Rc = g.N * (g.Di >> 1) * (g.Hi >> 1);
+    hipLaunchKernelGGL(split_grad_kernel, dim3((unsigned)(Rf + Rc)), dim3(256), 0, st, g, dxc, dxa, dxb, acc_a, acc_b,
+                       Rf);
     return hipGetLastError();
 }
 

@@ -126,6 +126,21 @@ def test_helper_kernels():
     ref_a = dxc[..., :8].reshape(2, 3, 2, 2, 2, 4, 2, 8).sum(dim=(2, 4, 6))
     torch.testing.assert_close(dxb.cpu(), ref_b, rtol=0, atol=0)
     torch.testing.assert_close(dxa.cpu(), ref_a, rtol=1e-6, atol=1e-6)
+    # channel groups that do not divide 256 (Ca = 12, Cb = 20), rows longer
+    # than one pass of the block, accumulation, and no skip part (Cb = 0)
+    for (N, Di, Hi, Wi, Ca, Cb) in [(1, 2, 4, 200, 12, 20), (2, 4, 2, 6, 16, 0)]:
+        geom = ops.conv_geom(N, Di, Hi, Wi, Ca, Cb, 4, 1, True)
+        dxc = torch.randn((N, Di, Hi, Wi, Ca + Cb), generator=g)
+        a0 = torch.randn((N, Di // 2, Hi // 2, Wi // 2, Ca), generator=g)
+        b0 = torch.randn((N, Di, Hi, Wi, Cb), generator=g) if Cb else None
+        dxa, dxb = ops.concat_grad_split(dxc.to(DEV), geom, dxa=a0.to(DEV), dxb=None if b0 is None else b0.to(DEV),
+                                         acc_a=True, acc_b=True)
+        ref_a = dxc[..., :Ca].reshape(N, Di // 2, 2, Hi // 2, 2, Wi // 2, 2, Ca).sum(dim=(2, 4, 6))
+        torch.testing.assert_close(dxa.cpu(), a0 + ref_a, rtol=1e-6, atol=1e-6)
+        if Cb:
+            torch.testing.assert_close(dxb.cpu(), b0 + dxc[..., Ca:], rtol=0, atol=0)
+        else:
+            assert dxb is None
     pred = torch.randn((2, 5, 6, 7, 4), generator=g)
     tgt = torch.randn((2, 3, 5, 6, 7), generator=g)
     loss, dpred = ops.mse_disp(pred.to(DEV), tgt.to(DEV))
