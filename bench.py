@@ -311,11 +311,11 @@ def unet_step_timing(steps: int = 3, batch: int = 4, shape=(160, 192, 224)):
     F, M, T = torch.stack(Fs), torch.stack(Ms), torch.stack(Ts)
     model = unet.UNet3D(dev, seed=0)
     rec = []
-    # backward-data runs as conv3d_act_grad (P in bf16) then conv3d_bwd_data_bf16;
-    # the first is counted into the second's time
+    # a layer's backward is conv3d_act_grad (P in bf16), conv3d_bwd_weight_bf16 and
+    # conv3d_bwd_data_bf16; the P pass is counted into the backward-weight time
     orig = {k: getattr(ops, k) for k in ("conv3d_fwd", "conv3d_act_grad", "conv3d_bwd_data_bf16",
-                                         "conv3d_bwd_weight")}
-    geom_arg = {"conv3d_fwd": 4, "conv3d_act_grad": None, "conv3d_bwd_data_bf16": 2, "conv3d_bwd_weight": 4}
+                                         "conv3d_bwd_weight_bf16")}
+    geom_arg = {"conv3d_fwd": 4, "conv3d_act_grad": None, "conv3d_bwd_data_bf16": 2, "conv3d_bwd_weight_bf16": 3}
 
     def wrap(kind):
         fn = orig[kind]

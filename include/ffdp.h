@@ -342,6 +342,13 @@ int ffdp_conv3d_bwd_data_bf16(const uint16_t* p, const uint16_t* wt, const ffdp_
  * added in a fixed order.  For the stride-2 layers and those with more than
  * 64 output channels the workspace also holds P as bf16 in [Cout][voxel]
  * order (2 bytes per output voxel and channel). */
+/* ffdp_conv3d_bwd_weight with P given directly: p bf16 [N][Do][Ho][Wo][Cout]
+ * (8-byte aligned), e.g. from ffdp_conv3d_act_grad; the same workspace.  The
+ * same dw and db, bit for bit, as ffdp_conv3d_bwd_weight(dy, y, slope, ...)
+ * for p = act_grad(dy, y, slope). */
+int ffdp_conv3d_bwd_weight_bf16(const uint16_t* xa, const uint16_t* xb, const uint16_t* p, const ffdp_conv_geom* g,
+                                float* dw, float* db, void* ws, size_t ws_bytes, void* stream);
+
 size_t ffdp_conv3d_bwd_weight_workspace_bytes(const ffdp_conv_geom* g);
 int ffdp_conv3d_bwd_weight(const uint16_t* xa, const uint16_t* xb, const float* dy, const uint16_t* y, float slope,
                            const ffdp_conv_geom* g, float* dw, float* db, void* ws, size_t ws_bytes, void* stream);

@@ -88,6 +88,7 @@ def lib():
         "ffdp_conv3d_fwd": ([vp, vp, vp, vp, cg, i32, f32, vp, vp, vp], C.c_int),
         "ffdp_conv3d_bwd_data": ([vp, vp, f32, vp, cg, vp, i32, vp], C.c_int),
         "ffdp_conv3d_act_grad": ([vp, vp, f32, i64, vp, vp], C.c_int),
+        "ffdp_conv3d_bwd_weight_bf16": ([vp, vp, vp, cg, vp, vp, vp, sz, vp], C.c_int),
         "ffdp_conv3d_bwd_data_bf16": ([vp, vp, cg, vp, i32, vp], C.c_int),
         "ffdp_conv3d_bwd_weight_workspace_bytes": ([cg], sz),
         "ffdp_conv3d_bwd_weight": ([vp, vp, vp, vp, f32, cg, vp, vp, vp, sz, vp], C.c_int),

@@ -778,6 +778,23 @@ int ffdp_conv3d_bwd_weight(const uint16_t* xa, const uint16_t* xb, const float* 
                       "ffdp_conv3d_bwd_weight");
 }
 
+int ffdp_conv3d_bwd_weight_bf16(const uint16_t* xa, const uint16_t* xb, const uint16_t* p, const ffdp_conv_geom* cg,
+                                float* dw, float* db, void* ws, size_t ws_bytes, void* stream)
+{
+    ConvGeom g;
+    int s = conv_geom(cg, g, true);
+    if (s) return s;
+    if ((s = bf16_ptr(xa, "xa", true)) || (s = bf16_ptr(xb, "xb", g.Cb > 0)) || (s = bf16_ptr(p, "p", true)) ||
+        (s = f32_ptr(dw, "dw", true, 4)) || (s = f32_ptr(db, "db", false, 4)))
+        return s;
+    const size_t need = (size_t)conv_wgrad_plan(g).part_floats * sizeof(float);
+    if (!ws || ws_bytes < need) return fail(FFDP_ERR_WORKSPACE, "workspace of %zu bytes required (got %zu)", need, ws_bytes);
+    if (misaligned_n(ws, 4)) return fail(FFDP_ERR_ALIGN, "workspace must be 4-byte aligned");
+    return hip_status(conv_bwd_weight_p_launch(g, (const unsigned short*)xa, (const unsigned short*)xb,
+                                               (const unsigned short*)p, dw, db, (float*)ws, (hipStream_t)stream),
+                      "ffdp_conv3d_bwd_weight_bf16");
+}
+
 int ffdp_conv3d_weight_prep(const float* w, int32_t Cout, int32_t Cin, uint16_t* w_bf16, uint16_t* wt_bf16,
                             void* stream)
 {

@@ -414,21 +414,26 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
 constexpr int PT_MAXC = 128;
 __global__ void __launch_bounds__(256) p_transpose_kernel(const float* __restrict__ dy,
                                                           const unsigned short* __restrict__ y, float slope,
-                                                          long long M, int Cout, long long MP,
-                                                          unsigned short* __restrict__ pt)
+                                                          const unsigned short* __restrict__ pbf, long long M,
+                                                          int Cout, long long MP, unsigned short* __restrict__ pt)
 {
     __shared__ unsigned short tile[PT_MAXC][64 + 2];
     const long long o0 = (long long)blockIdx.x * 64;
     const long long nv = min(64LL, M - o0);  // <= 0 in the padding past M
     for (int q = threadIdx.x; q < 64 * Cout; q += 256) {
         const int v = q / Cout, co = q - v * Cout;
-        float p = 0.0f;
+        unsigned short h = 0;  // bf16 zero
         if (v < nv) {
             const size_t k = (size_t)(o0 + v) * Cout + co;
-            p = dy[k];
-            if (y) p *= lrelu_d(y[k], slope);
+            if (pbf) {
+                h = pbf[k];
+            } else {
+                float p = dy[k];
+                if (y) p *= lrelu_d(y[k], slope);
+                h = f2bf(p);
+            }
         }
-        tile[co][v] = f2bf(p);
+        tile[co][v] = h;
     }
     __syncthreads();
     for (int q = threadIdx.x; q < Cout * 64; q += 256) {
@@ -672,12 +677,13 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_taps_kernel(ConvGeom g, c
 constexpr int WR_KP = 40;   // LDS row pitch (bf16): 32 voxels + 8
 constexpr int WR_SEG = 30;  // output voxels per row of a step
 __host__ __device__ constexpr int wgrad_rows_yb(int tm) { return tm == 1 ? 4 : (tm == 2 ? 2 : 1); }
-template <int TM, int NG>
+template <int TM, int NG, bool PB>
 __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
                                                               const unsigned short* __restrict__ xb,
                                                               const float* __restrict__ dy,
                                                               const unsigned short* __restrict__ y, float slope,
-                                                              long long VS, float* __restrict__ part)
+                                                              const unsigned short* __restrict__ pbf, long long VS,
+                                                              float* __restrict__ part)
 {
     constexpr int YB = wgrad_rows_yb(TM);  // output rows per step
     constexpr int R = YB + 2;              // ring slots of input rows
@@ -707,7 +713,7 @@ __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const 
 #pragma unroll
     for (int q = 0; q < QI; ++q) acc[q] = f4v{0.f, 0.f, 0.f, 0.f};
     // global loads of one step's operands into registers, raw (xr: 4 bf16
-    // channels of X; dr, yr: dL/dy and y)
+    // channels of X; dr, yr: dL/dy and y, or yr: P in bf16 when PB)
     uint2 xr[XPT], yr[NPT];
     float4 dr[NPT];
     int nrow_ld = 0, row0_ld = 0, y0_ld = 0;  // staged rows yi = y0 + row0 + r, r < nrow
@@ -755,11 +761,15 @@ __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const 
             const int cg = (it % (TM * 4)) * 4, rest = it / (TM * 4);
             const int jx = rest % WR_SEG, jy = rest / WR_SEG;
             dr[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-            yr[u] = make_uint2(0x3f803f80u, 0x3f803f80u);  // y = 1: no activation factor
+            yr[u] = PB ? make_uint2(0u, 0u) : make_uint2(0x3f803f80u, 0x3f803f80u);  // y = 1: no activation factor
             if (it < NP && x0 + jx < g.Wo && y0 + jy < g.Ho && cg < g.Cout) {  // Cout is a multiple of 4
                 const size_t o = ((oplane + y0 + jy) * g.Wo + x0 + jx) * g.Cout + cg;
-                dr[u] = *reinterpret_cast<const float4*>(dy + o);
-                if (y) yr[u] = *reinterpret_cast<const uint2*>(y + o);
+                if (PB) {
+                    yr[u] = *reinterpret_cast<const uint2*>(pbf + o);
+                } else {
+                    dr[u] = *reinterpret_cast<const float4*>(dy + o);
+                    if (y) yr[u] = *reinterpret_cast<const uint2*>(y + o);
+                }
             }
         }
         first = false;
@@ -785,7 +795,7 @@ __global__ void __launch_bounds__(256) conv_wgrad_rows_kernel(ConvGeom g, const 
                                           (unsigned short)(yr[u].y & 0xffffu), (unsigned short)(yr[u].y >> 16)};
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const unsigned short h = f2bf(pv[c] * lrelu_d(yv[c], slope));
+                const unsigned short h = PB ? yv[c] : f2bf(pv[c] * lrelu_d(yv[c], slope));
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) Ps[(((dx * TM * 16 + cg + c) * YB) + jy) * WR_KP + jx + dx] = h;
             }
@@ -878,8 +888,8 @@ __global__ void __launch_bounds__(256) reduce_parts_kernel(const float* __restri
 // load) of the voxels o = t / G, t / G + 256 / G, ... (G = Cout / 4), then
 // the threads of a group are summed in a fixed tree order.
 __global__ void __launch_bounds__(256) bias_grad_kernel(const float* __restrict__ dy, const unsigned short* __restrict__ y,
-                                                        float slope, long long M, int Cout, long long VC,
-                                                        float* __restrict__ part)
+                                                        float slope, const unsigned short* __restrict__ pbf, long long M,
+                                                        int Cout, long long VC, float* __restrict__ part)
 {
     __shared__ float red[4][256];
     const int G = Cout / 4;                  // Cout is a multiple of 4, at most 1024
@@ -890,6 +900,12 @@ __global__ void __launch_bounds__(256) bias_grad_kernel(const float* __restrict_
     if ((int)threadIdx.x < T) {
         for (long long o = ob + vs; o < oe; o += nv) {
             const size_t i = (size_t)o * Cout + 4 * cg;
+            if (pbf) {  // P given in bf16
+                const s4v pv = ld4bf(pbf + i);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) s[c] += bf2f((unsigned short)pv[c]);
+                continue;
+            }
             const float4 d = *reinterpret_cast<const float4*>(dy + i);
             const float pv[4] = {d.x, d.y, d.z, d.w};
             float f[4] = {1.f, 1.f, 1.f, 1.f};
@@ -955,55 +971,57 @@ __global__ void __launch_bounds__(256) pack_pair_kernel(const float* __restrict_
 // split the gradient of a concatenated, upsampled input: dXcat fp32 [N][Di][Hi][Wi][Ca+Cb]
 //   dxb[n,z,y,x,c]  (+)= dXcat[..., Ca + c]
 //   dxa[n,Z,Y,X,c]  (+)= sum over the 8 fine voxels (2Z+a, 2Y+b, 2X+c) of dXcat[..., c]
-// One block per row: blocks [0, Rf) take the fine rows (n, z, y) of the skip
-// part, blocks [Rf, Rf + Rc) the coarse rows (n, Z, Y) of part a.  A thread
-// owns one 4-channel group q of every nx-th voxel of its row (16-byte loads
-// and stores; Ca and Cb are multiples of 4, the pointers 16-byte aligned).
-// The 8 fine terms of a coarse voxel are added in (a, b, c) order.
+// One block per coarse row (n, Z, Y): it writes dxa of that row and dxb of the
+// 4 fine rows (2Z + a, 2Y + b) beneath it, so that the two parts of each
+// fine voxel's channels are read by the same block at about the same time
+// (a cache line holds both).  Work item (X, k): k < Ca/4 sums channel group k
+// of the 8 fine voxels of coarse voxel X (in (a, b, c) order); k = Ca/4 +
+// 8 f + q copies channel group q of the skip part of fine voxel f = 4a + 2b + c.
+// 16-byte loads and stores (Ca and Cb are multiples of 4, the pointers
+// 16-byte aligned).
 __global__ void __launch_bounds__(256) split_grad_kernel(ConvGeom g, const float* __restrict__ dxc,
                                                          float* __restrict__ dxa, float* __restrict__ dxb, int acc_a,
-                                                         int acc_b, int Rf)
+                                                         int acc_b)
 {
     const int Cin = g.Ca + g.Cb;
-    const int r = (int)blockIdx.x;
-    if (r < Rf) {
-        const int G = g.Cb >> 2, q = (int)threadIdx.x % G, nx = 256 / G;
-        const int xs = (int)threadIdx.x / G;
-        if (xs >= nx) return;
-        const size_t base = (size_t)r * g.Wi;
-        for (int x = xs; x < g.Wi; x += nx) {
-            const float4 s = *reinterpret_cast<const float4*>(dxc + (base + x) * Cin + g.Ca + 4 * q);
-            float4* d = reinterpret_cast<float4*>(dxb + (base + x) * g.Cb + 4 * q);
-            if (acc_b) {
-                const float4 o = *d;
-                *d = make_float4(o.x + s.x, o.y + s.y, o.z + s.z, o.w + s.w);
-            } else {
-                *d = s;
-            }
-        }
-        return;
-    }
-    const int R = r - Rf;
+    const int R = (int)blockIdx.x;
     const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
     const int Y = R % Ha, Z = (R / Ha) % Da, n = R / (Ha * Da);
-    const int G = g.Ca >> 2, q = (int)threadIdx.x % G, nx = 256 / G;
-    const int xs = (int)threadIdx.x / G;
-    if (xs >= nx) return;
-    for (int X = xs; X < Wa; X += nx) {
-        float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b)
-                for (int c = 0; c < 2; ++c) {
-                    const size_t f = (((size_t)n * g.Di + 2 * Z + a) * g.Hi + 2 * Y + b) * g.Wi + 2 * X + c;
-                    const float4 v = *reinterpret_cast<const float4*>(dxc + f * Cin + 4 * q);
-                    s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+    const int Ga = g.Ca >> 2, Gb = g.Cb >> 2, K = Ga + 8 * Gb;
+    const int XC = max(1, (1 << 24) / K);  // X positions per pass: 32-bit item indices
+    for (int X0 = 0; X0 < Wa; X0 += XC) {
+        const int nit = min(XC, Wa - X0) * K;
+        for (int it = (int)threadIdx.x; it < nit; it += 256) {
+            const int X = X0 + it / K, k = it % K;
+            if (k < Ga) {
+                float4 s = make_float4(0.f, 0.f, 0.f, 0.f);
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b)
+                        for (int c = 0; c < 2; ++c) {
+                            const size_t f = (((size_t)n * g.Di + 2 * Z + a) * g.Hi + 2 * Y + b) * g.Wi + 2 * X + c;
+                            const float4 v = *reinterpret_cast<const float4*>(dxc + f * Cin + 4 * k);
+                            s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w;
+                        }
+                float4* d = reinterpret_cast<float4*>(dxa + ((size_t)R * Wa + X) * g.Ca + 4 * k);
+                if (acc_a) {
+                    const float4 o = *d;
+                    s = make_float4(o.x + s.x, o.y + s.y, o.z + s.z, o.w + s.w);
                 }
-        float4* d = reinterpret_cast<float4*>(dxa + ((size_t)R * Wa + X) * g.Ca + 4 * q);
-        if (acc_a) {
-            const float4 o = *d;
-            s = make_float4(o.x + s.x, o.y + s.y, o.z + s.z, o.w + s.w);
+                *d = s;
+            } else {
+                const int kk = k - Ga, fv = kk / Gb, q = kk - fv * Gb;
+                const int a = fv >> 2, b = (fv >> 1) & 1, c = fv & 1;
+                const size_t f = (((size_t)n * g.Di + 2 * Z + a) * g.Hi + 2 * Y + b) * g.Wi + 2 * X + c;
+                const float4 s = *reinterpret_cast<const float4*>(dxc + f * Cin + g.Ca + 4 * q);
+                float4* d = reinterpret_cast<float4*>(dxb + f * g.Cb + 4 * q);
+                if (acc_b) {
+                    const float4 o = *d;
+                    *d = make_float4(o.x + s.x, o.y + s.y, o.z + s.z, o.w + s.w);
+                } else {
+                    *d = s;
+                }
+            }
         }
-        *d = s;
     }
 }
 
@@ -1211,29 +1229,31 @@ static void launch_wg_tm(int tnw, dim3 grid, hipStream_t st, const ConvGeom& g, 
     else hipLaunchKernelGGL((conv_bwd_weight_kernel<TM, 3>), grid, dim3(256), 0, st, g, xa, xb, pt, MP, VC, part);
 }
 
-template <int TM>
+template <int TM, bool PB>
 static void launch_wgrad_rows_tm(int ng, dim3 grid, hipStream_t st, const ConvGeom& g, const unsigned short* xa,
                                  const unsigned short* xb, const float* dy, const unsigned short* y, float slope,
-                                 long long VS, float* part)
+                                 const unsigned short* pbf, long long VS, float* part)
 {
-    if (ng == 4) hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 4>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VS, part);
-    else if (ng == 8) hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 8>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VS, part);
-    else if (ng == 12) hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 12>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VS, part);
-    else hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 16>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, VS, part);
+    if (ng == 4) hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 4, PB>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, pbf, VS, part);
+    else if (ng == 8) hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 8, PB>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, pbf, VS, part);
+    else if (ng == 12) hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 12, PB>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, pbf, VS, part);
+    else hipLaunchKernelGGL((conv_wgrad_rows_kernel<TM, 16, PB>), grid, dim3(256), 0, st, g, xa, xb, dy, y, slope, pbf, VS, part);
 }
 
+template <bool PB>
 static void launch_wgrad_rows(int tm, int ng, dim3 grid, hipStream_t st, const ConvGeom& g, const unsigned short* xa,
                               const unsigned short* xb, const float* dy, const unsigned short* y, float slope,
-                              long long VS, float* part)
+                              const unsigned short* pbf, long long VS, float* part)
 {
-    if (tm == 1) launch_wgrad_rows_tm<1>(ng, grid, st, g, xa, xb, dy, y, slope, VS, part);
-    else if (tm == 2) launch_wgrad_rows_tm<2>(ng, grid, st, g, xa, xb, dy, y, slope, VS, part);
-    else launch_wgrad_rows_tm<4>(ng, grid, st, g, xa, xb, dy, y, slope, VS, part);
+    if (tm == 1) launch_wgrad_rows_tm<1, PB>(ng, grid, st, g, xa, xb, dy, y, slope, pbf, VS, part);
+    else if (tm == 2) launch_wgrad_rows_tm<2, PB>(ng, grid, st, g, xa, xb, dy, y, slope, pbf, VS, part);
+    else launch_wgrad_rows_tm<4, PB>(ng, grid, st, g, xa, xb, dy, y, slope, pbf, VS, part);
 }
 
-hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
-                                  const float* dy, const unsigned short* y, float slope, float* dw, float* db,
-                                  float* part, hipStream_t st)
+// P = dL/dy act'(y) from dy and y, or given in bf16 (pbf non-NULL)
+static hipError_t bwd_weight_run(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
+                                 const float* dy, const unsigned short* y, float slope, const unsigned short* pbf,
+                                 float* dw, float* db, float* part, hipStream_t st)
 {
     const ConvWgradPlan p = conv_wgrad_plan(g);
     const int Cin = g.Ca + g.Cb;
@@ -1242,14 +1262,15 @@ hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, c
     if (p.rows) {
         const int ng = wgrad_rows_ng(g);
         dim3 grid(p.nchunks, 3 * ((Cin + 4 * ng - 1) / (4 * ng)));
-        launch_wgrad_rows(tm, ng, grid, st, g, xa, xb, dy, y, slope, p.VS, part);
+        if (pbf) launch_wgrad_rows<true>(tm, ng, grid, st, g, xa, xb, dy, y, slope, pbf, p.VS, part);
+        else launch_wgrad_rows<false>(tm, ng, grid, st, g, xa, xb, dy, y, slope, pbf, p.VS, part);
     } else {
         // P^T first (the voxel-chunk kernels read their A operands from it)
         const long long M = (long long)g.N * g.Do * g.Ho * g.Wo, MP = wgrad_mp(M);
         const uintptr_t pa = reinterpret_cast<uintptr_t>(part + (size_t)p.nchunks * (g.Cout * 27LL * Cin + g.Cout));
         unsigned short* pt = reinterpret_cast<unsigned short*>((pa + 15) & ~(uintptr_t)15);
-        hipLaunchKernelGGL(p_transpose_kernel, dim3((unsigned)((MP + 63) / 64)), dim3(256), 0, st, dy, y, slope, M,
-                           g.Cout, MP, pt);
+        hipLaunchKernelGGL(p_transpose_kernel, dim3((unsigned)((MP + 63) / 64)), dim3(256), 0, st, dy, y, slope, pbf,
+                           M, g.Cout, MP, pt);
         if (wgrad_all_taps(g)) {
             dim3 grid1(p.nchunks);
             if (tm == 1 && tn == 1) hipLaunchKernelGGL((conv_bwd_weight_taps_kernel<1, 1>), grid1, dim3(256), 0, st, g, xa, xb, pt, MP, p.VC, part);
@@ -1275,13 +1296,27 @@ hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, c
     if (db) {
         const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
         float* pb = part + (size_t)p.nchunks * q;
-        hipLaunchKernelGGL(bias_grad_kernel, dim3(p.nchunks), dim3(256), 0, st, dy, y, slope, M, g.Cout, p.VC, pb);
+        hipLaunchKernelGGL(bias_grad_kernel, dim3(p.nchunks), dim3(256), 0, st, dy, y, slope, pbf, M, g.Cout, p.VC,
+                           pb);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(reduce_parts_kernel, dim3((unsigned)((g.Cout + 63) / 64)), dim3(256), 0, st, pb, p.nchunks,
                            (long long)g.Cout, db);
         e = hipGetLastError();
     }
     return e;
+}
+
+hipError_t conv_bwd_weight_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
+                                  const float* dy, const unsigned short* y, float slope, float* dw, float* db,
+                                  float* part, hipStream_t st)
+{
+    return bwd_weight_run(g, xa, xb, dy, y, slope, nullptr, dw, db, part, st);
+}
+
+hipError_t conv_bwd_weight_p_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
+                                    const unsigned short* p, float* dw, float* db, float* part, hipStream_t st)
+{
+    return bwd_weight_run(g, xa, xb, nullptr, nullptr, 0.0f, p, dw, db, part, st);
 }
 
 hipError_t cast_bf16_launch(const float* x, long long n, unsigned short* y, hipStream_t st)
@@ -1307,11 +1342,8 @@ hipError_t pack_pair_launch(const float* F, const float* M, long long nvox, unsi
 hipError_t split_grad_launch(const ConvGeom& g, const float* dxc, float* dxa, float* dxb, int acc_a, int acc_b,
                              hipStream_t st)
 {
-    // rows: below 2^31 / Wi each, as the voxel count is below 2^31
-    const int Rf = g.Cb > 0 ? g.N * g.Di * g.Hi : 0;
-    const int Rc = g.N * (g.Di >> 1) * (g.Hi >> 1);
-    hipLaunchKernelGGL(split_grad_kernel, dim3((unsigned)(Rf + Rc)), dim3(256), 0, st, g, dxc, dxa, dxb, acc_a, acc_b,
-                       Rf);
+    const int Rc = g.N * (g.Di >> 1) * (g.Hi >> 1);  // coarse rows: the voxel count is below 2^31
+    hipLaunchKernelGGL(split_grad_kernel, dim3((unsigned)Rc), dim3(256), 0, st, g, dxc, dxa, dxb, acc_a, acc_b);
     return hipGetLastError();
 }
 

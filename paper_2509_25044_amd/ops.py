@@ -543,6 +543,28 @@ def conv3d_bwd_weight(xa, xb, dy, y, g: ConvGeom, slope=0.2, dw=None, db=None, w
     return dw, db
 
 
+def conv3d_bwd_weight_bf16(xa, xb, p, g: ConvGeom, dw=None, db=None, ws=None):
+    """ffdp_conv3d_bwd_weight from P (bf16 [N][Do][Ho][Wo][Cout], ffdp_conv3d_bwd_weight_bf16)."""
+    L = _lib.lib()
+    dev = _conv_inputs(xa, xb, g)
+    _out(p, "p", (g.N,) + conv_out_shape(g) + (g.Cout,), dev, torch.bfloat16)
+    nb = int(L.ffdp_conv3d_bwd_weight_workspace_bytes(C.byref(g)))
+    if ws is None or _ws_bytes(ws, dev) < nb:
+        ws = torch.empty(max(nb, 16), dtype=torch.uint8, device=dev)
+    if dw is None:
+        dw = torch.empty((g.Cout, 27, g.Ca + g.Cb), dtype=torch.float32, device=dev)
+    else:
+        _out(dw, "dw", (g.Cout, 27, g.Ca + g.Cb), dev)
+    if db is None:
+        db = torch.empty(g.Cout, dtype=torch.float32, device=dev)
+    else:
+        _out(db, "db", (g.Cout,), dev)
+    check("ffdp_conv3d_bwd_weight_bf16", L.ffdp_conv3d_bwd_weight_bf16(_ptr(xa), _ptr(xb), _ptr(p), C.byref(g), _ptr(dw),
+                                                                       _ptr(db), _ptr(ws), _ws_bytes(ws, dev),
+                                                                       _stream(p)))
+    return dw, db
+
+
 def conv3d_bwd_weight_workspace_bytes(g: ConvGeom) -> int:
     return int(_lib.lib().ffdp_conv3d_bwd_weight_workspace_bytes(C.byref(g)))
 

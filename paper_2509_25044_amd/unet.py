@@ -181,11 +181,11 @@ class UNet3D:
             nb = ops.conv3d_bwd_weight_workspace_bytes(g)
             if self._ws is None or self._ws.numel() < nb:
                 self._ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
-            ops.conv3d_bwd_weight(xa, xb, dy, y, g, slope=SLOPE, dw=self.w(L.name, self.grad),
-                                  db=self.b(L.name, self.grad), ws=self._ws)
+            p = ops.conv3d_act_grad(dy, y, slope=SLOPE)  # bf16 dL/dy act'(y), the operand of both products
+            ops.conv3d_bwd_weight_bf16(xa, xb, p, g, dw=self.w(L.name, self.grad), db=self.b(L.name, self.grad),
+                                       ws=self._ws)
             if L.a == "x":
                 continue
-            p = ops.conv3d_act_grad(dy, y, slope=SLOPE)  # bf16 dL/dy act'(y), read 27 times below
             if L.ups:
                 dxc = ops.conv3d_bwd_data_bf16(p, self.wt[L.name], g)
                 dxa, dxb = ops.concat_grad_split(dxc, g)

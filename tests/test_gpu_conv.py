@@ -93,6 +93,8 @@ def test_conv_backward(case):
                                               Cb, Cout, stride=s, ups=ups)
     assert_grad(dw.cpu().numpy(), ref_dw, "bwd weight")
     assert_grad(db.cpu().numpy(), ref_db, "bwd bias")
+    dwp, dbp = ops.conv3d_bwd_weight_bf16(xad, xbd, pb, geom)
+    assert torch.equal(dwp, dw) and torch.equal(dbp, db)
 
 
 def test_no_activation_backward():
@@ -111,6 +113,8 @@ def test_no_activation_backward():
     rdw, rdb = oracle.conv3d_bwd_weight(xa.double(), None, P, N, Di, Hi, Wi, Ca, Cb, Cout)
     assert_grad(dw.cpu().numpy(), rdw, "dw")
     assert_grad(db.cpu().numpy(), rdb, "db")
+    dwp, dbp = ops.conv3d_bwd_weight_bf16(xa.to(DEV), None, pb, geom)
+    assert torch.equal(dwp, dw) and torch.equal(dbp, db)
 
 
 def test_helper_kernels():
