@@ -1164,13 +1164,52 @@ __global__ void __launch_bounds__(256) act_grad_kernel(const float* __restrict__
     }
 }
 
+// The same, 8 elements per thread and step (n8 groups of 8; 16-byte aligned
+// operands): two 16-byte loads of dy, one of y, one 16-byte store.
+__global__ void __launch_bounds__(256) act_grad8_kernel(const float* __restrict__ dy,
+                                                        const unsigned short* __restrict__ y, float slope, long long n8,
+                                                        unsigned short* __restrict__ p)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n8; i += (long long)gridDim.x * 256) {
+        const float4 d0 = reinterpret_cast<const float4*>(dy)[2 * i];
+        const float4 d1 = reinterpret_cast<const float4*>(dy)[2 * i + 1];
+        float v[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+        if (y) {
+            const uint4 yv = reinterpret_cast<const uint4*>(y)[i];
+            const unsigned yw[4] = {yv.x, yv.y, yv.z, yv.w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] *= lrelu_d((unsigned short)(yw[q >> 1] >> (16 * (q & 1))), slope);
+        }
+        uint4 o;
+        o.x = (unsigned)f2bf(v[0]) | ((unsigned)f2bf(v[1]) << 16);
+        o.y = (unsigned)f2bf(v[2]) | ((unsigned)f2bf(v[3]) << 16);
+        o.z = (unsigned)f2bf(v[4]) | ((unsigned)f2bf(v[5]) << 16);
+        o.w = (unsigned)f2bf(v[6]) | ((unsigned)f2bf(v[7]) << 16);
+        reinterpret_cast<uint4*>(p)[i] = o;
+    }
+}
+
 hipError_t act_grad_launch(const float* dy, const unsigned short* y, float slope, long long n, unsigned short* p,
                            hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    long long blocks = (n + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(act_grad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dy, y, slope, n, p);
+    const bool a16 = ((reinterpret_cast<uintptr_t>(dy) | reinterpret_cast<uintptr_t>(y) |
+                       reinterpret_cast<uintptr_t>(p)) & 15u) == 0;
+    long long head = 0;  // elements done by the vector kernel
+    if (a16 && n >= 8) {
+        const long long n8 = n / 8;
+        long long blocks = (n8 + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(act_grad8_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dy, y, slope, n8, p);
+        head = n8 * 8;
+    }
+    if (head < n) {
+        const long long rest = n - head;
+        long long blocks = (rest + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(act_grad_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dy + head, y ? y + head : nullptr,
+                           slope, rest, p + head);
+    }
     return hipGetLastError();
 }
 

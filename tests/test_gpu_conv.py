@@ -117,6 +117,21 @@ def test_no_activation_backward():
     assert torch.equal(dwp, dw) and torch.equal(dbp, db)
 
 
+def test_act_grad_lengths_and_offsets():
+    # the 8-wide kernel with a scalar tail, and the scalar kernel alone for
+    # operands that are not 16-byte aligned
+    g = torch.Generator().manual_seed(11)
+    for n in (1, 7, 8, 1003, 4096 + 5):
+        dy = torch.randn(n + 1, generator=g)
+        y = _bf(torch.randn(n + 1, generator=g))
+        dyd, yd = dy.to(DEV), y.to(DEV)
+        for off in (0, 1):  # offset 1: views 4 and 2 bytes past a 16-byte boundary
+            d, yy = dy[off:off + n], y[off:off + n]
+            ref = _bf(d * torch.where(yy.float() > 0, 1.0, SLOPE))
+            assert torch.equal(ops.conv3d_act_grad(dyd[off:off + n], yd[off:off + n], slope=SLOPE).cpu(), ref)
+            assert torch.equal(ops.conv3d_act_grad(dyd[off:off + n], None).cpu(), _bf(d))
+
+
 def test_helper_kernels():
     g = torch.Generator().manual_seed(9)
     F = torch.rand((2, 6, 5, 4), generator=g)
