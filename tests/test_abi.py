@@ -223,3 +223,33 @@ def test_smooth_adam_validation(L):
     assert L.ffdp_smooth_adam_step(x, g, m, v, 8, 8, 8, 3, 3.0, 0.1, 0.9, 0.999, 1e-8, 1, None) == 3  # sigma
     assert L.ffdp_smooth_adam_step(x, g, m, v, 8, 8, 8, 3, 1.0, 0.1, 1.0, 0.999, 1e-8, 1, None) == 3  # beta1
     assert L.ffdp_smooth_adam_step(x, g, m, v, 8, 0, 8, 3, 1.0, 0.1, 0.9, 0.999, 1e-8, 1, None) == 2  # shape
+
+
+def _cg(N=1, Di=4, Hi=4, Wi=4, Ca=16, Cb=0, Cout=16, stride=1, ups=0):
+    g = _lib.ConvGeom()
+    g.N, g.Di, g.Hi, g.Wi, g.Ca, g.Cb, g.Cout, g.stride, g.ups = N, Di, Hi, Wi, Ca, Cb, Cout, stride, ups
+    return g
+
+
+def test_conv_backward_from_p_validation(L):
+    a16, b16 = C.c_void_p(0x100000), C.c_void_p(0x900000)
+    # the P pass: n < 0, NULL operands with n > 0, n = 0 a no-op
+    assert L.ffdp_conv3d_act_grad(a16, None, 0.2, -1, b16, None) == 2
+    assert L.ffdp_conv3d_act_grad(None, None, 0.2, 8, b16, None) == 1
+    assert L.ffdp_conv3d_act_grad(a16, None, 0.2, 8, None, None) == 1
+    assert L.ffdp_conv3d_act_grad(FAKE_MIS, None, 0.2, 8, b16, None) == 4
+    assert L.ffdp_conv3d_act_grad(None, None, 0.2, 0, None, None) == 0
+    g = _cg()
+    # backward-data from P: geometry, P alignment (16 bytes), accumulate flag
+    assert L.ffdp_conv3d_bwd_data_bf16(a16, b16, C.byref(_cg(Ca=3)), a16, 0, None) == 3
+    assert L.ffdp_conv3d_bwd_data_bf16(C.c_void_p(0x100008), b16, C.byref(g), a16, 0, None) == 4
+    assert L.ffdp_conv3d_bwd_data_bf16(None, b16, C.byref(g), a16, 0, None) == 1
+    assert L.ffdp_conv3d_bwd_data_bf16(a16, b16, C.byref(g), a16, 2, None) == 3
+    # backward-weight from P: NULL P, missing skip input, workspace size
+    assert L.ffdp_conv3d_bwd_weight_bf16(a16, None, None, C.byref(g), b16, None, a16, 1 << 30, None) == 1
+    assert L.ffdp_conv3d_bwd_weight_bf16(a16, None, b16, C.byref(_cg(Cb=8)), b16, None, a16, 1 << 30, None) == 1
+    assert L.ffdp_conv3d_bwd_weight_bf16(a16, None, b16, C.byref(g), b16, None, a16, 8, None) == 5
+    # the concatenated-gradient split needs ups = 1 and 16-byte aligned buffers
+    assert L.ffdp_concat_grad_split(a16, C.byref(g), b16, None, 0, 0, None) == 3
+    gu = _cg(Cb=8, ups=1)
+    assert L.ffdp_concat_grad_split(C.c_void_p(0x100004), C.byref(gu), b16, C.c_void_p(0x500000), 0, 0, None) == 4
