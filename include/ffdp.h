@@ -283,7 +283,12 @@ int ffdp_smooth_adam_step(float* x, const float* g, float* m, float* v, int64_t 
                           void* stream);
 
 /* ------------------------------------------------------------------------
- * Warm-start network (3D U-Net) kernels.  BF16 operands on MFMA with FP32
+ * Warm-start network (3D U-Net) kernels.  The paper trains a learned
+ * registration network with its fused losses (App. "Accelerating TransMorph
+ * training") but specifies no architecture; this network, which predicts an
+ * initial displacement for the optimisation, is this library's own.  The
+ * operations are the textbook 3x3x3 convolution, its two adjoints (to the
+ * input and to the weights) and LeakyReLU.  BF16 operands on MFMA with FP32
  * accumulation.  Activations are channels-last bf16 [N][D][H][W][C]
  * (uint16_t holding bfloat16 bits).  All convolutions are 3x3x3 with zero
  * padding 1 and stride 1 or 2; output size Do = (Di - 1)/stride + 1 per axis.
