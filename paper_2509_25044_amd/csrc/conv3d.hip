@@ -897,15 +897,25 @@ __global__ void __launch_bounds__(256) bias_grad_kernel(const float* __restrict_
     const int cg = (int)threadIdx.x % G, vs = (int)threadIdx.x / G, nv = 256 / G;
     const long long ob = (long long)blockIdx.x * VC, oe = min(M, ob + VC);
     float s[4] = {0.f, 0.f, 0.f, 0.f};
-    if ((int)threadIdx.x < T) {
+    if ((int)threadIdx.x < T && pbf) {  // P given in bf16: 4 voxels' loads in flight, added in voxel order
+        long long o = ob + vs;
+        for (; o + 3 * nv < oe; o += 4 * nv) {
+            s4v pv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pv[k] = ld4bf(pbf + (size_t)(o + k * nv) * Cout + 4 * cg);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) s[c] += bf2f((unsigned short)pv[k][c]);
+        }
+        for (; o < oe; o += nv) {
+            const s4v pv = ld4bf(pbf + (size_t)o * Cout + 4 * cg);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s[c] += bf2f((unsigned short)pv[c]);
+        }
+    } else if ((int)threadIdx.x < T) {
         for (long long o = ob + vs; o < oe; o += nv) {
             const size_t i = (size_t)o * Cout + 4 * cg;
-            if (pbf) {  // P given in bf16
-                const s4v pv = ld4bf(pbf + i);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) s[c] += bf2f((unsigned short)pv[c]);
-                continue;
-            }
             const float4 d = *reinterpret_cast<const float4*>(dy + i);
             const float pv[4] = {d.x, d.y, d.z, d.w};
             float f[4] = {1.f, 1.f, 1.f, 1.f};
