@@ -197,6 +197,7 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < CONV_KC; kk += 32) {
+            if (k0 + kk >= K) break;  // uniform: no all-zero K steps in the last round
             bf8v a;
             if (C8) {
                 a = load_a8(t, c);
