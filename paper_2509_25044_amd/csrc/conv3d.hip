@@ -1124,7 +1124,9 @@ static void launch_bwd_data(int nt, unsigned blocks, hipStream_t st, const ConvG
     hipLaunchKernelGGL((conv_bwd_data_kernel<T, C8, PAR, PB>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, pb, wt, dx, accumulate)
     if (nt <= 1) BWD_DATA(1);
     else if (nt <= 2) BWD_DATA(2);
+    else if (nt <= 3) BWD_DATA(3);
     else if (nt <= 4) BWD_DATA(4);
+    else if (nt <= 6) BWD_DATA(6);
     else if (nt <= 8) BWD_DATA(8);
     else BWD_DATA(12);
 #undef BWD_DATA
