@@ -128,8 +128,11 @@ __device__ __forceinline__ bf8v b_from_lds(const unsigned short* __restrict__ ws
 
 // ---------------------------------------------------------------- forward --
 // C8: Ca and Cb are multiples of 8, so a lane's 8 K elements are 8
-// contiguous channels of one tap and one 16-byte load.
-template <int NT, bool C8>
+// contiguous channels of one tap and one 16-byte load.  MT: output tiles of
+// 16 voxels per wave; each B operand read from LDS feeds MT MFMAs (with one
+// voxel tile per wave the LDS reads of the weights, one per MFMA, bound the
+// kernel).
+template <int NT, bool C8, int MT>
 __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigned short* __restrict__ xa,
                                                        const unsigned short* __restrict__ xb,
                                                        const unsigned short* __restrict__ w,
@@ -141,45 +144,50 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
     const int Cin = g.Ca + g.Cb;
     const int K = 27 * Cin;
     const long long M = (long long)g.N * g.Do * g.Ho * g.Wo;
-    const long long m0 = ((long long)blockIdx.x * 4 + wave) * 16;
-    const long long m = m0 + (lane & 15);
-    const bool mvalid = m < M;
-    int n = 0, zs = 0, ys = 0, xs = 0;  // the row's input corner (tap 0, 0, 0)
-    if (mvalid) {
-        const Vox v = vox_of(m, g.Do, g.Ho, g.Wo);
-        n = v.n;
-        zs = v.z * g.stride - 1; ys = v.y * g.stride - 1; xs = v.x * g.stride - 1;
+    const long long mb = ((long long)blockIdx.x * 4 + wave) * 16 * MT;  // the wave's first output voxel
+    int n[MT], zs[MT], ys[MT], xs[MT];  // each row's input corner (tap 0, 0, 0)
+    bool mvalid[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const long long m = mb + 16 * mt + (lane & 15);
+        mvalid[mt] = m < M;
+        n[mt] = 0; zs[mt] = 0; ys[mt] = 0; xs[mt] = 0;
+        if (mvalid[mt]) {
+            const Vox v = vox_of(m, g.Do, g.Ho, g.Wo);
+            n[mt] = v.n;
+            zs[mt] = v.z * g.stride - 1; ys[mt] = v.y * g.stride - 1; xs[mt] = v.x * g.stride - 1;
+        }
     }
     const int Da = g.Di >> 1, Ha = g.Hi >> 1, Wa = g.Wi >> 1;
-    auto load_a4 = [&](int t, int c) {  // channels c..c+3 of tap t (32-bit voxel indices)
+    auto load_a4 = [&](int mt, int t, int c) {  // channels c..c+3 of tap t (32-bit voxel indices)
         s4v a = s4v{0, 0, 0, 0};
         const int dz = t / 9, dy = (t - 9 * dz) / 3, dx = t - 9 * dz - 3 * dy;
-        const int zi = zs + dz, yi = ys + dy, xi = xs + dx;
-        if (mvalid && t < 27 && (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi &&
+        const int zi = zs[mt] + dz, yi = ys[mt] + dy, xi = xs[mt] + dx;
+        if (mvalid[mt] && t < 27 && (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi &&
             (unsigned)xi < (unsigned)g.Wi) {
             if (c < g.Ca) {
-                const unsigned v = g.ups ? ((unsigned)(n * Da + (zi >> 1)) * Ha + (yi >> 1)) * Wa + (xi >> 1)
-                                         : ((unsigned)(n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                const unsigned v = g.ups ? ((unsigned)(n[mt] * Da + (zi >> 1)) * Ha + (yi >> 1)) * Wa + (xi >> 1)
+                                         : ((unsigned)(n[mt] * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
                 a = ld4bf(xa + (size_t)v * g.Ca + c);
             } else {
-                const unsigned v = ((unsigned)(n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                const unsigned v = ((unsigned)(n[mt] * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
                 a = ld4bf(xb + (size_t)v * g.Cb + (c - g.Ca));
             }
         }
         return a;
     };
-    auto load_a8 = [&](int t, int c) {  // channels c..c+7 of tap t (C8)
+    auto load_a8 = [&](int mt, int t, int c) {  // channels c..c+7 of tap t (C8)
         uint4 a = make_uint4(0u, 0u, 0u, 0u);
         const int dz = t / 9, dy = (t - 9 * dz) / 3, dx = t - 9 * dz - 3 * dy;
-        const int zi = zs + dz, yi = ys + dy, xi = xs + dx;
-        if (mvalid && t < 27 && (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi &&
+        const int zi = zs[mt] + dz, yi = ys[mt] + dy, xi = xs[mt] + dx;
+        if (mvalid[mt] && t < 27 && (unsigned)zi < (unsigned)g.Di && (unsigned)yi < (unsigned)g.Hi &&
             (unsigned)xi < (unsigned)g.Wi) {
             if (c < g.Ca) {
-                const unsigned v = g.ups ? ((unsigned)(n * Da + (zi >> 1)) * Ha + (yi >> 1)) * Wa + (xi >> 1)
-                                         : ((unsigned)(n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                const unsigned v = g.ups ? ((unsigned)(n[mt] * Da + (zi >> 1)) * Ha + (yi >> 1)) * Wa + (xi >> 1)
+                                         : ((unsigned)(n[mt] * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
                 a = *reinterpret_cast<const uint4*>(xa + (size_t)v * g.Ca + c);
             } else {
-                const unsigned v = ((unsigned)(n * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
+                const unsigned v = ((unsigned)(n[mt] * g.Di + zi) * g.Hi + yi) * g.Wi + xi;
                 a = *reinterpret_cast<const uint4*>(xb + (size_t)v * g.Cb + (c - g.Ca));
             }
         }
@@ -188,9 +196,11 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
     const int kg = (lane >> 4) * 8;
     // the lane's K index k = (tap t, channel c), advanced by 32 per step
     int t = kg / Cin, c = kg - t * Cin;
-    f4v acc[NT];
+    f4v acc[MT][NT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[mt][j] = f4v{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += CONV_KC) {
         __syncthreads();
         stage_weights<NT>(ws, w, g.Cout, K, k0);
@@ -198,34 +208,43 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
 #pragma unroll
         for (int kk = 0; kk < CONV_KC; kk += 32) {
             if (k0 + kk >= K) break;  // uniform: no all-zero K steps in the last round
-            bf8v a;
-            if (C8) {
-                a = load_a8(t, c);
-            } else {
-                const bool wrap = c + 4 >= Cin;  // channels c + 4 .. c + 7 start the next tap (Cin % 4 == 0)
-                a = cat8(load_a4(t, c), load_a4(wrap ? t + 1 : t, wrap ? c + 4 - Cin : c + 4));
+            bf8v a[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                if (C8) {
+                    a[mt] = load_a8(mt, t, c);
+                } else {
+                    const bool wrap = c + 4 >= Cin;  // channels c + 4 .. c + 7 start the next tap (Cin % 4 == 0)
+                    a[mt] = cat8(load_a4(mt, t, c), load_a4(mt, wrap ? t + 1 : t, wrap ? c + 4 - Cin : c + 4));
+                }
             }
 #pragma unroll
-            for (int j = 0; j < NT; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b_from_lds(ws, j, lane, kk), acc[j], 0, 0, 0);
+            for (int j = 0; j < NT; ++j) {
+                const bf8v b = b_from_lds(ws, j, lane, kk);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[mt][j], 0, 0, 0);
+            }
             c += 32;
             while (c >= Cin) { c -= Cin; ++t; }
         }
     }
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int co = j * 16 + (lane & 15);
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const long long mo = m0 + (lane >> 4) * 4 + e;
-            if (mo < M && co < g.Cout) {
-                float v = acc[j][e] + (bias ? bias[co] : 0.0f);
-                if (act) v = v > 0.0f ? v : v * slope;
-                if (ybf) ybf[mo * g.Cout + co] = f2bf(v);
-                if (yf) yf[mo * g.Cout + co] = v;
+        for (int j = 0; j < NT; ++j) {
+            const int co = j * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const long long mo = mb + 16 * mt + (lane >> 4) * 4 + e;
+                if (mo < M && co < g.Cout) {
+                    float v = acc[mt][j][e] + (bias ? bias[co] : 0.0f);
+                    if (act) v = v > 0.0f ? v : v * slope;
+                    if (ybf) ybf[mo * g.Cout + co] = f2bf(v);
+                    if (yf) yf[mo * g.Cout + co] = v;
+                }
             }
         }
-    }
 }
 
 // ----------------------------------------------------------- backward data --
@@ -1096,10 +1115,13 @@ static void launch_fwd(int nt, unsigned blocks, hipStream_t st, const ConvGeom& 
                        const unsigned short* xb, const unsigned short* w, const float* bias, int act, float slope,
                        unsigned short* ybf, float* yf)
 {
-    if (nt <= 1) hipLaunchKernelGGL((conv_fwd_kernel<1, C8>), dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
-    else if (nt <= 2) hipLaunchKernelGGL((conv_fwd_kernel<2, C8>), dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
-    else if (nt <= 4) hipLaunchKernelGGL((conv_fwd_kernel<4, C8>), dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
-    else hipLaunchKernelGGL((conv_fwd_kernel<8, C8>), dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    // up to 2 output-channel tiles: 2 voxel tiles per wave (a block covers 128
+    // voxels); with 4 or 8 the kernel is faster with one (fewer registers)
+    const unsigned b2 = (blocks + 1) / 2;
+    if (nt <= 1) hipLaunchKernelGGL((conv_fwd_kernel<1, C8, 2>), dim3(b2), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else if (nt <= 2) hipLaunchKernelGGL((conv_fwd_kernel<2, C8, 2>), dim3(b2), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else if (nt <= 4) hipLaunchKernelGGL((conv_fwd_kernel<4, C8, 1>), dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
+    else hipLaunchKernelGGL((conv_fwd_kernel<8, C8, 1>), dim3(blocks), dim3(256), 0, st, g, xa, xb, w, bias, act, slope, ybf, yf);
 }
 
 hipError_t conv_fwd_launch(const ConvGeom& g, const unsigned short* xa, const unsigned short* xb,
