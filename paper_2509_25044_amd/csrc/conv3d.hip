@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(ConvGeom g, const unsigne
 // PB: P = dL/dy act'(y) arrives precomputed as bf16 in dL/dy's layout (pb),
 // so a lane's 8 K elements are one 16-byte load (4 channels: 8 bytes) and no
 // conversion; dy and y are not read.
-template <int NT, bool C8, bool PAR, bool PB>
+template <int NT, bool C8, bool PAR, bool PB, int MT>
 __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const float* __restrict__ dy,
                                                             const unsigned short* __restrict__ y, float slope,
                                                             const unsigned short* __restrict__ pb,
@@ -275,14 +275,14 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
     // voxels over the half-resolution grid Dc x Hc x Wc (rounded up)
     const int Dc = (g.Di + 1) >> 1, Hc = (g.Hi + 1) >> 1, Wc = (g.Wi + 1) >> 1;
     const long long Mc = (long long)g.N * Dc * Hc * Wc;
-    const int bpc = PAR ? (int)((Mc + 63) / 64) : 0;  // blocks per class
+    const int bpc = PAR ? (int)((Mc + 64 * MT - 1) / (64 * MT)) : 0;  // blocks per class
     const int cls = PAR ? (int)blockIdx.x / bpc : 0;
     const int pz = (cls >> 2) & 1, py = (cls >> 1) & 1, px = cls & 1;
     const int ny = PAR ? 1 + py : 3, nx = PAR ? 1 + px : 3;  // taps per axis
     const int ntap = PAR ? (1 + pz) * ny * nx : 27;
     const int K = ntap * g.Cout;
-    const long long m0 = ((long long)(PAR ? (int)blockIdx.x - cls * bpc : (int)blockIdx.x) * 4 + wave) * 16;
-    const long long m = m0 + (lane & 15);
+    // the wave's MT tiles of 16 rows
+    const long long m0 = ((long long)(PAR ? (int)blockIdx.x - cls * bpc : (int)blockIdx.x) * 4 + wave) * 16 * MT;
     auto voxel = [&](long long r, int& n_, int& z_, int& y_, int& x_) -> bool {  // row -> voxel
         if (!PAR) {
             if (r >= M) return false;
@@ -295,8 +295,13 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
         n_ = v.n; z_ = 2 * v.z + pz; y_ = 2 * v.y + py; x_ = 2 * v.x + px;
         return z_ < g.Di && y_ < g.Hi && x_ < g.Wi;
     };
-    int n = 0, zi = 0, yi = 0, xi = 0;
-    const bool mvalid = voxel(m, n, zi, yi, xi);
+    int n[MT], zi[MT], yi[MT], xi[MT];
+    bool mvalid[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        n[mt] = 0; zi[mt] = 0; yi[mt] = 0; xi[mt] = 0;
+        mvalid[mt] = voxel(m0 + 16 * mt + (lane & 15), n[mt], zi[mt], yi[mt], xi[mt]);
+    }
     // tap number of the class's j-th tap (PAR), else j itself
     auto tap_of = [&](int j) -> int {
         if (!PAR) return j;
@@ -306,22 +311,22 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
     };
     // element offset of P at output channel co of tap t, or -1 where the tap
     // reaches no output voxel (a non-integer or out-of-range output index)
-    auto p_offset = [&](int j, int co) -> long long {  // j: tap index within the class (PAR) or tap
-        if (!mvalid || j >= ntap) return -1;
+    auto p_offset = [&](int mt, int j, int co) -> long long {  // j: tap index within the class (PAR) or tap
+        if (!mvalid[mt] || j >= ntap) return -1;
         const int t = tap_of(j);
         const int dz = t / 9, dyy = (t - 9 * dz) / 3, dx_ = t - 9 * dz - 3 * dyy;
-        int oz = zi + 1 - dz, oy = yi + 1 - dyy, ox = xi + 1 - dx_;
+        int oz = zi[mt] + 1 - dz, oy = yi[mt] + 1 - dyy, ox = xi[mt] + 1 - dx_;
         bool ok = oz >= 0 && oy >= 0 && ox >= 0;
         if (g.stride == 2) {
             ok = ok && !(oz & 1) && !(oy & 1) && !(ox & 1);
             oz >>= 1; oy >>= 1; ox >>= 1;
         }
         ok = ok && oz < g.Do && oy < g.Ho && ox < g.Wo;
-        return ok ? (long long)(((unsigned)(n * g.Do + oz) * g.Ho + oy) * g.Wo + ox) * g.Cout + co : -1;
+        return ok ? (long long)(((unsigned)(n[mt] * g.Do + oz) * g.Ho + oy) * g.Wo + ox) * g.Cout + co : -1;
     };
-    auto load_p4 = [&](int t, int co) {  // P = dL/dy * act'(y) at output channels co..co+3 of tap t
+    auto load_p4 = [&](int mt, int t, int co) {  // P = dL/dy * act'(y) at output channels co..co+3 of tap t
         s4v a = s4v{0, 0, 0, 0};
-        const long long o = p_offset(t, co);
+        const long long o = p_offset(mt, t, co);
         if (PB) {
             if (o >= 0) a = ld4bf(pb + o);
         } else if (o >= 0) {
@@ -336,9 +341,9 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
         }
         return a;
     };
-    auto load_p8 = [&](int t, int co) {  // channels co..co+7 of tap t (C8)
+    auto load_p8 = [&](int mt, int t, int co) {  // channels co..co+7 of tap t (C8)
         s4v lo = s4v{0, 0, 0, 0}, hi = s4v{0, 0, 0, 0};
-        const long long o = p_offset(t, co);
+        const long long o = p_offset(mt, t, co);
         if (PB) {
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (o >= 0) v = *reinterpret_cast<const uint4*>(pb + o);
@@ -362,9 +367,11 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
     const int kg = (lane >> 4) * 8;
     // the lane's K index k = (tap t, output channel c), advanced by 32 per step
     int t = kg / g.Cout, c = kg - t * g.Cout;
-    f4v acc[NT];
+    f4v acc[MT][NT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[mt][j] = f4v{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += CONV_KC) {
         __syncthreads();
         if (PAR) {
@@ -389,36 +396,46 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(ConvGeom g, const fl
 #pragma unroll
         for (int kk = 0; kk < CONV_KC; kk += 32) {
             if (k0 + kk >= K) break;  // uniform: past the last K column
-            bf8v a;
-            if (C8) {
-                a = load_p8(t, c);
-            } else {
-                const bool wrap = c + 4 >= g.Cout;  // Cout % 4 == 0
-                a = cat8(load_p4(t, c), load_p4(wrap ? t + 1 : t, wrap ? c + 4 - g.Cout : c + 4));
+            bf8v a[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                if (C8) {
+                    a[mt] = load_p8(mt, t, c);
+                } else {
+                    const bool wrap = c + 4 >= g.Cout;  // Cout % 4 == 0
+                    a[mt] = cat8(load_p4(mt, t, c), load_p4(mt, wrap ? t + 1 : t, wrap ? c + 4 - g.Cout : c + 4));
+                }
             }
 #pragma unroll
-            for (int j = 0; j < NT; ++j)
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b_from_lds(ws, j, lane, kk), acc[j], 0, 0, 0);
+            for (int j = 0; j < NT; ++j) {
+                const bf8v b = b_from_lds(ws, j, lane, kk);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[mt][j], 0, 0, 0);
+            }
             c += 32;
             while (c >= g.Cout) { c -= g.Cout; ++t; }
         }
     }
-    long long vo[4];  // voxels of the lane's 4 output rows (-1: none)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        int n_, z_, y_, x_;
-        const long long r = m0 + (lane >> 4) * 4 + e;
-        vo[e] = -1;
-        if (voxel(r, n_, z_, y_, x_)) vo[e] = PAR ? (((long long)n_ * g.Di + z_) * g.Hi + y_) * g.Wi + x_ : r;
-    }
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int ci = j * 16 + (lane & 15);
+    for (int mt = 0; mt < MT; ++mt) {
+        long long vo[4];  // voxels of the lane's 4 output rows of tile mt (-1: none)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            if (vo[e] >= 0 && ci < Cin) {
-                float* p = dx + vo[e] * Cin + ci;
-                *p = accumulate ? *p + acc[j][e] : acc[j][e];
+            int n_, z_, y_, x_;
+            const long long r = m0 + 16 * mt + (lane >> 4) * 4 + e;
+            vo[e] = -1;
+            if (voxel(r, n_, z_, y_, x_)) vo[e] = PAR ? (((long long)n_ * g.Di + z_) * g.Hi + y_) * g.Wi + x_ : r;
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const int ci = j * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (vo[e] >= 0 && ci < Cin) {
+                    float* p = dx + vo[e] * Cin + ci;
+                    *p = accumulate ? *p + acc[mt][j][e] : acc[mt][j][e];
+                }
             }
         }
     }
@@ -1137,20 +1154,23 @@ hipError_t conv_fwd_launch(const ConvGeom& g, const unsigned short* xa, const un
     return hipGetLastError();
 }
 
-template <bool C8, bool PAR, bool PB>
+template <bool C8, bool PAR, bool PB, int MT>
 static void launch_bwd_data(int nt, unsigned blocks, hipStream_t st, const ConvGeom& g, const float* dy,
                             const unsigned short* y, float slope, const unsigned short* pb, const unsigned short* wt,
                             float* dx, int accumulate)
 {
 #define BWD_DATA(T) \
-    hipLaunchKernelGGL((conv_bwd_data_kernel<T, C8, PAR, PB>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, pb, wt, dx, accumulate)
-    if (nt <= 1) BWD_DATA(1);
-    else if (nt <= 2) BWD_DATA(2);
-    else if (nt <= 3) BWD_DATA(3);
-    else if (nt <= 4) BWD_DATA(4);
-    else if (nt <= 6) BWD_DATA(6);
-    else if (nt <= 8) BWD_DATA(8);
-    else BWD_DATA(12);
+    hipLaunchKernelGGL((conv_bwd_data_kernel<T, C8, PAR, PB, MT>), dim3(blocks), dim3(256), 0, st, g, dy, y, slope, pb, wt, dx, accumulate)
+    if constexpr (MT == 2) {  // nt <= 3
+        if (nt <= 1) BWD_DATA(1);
+        else if (nt <= 2) BWD_DATA(2);
+        else BWD_DATA(3);
+    } else {  // nt >= 4
+        if (nt <= 4) BWD_DATA(4);
+        else if (nt <= 6) BWD_DATA(6);
+        else if (nt <= 8) BWD_DATA(8);
+        else BWD_DATA(12);
+    }
 #undef BWD_DATA
 }
 
@@ -1161,16 +1181,29 @@ static hipError_t bwd_data_dispatch(const ConvGeom& g, const float* dy, const un
 {
     const int nt = (g.Ca + g.Cb + 15) / 16;
     if (nt > 12) return hipErrorInvalidValue;
+    // up to 3 input-channel tiles: 2 voxel tiles per wave, so that each LDS
+    // read of the weights feeds two MFMAs (a block covers 128 voxels)
+    const int MTv = nt <= 3 ? 2 : 1;
     if (g.stride == 2) {  // 8 parity classes of the half-resolution grid (rounded up)
         const long long Mc = (long long)g.N * ((g.Di + 1) / 2) * ((g.Hi + 1) / 2) * ((g.Wi + 1) / 2);
-        const unsigned blocks = (unsigned)(8 * ((Mc + 63) / 64));
-        if (g.Cout % 8 == 0) launch_bwd_data<true, true, PB>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
-        else launch_bwd_data<false, true, PB>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+        const unsigned blocks = (unsigned)(8 * ((Mc + 64 * MTv - 1) / (64 * MTv)));
+        if (MTv == 2) {
+            if (g.Cout % 8 == 0) launch_bwd_data<true, true, PB, 2>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+            else launch_bwd_data<false, true, PB, 2>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+        } else {
+            if (g.Cout % 8 == 0) launch_bwd_data<true, true, PB, 1>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+            else launch_bwd_data<false, true, PB, 1>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+        }
     } else {
         const long long M = (long long)g.N * g.Di * g.Hi * g.Wi;
-        const unsigned blocks = (unsigned)((M + 63) / 64);
-        if (g.Cout % 8 == 0) launch_bwd_data<true, false, PB>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
-        else launch_bwd_data<false, false, PB>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+        const unsigned blocks = (unsigned)((M + 64 * MTv - 1) / (64 * MTv));
+        if (MTv == 2) {
+            if (g.Cout % 8 == 0) launch_bwd_data<true, false, PB, 2>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+            else launch_bwd_data<false, false, PB, 2>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+        } else {
+            if (g.Cout % 8 == 0) launch_bwd_data<true, false, PB, 1>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+            else launch_bwd_data<false, false, PB, 1>(nt, blocks, st, g, dy, y, slope, pb, wt, dx, accumulate);
+        }
     }
     return hipGetLastError();
 }
